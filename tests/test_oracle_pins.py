@@ -1,0 +1,404 @@
+"""Pins of the CPU oracle against closed forms, invariants, library routines
+and brute force (no GPU).  Each test names the passage it follows."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle
+from oracle import binning, composite, projection, selection
+from paper_2510_06644_amd import synth
+from tests.helpers import cam_tuple, one_gaussian_scene
+
+F64 = torch.float64
+CAM64 = synth.Camera(64, 64, 51.2, 51.2, 32.0, 32.0)
+
+
+def _eye_view():
+    return np.concatenate([np.eye(3), np.zeros((3, 1))], 1)
+
+
+# ---------------------------------------------------------------- Eq. (1)
+def test_identity_quaternion_gives_diagonal_covariance():
+    ls = torch.tensor([[-3.0, -2.5, -4.0], [0.1, 0.2, -0.3]], dtype=F64)
+    q = torch.tensor([[1.0, 0, 0, 0], [2.0, 0, 0, 0]], dtype=F64)  # unnormalised too
+    sig = oracle.covariance3d(ls, q)
+    want = torch.diag_embed(torch.exp(2 * ls))
+    assert torch.allclose(sig, want, rtol=0, atol=1e-15)
+
+
+def test_rotation_keeps_eigenvalues_and_matches_scipy():
+    rng = np.random.default_rng(0)
+    q = rng.normal(size=(50, 4))
+    ls = rng.normal(-3, 0.5, size=(50, 3))
+    sig = oracle.covariance3d(torch.tensor(ls), torch.tensor(q)).numpy()
+    ev = np.sort(np.linalg.eigvalsh(sig), 1)
+    assert np.allclose(ev, np.sort(np.exp(2 * ls), 1), rtol=1e-10)
+    # scipy's quaternion is scalar-last; same Hamilton convention
+    r_ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    r = oracle.quat_to_rotmat(torch.tensor(q)).numpy()
+    assert np.allclose(r, r_ref, atol=1e-12)
+
+
+def test_quarter_turn_about_z_maps_x_to_y():
+    h = math.sqrt(0.5)
+    r = oracle.quat_to_rotmat(torch.tensor([h, 0, 0, h], dtype=F64)).numpy()
+    assert np.allclose(r @ [1, 0, 0], [0, 1, 0], atol=1e-15)
+
+
+# ---------------------------------------------------------------- pose algebra
+def test_se3_exp_matches_rodrigues_and_inverts():
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        xi = rng.normal(size=6) * [0.3, 0.3, 0.3, 0.7, 0.7, 0.7]
+        t = oracle.se3_exp(torch.tensor(xi)).numpy()
+        assert np.allclose(t[:, :3], Rotation.from_rotvec(xi[3:]).as_matrix(), atol=1e-13)
+        ti = oracle.se3_exp(torch.tensor(-xi)).numpy()
+        comp = t[:, :3] @ ti[:, :3]
+        assert np.allclose(comp, np.eye(3), atol=1e-13)
+        assert np.allclose(t[:, :3] @ ti[:, 3] + t[:, 3], 0, atol=1e-13)
+    # pure translation; tiny angle takes the series branch and stays continuous
+    t = oracle.se3_exp(torch.tensor([0.1, -0.2, 0.3, 0, 0, 0], dtype=F64)).numpy()
+    assert np.allclose(t, np.concatenate([np.eye(3), [[0.1], [-0.2], [0.3]]], 1))
+    a = oracle.se3_exp(torch.tensor([0.1, 0, 0, 1e-5, 0, 0], dtype=F64)).numpy()
+    b = oracle.se3_exp(torch.tensor([0.1, 0, 0, 1.0001e-4, 0, 0], dtype=F64)).numpy()
+    assert np.allclose(a[:, :3], Rotation.from_rotvec([1e-5, 0, 0]).as_matrix(), atol=1e-15)
+    assert np.allclose(b[:, :3], Rotation.from_rotvec([1.0001e-4, 0, 0]).as_matrix(), atol=1e-15)
+
+
+# ---------------------------------------------------------------- Step 1-1
+def _proj(scene, cam, view=None):
+    t = lambda a: torch.tensor(np.asarray(a, np.float64))
+    sig, o = oracle.activate(t(scene.log_scales), t(scene.quats), t(scene.opacity_logits))
+    return oracle.project(t(scene.means), sig, o, t(_eye_view() if view is None else view),
+                          cam_tuple(cam))
+
+
+def test_projection_isotropic_on_axis_closed_form():
+    z, s = 2.0, 0.05
+    sc = one_gaussian_scene([0, 0, z], math.log(s), 0.7, [1, 1, 1])
+    p = _proj(sc, CAM64)
+    f = CAM64.fx
+    var = (f * s / z) ** 2 + 0.3
+    assert abs(p.u.item() - CAM64.cx) < 1e-12 and abs(p.v.item() - CAM64.cy) < 1e-12
+    assert np.allclose(p.cov2d[0].numpy(), var * np.eye(2), rtol=1e-6)
+    assert abs(p.a.item() - 1 / var) < 1e-6 / var and abs(p.b.item()) < 1e-12
+
+
+def test_projection_off_axis_closed_form_and_clamp():
+    f = CAM64.fx
+    z, s = 1.5, 0.03
+    sf = float(np.float32(s))
+    for x in (0.2, 3.0):            # the second lies beyond the 1.3x field of view
+        sc = one_gaussian_scene([x, 0, z], math.log(s), 0.7, [1, 1, 1])
+        p = _proj(sc, CAM64)
+        xt = np.clip(float(np.float32(x)) / z, -1.3 * 32 / f, 1.3 * 32 / f)
+        jac = np.array([[f / z, 0, -f * xt / z], [0, f / z, 0]])
+        s2 = np.exp(2 * float(np.float32(math.log(s))))
+        want = s2 * jac @ jac.T + 0.3 * np.eye(2)
+        assert np.allclose(p.cov2d[0].numpy(), want, rtol=1e-6)
+        assert abs(p.u.item() - (f * float(np.float32(x)) / z + CAM64.cx)) < 1e-9
+    del sf
+
+
+def test_projection_culls():
+    sc = one_gaussian_scene([[0, 0, 0.19], [0, 0, 0.21], [0, 0, 1.0], [0, 0, 1.0]],
+                            -3.0, [0.5, 0.5, 0.003, 0.005], [1, 1, 1])
+    p = _proj(sc, CAM64)
+    assert p.valid.tolist() == [False, True, False, True]   # near plane; 255 o < 1
+
+
+# ---------------------------------------------------------------- Eqs. (2)-(3)
+def _closed_alpha(cam, z, s, o, u0=None, v0=None, x=0.0, y=0.0):
+    """alpha of an isotropic Gaussian of scale s at camera point (x, y, z):
+    Sigma' = s^2 J J^T + 0.3 I with the EWA Jacobian J (no clamp inside the view)."""
+    u0 = cam.fx * x / z + cam.cx if u0 is None else u0
+    v0 = cam.fy * y / z + cam.cy if v0 is None else v0
+    jac = np.array([[cam.fx / z, 0, -cam.fx * x / z / z], [0, cam.fy / z, -cam.fy * y / z / z]])
+    cov = s * s * jac @ jac.T + 0.3 * np.eye(2)
+    m = np.linalg.inv(cov)
+    i = np.arange(cam.width) + 0.5
+    j = np.arange(cam.height) + 0.5
+    dx = i[None, :] - u0
+    dy = j[:, None] - v0
+    q = m[0, 0] * dx * dx + 2 * m[0, 1] * dx * dy + m[1, 1] * dy * dy
+    a = o * np.exp(-0.5 * q)
+    return np.where(a >= 1 / 255, np.minimum(a, 0.99), 0.0)
+
+
+@pytest.mark.parametrize("opacity", [0.9, 0.999])
+def test_single_gaussian_image_closed_form(opacity):
+    z, s = 2.0, 0.08
+    col = np.array([0.2, 0.5, 0.9])
+    # centred on the sample point of pixel (32, 32)
+    sc = one_gaussian_scene([0.5 * z / CAM64.fx, 0.5 * z / CAM64.fy, z], math.log(s), opacity, col)
+    o32 = 1 / (1 + np.exp(-float(sc.opacity_logits[0])))
+    s32 = math.exp(float(sc.log_scales[0, 0]))
+    out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(CAM64))
+    al = _closed_alpha(CAM64, z, s32, o32, x=float(sc.means[0, 0]), y=float(sc.means[0, 1]))
+    assert np.allclose(out.alpha.numpy(), al, atol=1e-12)
+    assert np.allclose(out.color.numpy(), al[None] * sc.colors[0].astype(np.float64)[:, None, None],
+                       atol=1e-12)
+    assert np.allclose(out.depth.numpy(), al * z, atol=1e-12)
+    assert np.array_equal(out.last_id.numpy(), np.where(al > 0, 0, -1))
+    if opacity > 0.99:
+        assert out.alpha.max().item() == pytest.approx(0.99, abs=1e-15)
+
+
+def test_two_gaussians_front_to_back_and_swap():
+    s = 0.1
+    c1, c2 = np.array([1.0, 0, 0]), np.array([0, 0, 1.0])
+    for z1, z2 in ((1.5, 2.5), (2.5, 1.5)):
+        sc = one_gaussian_scene([[0, 0, z1], [0.05 * z2, 0, z2]], math.log(s), [0.6, 0.8],
+                                [c1, c2])
+        x2 = float(sc.means[1, 0])
+        o = 1 / (1 + np.exp(-sc.opacity_logits.astype(np.float64)))
+        s32 = math.exp(float(sc.log_scales[0, 0]))
+        a1 = _closed_alpha(CAM64, z1, s32, o[0])
+        a2 = _closed_alpha(CAM64, z2, s32, o[1], x=x2)
+        front, back = (a1, a2) if z1 < z2 else (a2, a1)
+        cf, cb = (c1, c2) if z1 < z2 else (c2, c1)
+        want = front[None] * cf[:, None, None] + ((1 - front) * back)[None] * cb[:, None, None]
+        out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(CAM64))
+        assert np.allclose(out.color.numpy(), want, atol=1e-12)
+
+
+def test_early_stop_after_five_of_eight():
+    # eight identical opaque-ish Gaussians centred on pixel (32, 32): alpha = 0.8
+    cam = CAM64
+    zs = 1.0 + 0.1 * np.arange(8)
+    means = [[(32.5 - cam.cx) * z / cam.fx, (32.5 - cam.cy) * z / cam.fy, z] for z in zs]
+    col = np.array([0.3, 0.6, 0.9])
+    sc = one_gaussian_scene(means, math.log(0.05), 0.8, col)
+    out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam))
+    o = 1 / (1 + math.exp(-float(sc.opacity_logits[0])))
+    assert abs(o - 0.8) < 1e-7
+    assert out.n_blended[32, 32].item() == 5
+    assert out.last_id[32, 32].item() == 4
+    assert out.final_t[32, 32].item() == pytest.approx((1 - o) ** 5, rel=1e-12)
+    want = (1 - (1 - o) ** 5) * sc.colors[0].astype(np.float64)
+    assert np.allclose(out.color[:, 32, 32].numpy(), want, rtol=1e-12, atol=0)
+
+
+def test_clamp_has_zero_opacity_gradient_and_faint_gaussian_is_culled():
+    z, s = 2.0, 0.08
+    sc = one_gaussian_scene([(32.5 - 32) * z / CAM64.fx, (32.5 - 32) * z / CAM64.fy, z],
+                            math.log(s), 0.999, [1, 1, 1])
+    gc = np.zeros((3, 64, 64))
+    gc[:, 32, 32] = 1.0
+    out, g = oracle.render_with_grads(sc.arrays(), _eye_view(), cam_tuple(CAM64), gc,
+                                      np.zeros((64, 64)))
+    assert out.alpha[32, 32].item() == pytest.approx(0.99, abs=1e-15)
+    assert g.opacity_logits[0].item() == 0.0
+    assert np.all(g.means.numpy() == 0.0)
+    faint = one_gaussian_scene([0, 0, z], math.log(s), 0.003, [1, 1, 1])
+    out = oracle.render(faint.arrays(), _eye_view(), cam_tuple(CAM64))
+    assert out.alpha.abs().max().item() == 0.0 and not out.proj.valid[0]
+
+
+def _c0_small(n=600, seed=7):
+    spec = synth.SceneSpec("t", 64, 64, n, seed)
+    return synth.make_scene(spec, CAM64)
+
+
+def test_invariants_on_random_scene():
+    sc = _c0_small()
+    out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(CAM64))
+    a, t = out.alpha.numpy(), out.final_t.numpy()
+    assert np.all(a >= 0) and np.all(a <= 1)
+    assert np.all(t >= 1e-4)
+    zmax = sc.means[:, 2].max()
+    assert np.all(out.depth.numpy() <= zmax * a + 1e-12) and np.all(out.depth.numpy() >= 0)
+    cmax = sc.colors.max()
+    assert np.all(out.color.numpy() >= 0) and np.all(out.color.numpy() <= cmax * a[None] + 1e-12)
+    assert (out.n_blended.numpy() > 0).mean() > 0.5
+
+
+def test_colour_linearity_and_colour_gradient_by_one_hot_renders():
+    sc = _c0_small(n=150, seed=8)
+    out1 = oracle.render(sc.arrays(), _eye_view(), cam_tuple(CAM64))
+    sc2 = synth.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits,
+                      (sc.colors * np.float32(0.5)).astype(np.float32))
+    out2 = oracle.render(sc2.arrays(), _eye_view(), cam_tuple(CAM64))
+    assert np.allclose(out2.color.numpy(), 0.5 * out1.color.numpy(), atol=1e-14)
+    rng = np.random.default_rng(3)
+    gc = rng.normal(size=(3, 64, 64))
+    _, g = oracle.render_with_grads(sc.arrays(), _eye_view(), cam_tuple(CAM64), gc,
+                                    np.zeros((64, 64)))
+    for k in (0, 17, 99):
+        col = np.zeros_like(sc.colors)
+        col[k] = 1.0
+        sk = synth.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, col)
+        w = oracle.render(sk.arrays(), _eye_view(), cam_tuple(CAM64)).color[0].numpy()
+        want = (gc * w[None]).sum((1, 2))
+        assert np.allclose(g.colors[k].numpy(), want, rtol=1e-10, atol=1e-14)
+
+
+def _hamilton(a, b):
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b.T
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw], 1)
+
+
+def test_rigid_motion_of_scene_and_camera_leaves_image_unchanged():
+    sc = _c0_small(n=200, seed=9)
+    rng = np.random.default_rng(4)
+    qg = rng.normal(size=4)
+    qg /= np.linalg.norm(qg)
+    rg = Rotation.from_quat(qg[[1, 2, 3, 0]]).as_matrix()
+    tg = rng.normal(size=3)
+    means2 = sc.means.astype(np.float64) @ rg.T + tg
+    quats2 = _hamilton(qg, sc.quats.astype(np.float64))
+    view2 = np.concatenate([rg.T, (-rg.T @ tg)[:, None]], 1)     # V G^-1
+    a = oracle.render(sc.arrays(), _eye_view(), cam_tuple(CAM64))
+    b = oracle.render((means2, sc.log_scales, quats2, sc.opacity_logits, sc.colors), view2,
+                      cam_tuple(CAM64))
+    assert np.allclose(a.color.numpy(), b.color.numpy(), atol=1e-10)
+    assert np.allclose(a.depth.numpy(), b.depth.numpy(), atol=1e-10)
+
+
+def test_translation_identity_for_pose_gradient():
+    sc = _c0_small(n=200, seed=10)
+    xi = torch.tensor(synth.pose_offset(5, 0.05, 3.0))
+    view = oracle.apply_left(xi, torch.tensor(_eye_view())).numpy()
+    rng = np.random.default_rng(5)
+    _, g = oracle.render_with_grads(sc.arrays(), view, cam_tuple(CAM64),
+                                    rng.normal(size=(3, 64, 64)), rng.normal(size=(64, 64)),
+                                    rng.normal(size=(64, 64)))
+    lhs = g.pose[:3].numpy()
+    rhs = view[:, :3] @ g.means.numpy().sum(0)
+    assert np.allclose(lhs, rhs, rtol=1e-10, atol=1e-12)
+    assert np.abs(g.pose[3:].numpy()).max() > 0
+
+
+# ---------------------------------------------------------------- Step 1-2 / 2
+def _stage32(sc, cam):
+    p = _proj(sc, cam)
+    o = 1 / (1 + np.exp(-sc.opacity_logits.astype(np.float64)))
+    t = 2 * np.log(np.maximum(255 * o, 1.0))
+    ex = np.sqrt(t * p.cov2d[:, 0, 0].numpy()).astype(np.float32)
+    ey = np.sqrt(t * p.cov2d[:, 1, 1].numpy()).astype(np.float32)
+    return (p.u.numpy().astype(np.float32), p.v.numpy().astype(np.float32), ex, ey,
+            p.z.numpy().astype(np.float32), p.valid.numpy(), p)
+
+
+def test_tile_lists_match_bruteforce_loop_with_sorted_tuples():
+    cam = synth.Camera(72, 40, 57.6, 57.6, 36.0, 20.0)      # ragged 5x3 tiles
+    sc = synth.make_scene(synth.SceneSpec("t", 72, 40, 300, 11), cam)
+    u, v, ex, ey, z, valid, _ = _stage32(sc, cam)
+    z[5] = z[6]                                              # force a depth tie
+    ranges, ids = binning.tile_lists(u, v, ex, ey, z, valid, 72, 40)
+    tx0, ty0, tx1, ty1 = binning.tile_rects(u, v, ex, ey, valid, 72, 40)
+    for t in range(5 * 3):
+        tx, ty = t % 5, t // 5
+        members = [g for g in range(len(u))
+                   if tx0[g] <= tx <= tx1[g] and ty0[g] <= ty <= ty1[g]]
+        want = [g for _, g in sorted((int(np.float32(z[g]).view(np.uint32)), g) for g in members)]
+        got = ids[ranges[t, 0]:ranges[t, 1]].tolist()
+        assert got == want
+
+
+def test_tile_rect_rule_by_hand():
+    # centre 20.3, half-width 3.2: pixels [15, 24] -> tiles 0..1
+    tx0, ty0, tx1, ty1 = binning.tile_rects([20.3], [5.0], [3.2], [1.0], [True], 64, 64)
+    assert (tx0[0], tx1[0]) == (math.floor(20.3 - 3.2 - 1.5) // 16, math.ceil(20.3 + 3.2 + 0.5) // 16)
+    assert (ty0[0], ty1[0]) == (0, 0)
+    # fully off screen to the left
+    tx0, _, tx1, _ = binning.tile_rects([-10.0], [5.0], [3.0], [1.0], [True], 64, 64)
+    assert tx1[0] < tx0[0]
+
+
+def test_tile_lists_cover_every_fragment():
+    cam = CAM64
+    sc = _c0_small(n=300, seed=12)
+    u, v, ex, ey, z, valid, p = _stage32(sc, cam)
+    ranges, ids = binning.tile_lists(u, v, ex, ey, z, valid, 64, 64)
+    o = torch.sigmoid(torch.tensor(sc.opacity_logits, dtype=F64))
+    jj, ii = np.mgrid[0:64, 0:64]
+    px = torch.tensor(ii.ravel() + 0.5)
+    py = torch.tensor(jj.ravel() + 0.5)
+    dx = p.u[None] - px[:, None]
+    dy = p.v[None] - py[:, None]
+    al = o[None] * torch.exp(-0.5 * (p.a * dx * dx + 2 * p.b * dx * dy + p.c * dy * dy))
+    frag = (al >= 1 / 255) & p.valid[None]
+    tiles = (jj.ravel() // 16) * 4 + ii.ravel() // 16
+    members = [set(ids[ranges[t, 0]:ranges[t, 1]].tolist()) for t in range(16)]
+    pix, gs = torch.nonzero(frag, as_tuple=True)
+    assert len(pix) > 1000
+    for pi, g in zip(pix.tolist(), gs.tolist()):
+        assert g in members[tiles[pi]]
+
+
+# ---------------------------------------------------------------- Eq. (7), Sec. 4
+def test_importance_score_by_hand():
+    gm = np.array([[3.0, 4.0, 0.0], [0, 0, 0]])
+    g6 = np.array([[1.0, 0, 0, 0, 0, 0], [0, 1.0, 0, 0, 0, 0]])
+    s = selection.importance_score(gm, g6, 0.8)
+    assert np.allclose(s, [5.8, 0.8 * math.sqrt(2)])
+
+
+def test_prune_select_by_hand():
+    score = np.array([0.5, 0.1, 0.1, 0.9, 0.05, 0.3, 0.2, 0.4], np.float32)
+    visible = np.array([1, 1, 1, 1, 0, 1, 1, 1], np.uint8)
+    mask_in = np.array([0, 0, 0, 0, 0, 0, 1, 0], np.uint8)
+    out, k = selection.prune_select(score, visible, mask_in, 0.5)
+    # candidates 0,1,2,3,5,7 (V=6) -> 3 lowest: 1, 2 (tie, by index), 5
+    assert k == 3
+    assert out.tolist() == [0, 1, 1, 0, 0, 1, 1, 0]
+
+
+def test_downsample_schedule():
+    f = selection.downsample_log2_ratio
+    assert f(True, 10, 10) == 0
+    assert [f(False, n, 10, 2) for n in range(11, 16)] == [4, 3, 2, 2, 2]
+    assert [f(False, n, 10, 4) for n in range(11, 14)] == [4, 2, 2]
+    assert selection.block_shape(4) == (4, 4) and selection.block_shape(3) == (4, 2)
+    assert selection.block_shape(2) == (2, 2)
+
+
+def test_downsample_select_by_hand():
+    t = np.ones((5, 6), np.float32)
+    t[0, 1] = 0.5
+    t[1, 2] = 0.5          # tie inside the first 4x4 block: raster-first (0,1) wins
+    t[3, 5] = 0.2          # ragged right block (cols 4-5)
+    t[4, 0] = 0.9          # ragged bottom row
+    m = selection.downsample_select(t, 4)
+    assert m.sum() == 4
+    assert m[0, 1] == 1 and m[1, 2] == 0 and m[3, 5] == 1 and m[4, 0] == 1
+    m2 = selection.downsample_select(t, 0)
+    assert m2.all()
+
+
+def test_l1_loss_gradient_by_hand():
+    c = np.zeros((3, 2, 2))
+    tc = np.zeros((3, 2, 2))
+    tc[0, 0, 0] = 1.0
+    d = np.ones((2, 2))
+    td = np.zeros((2, 2))
+    loss, gc, gd = oracle.l1_loss_grads(c, d, tc, td)
+    assert loss.item() == pytest.approx(1 / 12 + 0.5)
+    assert gc[0, 0, 0].item() == pytest.approx(-1 / 12) and gc[1, 1, 1].item() == 0.0
+    assert torch.allclose(gd, torch.full((2, 2), 0.125, dtype=F64))
+
+
+def test_ambiguity_flags_mark_threshold_cases():
+    # choose the opacity so that alpha~ at pixel (32, 32) sits on the 1/255 floor
+    cam = CAM64
+    z, s = 2.0, 0.05
+    mean = [(32.5 - cam.cx - 3.0) * z / cam.fx, (32.5 - cam.cy) * z / cam.fy, z]
+    probe = one_gaussian_scene(mean, math.log(s), 0.5, [1, 1, 1])
+    p = _proj(probe, cam)
+    dx, dy = p.u.item() - 32.5, p.v.item() - 32.5
+    q = p.a.item() * dx * dx + 2 * p.b.item() * dx * dy + p.c.item() * dy * dy
+    o = (1 / 255) / math.exp(-0.5 * q) * (1 + 2e-6)
+    sc = one_gaussian_scene(mean, math.log(s), o, [1, 1, 1])
+    out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam), band_alpha=1e-4)
+    assert out.flags[32, 32]
+    assert out.flags.sum() < 10
+    far = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam), band_alpha=1e-9)
+    assert not far.flags[32, 32]
