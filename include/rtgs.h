@@ -1,0 +1,268 @@
+/*
+ * rtgs.h - C ABI of librtgs, the MI355X (gfx950) differentiable tile-based
+ * Gaussian-splatting rasterizer used by 3DGS-SLAM tracking and mapping.
+ *
+ * The operations follow the paper's rendering pipeline (Sec. 2.1, Steps 1-3)
+ * and its backpropagation (Sec. 2.2, Steps 4-5), plus the two redundancy
+ * reductions of Sec. 4 (adaptive Gaussian pruning, dynamic downsampling).
+ * The status query mirrors the paper's programming model (Sec. 5.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int32 status (RTGS_OK or a negative RTGS_ERR_*)
+ *   and never throws.  rtgs_last_error() returns a message for the calling
+ *   thread's last failure.
+ * - All array arguments are DEVICE pointers unless stated otherwise; they are
+ *   owned by the caller, must stay alive until the work on `stream` has
+ *   finished, and are never freed by the library.  Inputs are read-only;
+ *   outputs are overwritten, never accumulated.
+ * - `stream` is a hipStream_t passed as void*; every call only enqueues work
+ *   on it (asynchronous).  NULL means the default stream.
+ * - Layouts are contiguous float32:
+ *     means [n][3], log_scales [n][3] (log standard deviations per axis),
+ *     quats [n][4] as (w, x, y, z) (normalised inside), opacity_logits [n],
+ *     colors [n][3] (RGB, spherical harmonics of degree 0);
+ *     images are planar: color [3][H][W], depth/alpha/final_T [H][W];
+ *     viewmat is a device array of 12 floats, row-major 3x4 world->camera.
+ *   Pixel (i, j) samples the image plane at (i + 0.5, j + 0.5); depth is the
+ *   camera-space z.
+ * - A handle (rtgs_create) owns only small host/device scalars, an event and
+ *   a ring of pinned staging buffers; use one handle per stream.
+ * - Workspace: the caller allocates `ws` of the size given by
+ *   rtgs_workspace_size*, and passes the same `ws` to render_fwd and to the
+ *   render_bwd that follows it (the backward reuses the forward's projected
+ *   Gaussians, tile lists and depth order: the sort is not redone, Sec. 2.2).
+ * - Pair capacity: the number of (tile, Gaussian) pairs is data dependent.
+ *   The caller sizes the pair buffer (`pair_capacity`); if a frame needs more,
+ *   the excess pairs are dropped on the device (no fault), the output of that
+ *   call is invalid, and rtgs_query() reports RTGS_ERR_CAPACITY together
+ *   with the number of pairs needed.  Nothing forces a host sync.
+ */
+#ifndef RTGS_H
+#define RTGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define RTGS_OK               0
+#define RTGS_ERR_INVALID_ARG (-1)  /* null pointer, n < 0, W/H <= 0, bad flag  */
+#define RTGS_ERR_CAPACITY    (-2)  /* pair buffer too small (see rtgs_query)  */
+#define RTGS_ERR_HIP         (-3)  /* a HIP runtime call failed                */
+#define RTGS_ERR_WORKSPACE   (-4)  /* workspace smaller than required          */
+
+/* ---- render_fwd flags ---- */
+#define RTGS_FWD_SAVE_STATE   1   /* write final_T and last_idx (saved state)  */
+
+/* ---- render_bwd flags ---- */
+#define RTGS_GRAD_POSE        1   /* write g_pose6                             */
+#define RTGS_GRAD_MAP         2   /* write the five per-Gaussian gradients     */
+#define RTGS_GRAD_COV3D       4   /* also write g_cov3d (needs RTGS_GRAD_MAP)  */
+#define RTGS_GRAD_RECOMPUTE_STATE 8 /* final_T/last_idx were not saved: the
+                                       backward recomputes them first          */
+
+/* ---- query states (Sec. 5.5: IDLE / EXECUTING) ---- */
+#define RTGS_STATE_IDLE       0
+#define RTGS_STATE_EXECUTING  1
+
+#define RTGS_MAX_SESSIONS     64
+
+typedef struct rtgs_context* rtgs_handle_t;
+
+/* A Gaussian map (Eq. 1: mean, covariance via log-scales + quaternion,
+ * opacity via its logit, colour).  gauss_mask may be NULL; a nonzero entry
+ * excludes that Gaussian from rendering (the mask of the mask-prune step,
+ * Sec. 4.1). */
+typedef struct {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* colors;
+  const uint8_t* gauss_mask;
+  int32_t n;
+} rtgs_gaussians;
+
+/* Pinhole camera.  Intrinsics are host values; viewmat is a device pointer so
+ * a pose optimised on the device needs no host round trip. */
+typedef struct {
+  int32_t width;
+  int32_t height;
+  float fx, fy, cx, cy;
+  const float* viewmat;  /* device, 12 floats, row-major [R | t] */
+} rtgs_camera;
+
+/* One session of a batched call: its own map, camera, masks, outputs and
+ * gradients; same meaning as the arguments of render_fwd / render_bwd. */
+typedef struct {
+  rtgs_gaussians g;
+  rtgs_camera cam;
+  const uint8_t* pixel_mask;   /* [H][W] or NULL (all pixels active) */
+  /* forward outputs */
+  float* color;                /* [3][H][W] */
+  float* depth;                /* [H][W] expected depth sum w z */
+  float* alpha;                /* [H][W] 1 - final_T */
+  float* final_T;              /* [H][W] saved transmittance */
+  int32_t* last_idx;           /* [H][W] position of the last blended pair, -1 */
+  uint8_t* visible;            /* [n] 1 if projected and on screen, or NULL */
+  /* backward inputs */
+  const float* dL_dcolor;      /* [3][H][W] */
+  const float* dL_ddepth;      /* [H][W] */
+  const float* dL_dalpha;      /* [H][W] or NULL */
+  /* backward outputs (any may be NULL when its flag is off) */
+  float* g_means;              /* [n][3] */
+  float* g_log_scales;         /* [n][3] */
+  float* g_quats;              /* [n][4] */
+  float* g_opacity_logits;     /* [n] */
+  float* g_colors;             /* [n][3] */
+  float* g_pose6;              /* [6] (rho, phi) */
+  float* g_cov3d;              /* [n][6] (xx, xy, xz, yy, yz, zz) */
+} rtgs_session;
+
+/* Last error message of the calling thread (static storage, never NULL). */
+const char* rtgs_last_error(void);
+
+/* Create / destroy a handle bound to a HIP device. */
+int32_t rtgs_create(rtgs_handle_t* out, int32_t device);
+int32_t rtgs_destroy(rtgs_handle_t h);
+
+/* Bytes of workspace for one session of n Gaussians at width x height with
+ * room for pair_capacity (tile, Gaussian) pairs; flags are render_fwd flags.
+ * `bytes` is a HOST pointer. */
+int32_t rtgs_workspace_size(int32_t n, int32_t width, int32_t height,
+                            int64_t pair_capacity, int32_t flags,
+                            uint64_t* bytes);
+
+/* Same for a batch; n, width, height are HOST arrays of n_sessions. */
+int32_t rtgs_workspace_size_batched(const int32_t* n, const int32_t* width,
+                                    const int32_t* height, int32_t n_sessions,
+                                    int64_t pair_capacity, int32_t flags,
+                                    uint64_t* bytes);
+
+/* Forward pass (Steps 1-3, Sec. 2.1):
+ *  1-1 projection: EWA linearisation of each Gaussian (Eq. 1) to a 2D mean,
+ *      conic, opacity, colour and depth; Gaussians behind the near plane
+ *      (z <= 0.2), masked, or with 255 * opacity < 1 are culled;
+ *  1-2 tile intersection with 16x16 tiles;
+ *  2   per-tile depth sort (ascending z, ties by Gaussian index);
+ *  3   alpha (Eq. 2) and front-to-back blending (Eq. 3): alpha is clamped to
+ *      0.99, fragments with alpha < 1/255 are skipped, a pixel stops before
+ *      the fragment that would take T below 1e-4.
+ * pixel_mask may be NULL; masked pixels render 0 with final_T = 1.
+ * final_T and last_idx are written when RTGS_FWD_SAVE_STATE is set (they may
+ * be NULL otherwise); visible may be NULL.
+ * Errors: INVALID_ARG (null required pointer, n < 0, W or H <= 0,
+ * pair_capacity < 0, bad flags), WORKSPACE (ws_bytes too small), HIP. */
+int32_t render_fwd(rtgs_handle_t h, const rtgs_gaussians* g,
+                   const rtgs_camera* cam, const uint8_t* pixel_mask,
+                   void* ws, uint64_t ws_bytes, int64_t pair_capacity,
+                   float* out_color, float* out_depth, float* out_alpha,
+                   float* final_T, int32_t* last_idx, uint8_t* visible_out,
+                   int32_t flags, void* stream);
+
+/* Backward pass (Steps 4-5, Sec. 2.2): the compositing in reverse from the
+ * saved final_T and last_idx (or recomputed with RTGS_GRAD_RECOMPUTE_STATE),
+ * per-pixel gradients merged per Gaussian, then pushed through the projection
+ * to the map parameters and to the pose.  The pose gradient is the derivative
+ * with respect to xi = (rho, phi) of Exp(xi) * viewmat at xi = 0 (left
+ * perturbation; rho translation, phi rotation).  g_cov3d is dL/dSigma of the
+ * world-frame covariance (symmetric, stored as xx, xy, xz, yy, yz, zz), the
+ * input of the importance score.  dL_dalpha may be NULL.
+ * The arguments g, cam, pixel_mask, ws and pair_capacity must be those of the
+ * render_fwd whose results are being differentiated.
+ * Errors: as render_fwd. */
+int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g,
+                   const rtgs_camera* cam, const uint8_t* pixel_mask,
+                   void* ws, uint64_t ws_bytes, int64_t pair_capacity,
+                   const float* final_T, const int32_t* last_idx,
+                   const float* dL_dcolor, const float* dL_ddepth,
+                   const float* dL_dalpha, int32_t grad_flags,
+                   float* g_means, float* g_log_scales, float* g_quats,
+                   float* g_opacity_logits, float* g_colors, float* g_pose6,
+                   float* g_cov3d, void* stream);
+
+/* Batched forward / backward over n_sessions (<= RTGS_MAX_SESSIONS): one
+ * launch per stage for all sessions, one tile space and one sort.  `sessions`
+ * is a HOST array; each entry has the meaning of the single-session
+ * arguments.  Per-session results equal those of single-session calls. */
+int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* sessions,
+                           int32_t n_sessions, void* ws, uint64_t ws_bytes,
+                           int64_t pair_capacity, int32_t flags, void* stream);
+int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* sessions,
+                           int32_t n_sessions, void* ws, uint64_t ws_bytes,
+                           int64_t pair_capacity, int32_t grad_flags,
+                           void* stream);
+
+/* Adaptive Gaussian pruning, the mask step (Sec. 4.1, Eq. 7):
+ * score_k = ||dL/dmu_k||_2 + lambda * ||dL/dSigma_k||_F (Frobenius over the
+ * nine entries of the symmetric gradient); among the V Gaussians with
+ * visible != 0 and mask_in == 0, the floor(max_ratio * V) with the lowest
+ * (score, index) are added to the mask: mask_out = mask_in | selected.
+ * visible and mask_in may be NULL (all visible / none masked).
+ * n_masked_dev (device int32) receives the number newly masked; score_out
+ * (device float [n]) may be NULL.  Requires 0 <= max_ratio <= 0.5 (the
+ * paper's 50% cap, Sec. 6.2); lambda defaults to 0.8 in the paper.
+ * Errors: INVALID_ARG, HIP. */
+int32_t prune_by_grad(rtgs_handle_t h, const float* g_means,
+                      const float* g_cov3d, const uint8_t* visible,
+                      const uint8_t* mask_in, int32_t n, float lambda,
+                      float max_ratio, uint8_t* mask_out,
+                      int32_t* n_masked_dev, float* score_out, void* stream);
+
+/* Dynamic downsampling (Sec. 4.2) as a pixel mask: keep 1 pixel in 2^j,
+ * one per block of 2^ceil(j/2) x 2^floor(j/2) pixels (4x4, 4x2, 2x2 for
+ * j = 4, 3, 2; ragged blocks at the right and bottom edges), choosing the
+ * pixel with the lowest final_T of the previous forward (ties to the lowest
+ * raster index).  j = 0 keeps every pixel.  n_active_dev (device int32, may
+ * be NULL) receives the number of kept pixels.  0 <= log2_ratio <= 8.
+ * Errors: INVALID_ARG, HIP. */
+int32_t downsample_mask(const float* final_T, int32_t width, int32_t height,
+                        int32_t log2_ratio, uint8_t* mask_out,
+                        int32_t* n_active_dev, void* stream);
+
+/* The downsampling schedule of Sec. 4.2 (host only): 0 for a keyframe; for
+ * non-keyframe n after keyframe k, the pixel ratio min(2^-4 m^(n-k-1), 2^-2)
+ * as j = max(2, 4 - floor((n - k - 1) log2 m)).  Returns j, or
+ * RTGS_ERR_INVALID_ARG if n <= k for a non-keyframe or m < 2. */
+int32_t rtgs_downsample_log2_ratio(int32_t is_keyframe, int32_t n, int32_t k,
+                                   int32_t m);
+
+/* Status (Sec. 5.5, the check-status call): with blocking != 0 waits for the
+ * work enqueued through h, then reports in *pairs_needed (HOST, may be NULL)
+ * the largest pair count any render_fwd needed since the previous query and
+ * resets it; returns RTGS_ERR_CAPACITY if that exceeded the capacity it was
+ * given.  With blocking == 0 and work pending, *state = RTGS_STATE_EXECUTING
+ * and nothing is reset. */
+int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed,
+                   int32_t* state);
+
+/* Test access to forward intermediates kept in a workspace after render_fwd.
+ * n, width, height (HOST arrays of n_sessions) and pair_capacity must be those
+ * of that call.  All outputs are device arrays and any may be NULL: per
+ * Gaussian of the batch (global index over sessions)
+ *   stage [n][12] = u, v, conic a, b, c, opacity, depth z, e_x, e_y,
+ *                   r, g, b   (u, v: float32 part of the centre; e_x, e_y:
+ *                   half-widths of the bounding box of the alpha = 1/255
+ *                   ellipse, Step 1-2)
+ *   rect [n][4]   = tile rectangle x0, y0, x1, y1 (x1 < x0 when empty)
+ * per tile of the batch: ranges [T][2] = [start, end) into ids; ids [P] =
+ * Gaussian ids in tile-then-depth order (at most ids_capacity written). */
+int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width,
+                         const int32_t* height, int32_t n_sessions,
+                         int64_t pair_capacity, const void* ws,
+                         uint64_t ws_bytes, float* stage, int32_t* rect,
+                         int32_t* ranges, int32_t* ids, int64_t ids_capacity,
+                         void* stream);
+
+/* Test hook for the wavefront reduction used by the backward merge: out[w] =
+ * sum of in[64 w .. 64 w + 63] for each wave w of n_waves. */
+int32_t rtgs_selftest_wave_sum(const float* in, float* out, int32_t n_waves,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTGS_H */

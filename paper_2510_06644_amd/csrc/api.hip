@@ -1,0 +1,545 @@
+// Host side of the C ABI declared in include/rtgs.h: argument validation,
+// workspace layout, the device session table and the launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rtgs_internal.h"
+
+using namespace rtgs;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int32_t hip_fail(hipError_t e, const char* what) {
+  return fail(RTGS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int kRing = 16;
+constexpr uint64_t kAlign = 256;
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Geometry {
+  int64_t n_total = 0, t_total = 0, b_total = 0, px_total = 0;
+};
+
+int64_t tiles_of(int w, int h) {
+  return (int64_t)((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+}
+
+int64_t blocks_of(int n) { return (n + kGaussPerBlock - 1) / kGaussPerBlock; }
+
+}  // namespace
+
+struct rtgs_context {
+  int device = 0;
+  unsigned long long* d_scalars = nullptr;   // [0] largest pair count since last query
+  uint32_t* d_prune = nullptr;               // prune scratch
+  SessionDev* h_ring = nullptr;              // pinned [kRing][RTGS_MAX_SESSIONS]
+  hipEvent_t ring_ev[kRing] = {};
+  int ring_pos = 0;
+  hipStream_t last_stream = nullptr;
+  int64_t min_cap = INT64_MAX;               // smallest capacity since last query
+  bool used = false;
+};
+
+namespace rtgs {
+
+WsLayout make_layout(int64_t n, int64_t t, int64_t b, int64_t cap, int64_t px) {
+  WsLayout L{};
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.table = take(sizeof(SessionDev) * RTGS_MAX_SESSIONS);
+  L.counters = take(64);
+  L.rec0 = take(16 * (uint64_t)n);
+  L.rec1 = take(16 * (uint64_t)n);
+  L.rec2 = take(16 * (uint64_t)n);
+  L.ext = take(16 * (uint64_t)n);
+  L.rect = take(16 * (uint64_t)n);
+  L.grad2d = take(4 * (uint64_t)kGrad2dStride * n);
+  L.pose_part = take(64 * (uint64_t)b);
+  L.tile_count = take(4 * (uint64_t)(t + 1));
+  L.tile_start = take(4 * (uint64_t)(t + 1));
+  L.tile_cursor = take(4 * (uint64_t)(t + 1));
+  L.keys = take(8 * (uint64_t)cap);
+  L.ids = take(4 * (uint64_t)cap);
+  L.state_t = take(4 * (uint64_t)px);
+  L.state_last = take(4 * (uint64_t)px);
+  L.total = off;
+  L.n_total = n;
+  L.t_total = t;
+  L.b_total = b;
+  L.cap = cap;
+  return L;
+}
+
+WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
+  char* base = static_cast<char*>(ws);
+  WsPtrs w{};
+  w.table = reinterpret_cast<SessionDev*>(base + L.table);
+  w.counters = reinterpret_cast<long long*>(base + L.counters);
+  w.rec0 = reinterpret_cast<float4*>(base + L.rec0);
+  w.rec1 = reinterpret_cast<float4*>(base + L.rec1);
+  w.rec2 = reinterpret_cast<float4*>(base + L.rec2);
+  w.ext = reinterpret_cast<float4*>(base + L.ext);
+  w.rect = reinterpret_cast<int4*>(base + L.rect);
+  w.grad2d = reinterpret_cast<float*>(base + L.grad2d);
+  w.pose_part = reinterpret_cast<double*>(base + L.pose_part);
+  w.tile_count = reinterpret_cast<uint32_t*>(base + L.tile_count);
+  w.tile_start = reinterpret_cast<uint32_t*>(base + L.tile_start);
+  w.tile_cursor = reinterpret_cast<uint32_t*>(base + L.tile_cursor);
+  w.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
+  w.ids = reinterpret_cast<uint32_t*>(base + L.ids);
+  w.state_t = reinterpret_cast<float*>(base + L.state_t);
+  w.state_last = reinterpret_cast<int32_t*>(base + L.state_last);
+  w.cap = L.cap;
+  return w;
+}
+
+}  // namespace rtgs
+
+namespace {
+
+int32_t geometry(const int32_t* n, const int32_t* w, const int32_t* h, int32_t ns, Geometry& g) {
+  if (ns < 1 || ns > RTGS_MAX_SESSIONS)
+    return fail(RTGS_ERR_INVALID_ARG, "n_sessions %d outside [1, %d]", ns, RTGS_MAX_SESSIONS);
+  for (int s = 0; s < ns; ++s) {
+    if (n[s] < 0) return fail(RTGS_ERR_INVALID_ARG, "session %d: n = %d < 0", s, n[s]);
+    if (w[s] <= 0 || h[s] <= 0)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: image %d x %d", s, w[s], h[s]);
+    g.n_total += n[s];
+    g.t_total += tiles_of(w[s], h[s]);
+    g.b_total += blocks_of(n[s]);
+    g.px_total += (int64_t)w[s] * h[s];
+  }
+  if (g.n_total > INT32_MAX / 2 || g.t_total > INT32_MAX / 2 || g.px_total > INT32_MAX / 2)
+    return fail(RTGS_ERR_INVALID_ARG, "batch too large");
+  return RTGS_OK;
+}
+
+int32_t check_cap(int64_t cap) {
+  if (cap < 0 || cap > (int64_t)INT32_MAX)
+    return fail(RTGS_ERR_INVALID_ARG, "pair_capacity %lld outside [0, 2^31)", (long long)cap);
+  return RTGS_OK;
+}
+
+// Validate one session's pointers for the requested direction.
+int32_t check_session(const rtgs_session& s, int idx, bool fwd, int32_t flags) {
+  const rtgs_gaussians& g = s.g;
+  if (g.n > 0 && (!g.means || !g.log_scales || !g.quats || !g.opacity_logits || !g.colors))
+    return fail(RTGS_ERR_INVALID_ARG, "session %d: null Gaussian parameter array", idx);
+  if (!s.cam.viewmat) return fail(RTGS_ERR_INVALID_ARG, "session %d: null viewmat", idx);
+  if (!(s.cam.fx > 0.f) || !(s.cam.fy > 0.f) || !std::isfinite(s.cam.fx) ||
+      !std::isfinite(s.cam.fy) || !std::isfinite(s.cam.cx) || !std::isfinite(s.cam.cy))
+    return fail(RTGS_ERR_INVALID_ARG, "session %d: bad intrinsics", idx);
+  if (fwd) {
+    if (!s.color || !s.depth || !s.alpha)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: null colour/depth/alpha output", idx);
+    if ((flags & RTGS_FWD_SAVE_STATE) && (!s.final_T || !s.last_idx))
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: SAVE_STATE needs final_T and last_idx", idx);
+  } else {
+    if (!s.dL_dcolor || !s.dL_ddepth)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: null dL/dcolor or dL/ddepth", idx);
+    if (!(flags & RTGS_GRAD_RECOMPUTE_STATE) && (!s.final_T || !s.last_idx))
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: saved state missing", idx);
+    if ((flags & RTGS_GRAD_MAP) && g.n > 0 &&
+        (!s.g_means || !s.g_log_scales || !s.g_quats || !s.g_opacity_logits || !s.g_colors))
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: null map gradient output", idx);
+    if ((flags & RTGS_GRAD_POSE) && !s.g_pose6)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: null pose gradient output", idx);
+    if ((flags & RTGS_GRAD_COV3D) && (!(flags & RTGS_GRAD_MAP) || (g.n > 0 && !s.g_cov3d)))
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: COV3D needs MAP and g_cov3d", idx);
+  }
+  return RTGS_OK;
+}
+
+// Fill a ring slot with the device table, copy it into the workspace.
+int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPtrs& w,
+                     hipStream_t st, bool fwd, int32_t flags, Batch& B) {
+  const int slot = h->ring_pos;
+  h->ring_pos = (h->ring_pos + 1) % kRing;
+  hipError_t e = hipEventSynchronize(h->ring_ev[slot]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  SessionDev* t = h->h_ring + (size_t)slot * RTGS_MAX_SESSIONS;
+  int32_t gbase = 0, bbase = 0, tbase = 0;
+  int64_t pbase = 0;
+  for (int i = 0; i < ns; ++i) {
+    const rtgs_session& s = ss[i];
+    SessionDev d{};
+    d.means = s.g.means;
+    d.log_scales = s.g.log_scales;
+    d.quats = s.g.quats;
+    d.opac = s.g.opacity_logits;
+    d.colors = s.g.colors;
+    d.gmask = s.g.gauss_mask;
+    d.viewmat = s.cam.viewmat;
+    d.pmask = s.pixel_mask;
+    d.n = s.g.n;
+    d.width = s.cam.width;
+    d.height = s.cam.height;
+    d.tiles_x = (s.cam.width + kTile - 1) / kTile;
+    d.tiles_y = (s.cam.height + kTile - 1) / kTile;
+    d.fx = s.cam.fx;
+    d.fy = s.cam.fy;
+    d.cx = s.cam.cx;
+    d.cy = s.cam.cy;
+    d.gauss_base = gbase;
+    d.block_base = bbase;
+    d.tile_base = tbase;
+    if (fwd) {
+      d.color = s.color;
+      d.depth = s.depth;
+      d.alpha = s.alpha;
+      d.final_T = (flags & RTGS_FWD_SAVE_STATE) ? s.final_T : nullptr;
+      d.last_idx = (flags & RTGS_FWD_SAVE_STATE) ? s.last_idx : nullptr;
+      d.visible = s.visible;
+    } else {
+      if (flags & RTGS_GRAD_RECOMPUTE_STATE) {
+        d.final_T = w.state_t + pbase;
+        d.last_idx = w.state_last + pbase;
+      } else {
+        d.final_T = const_cast<float*>(s.final_T);
+        d.last_idx = const_cast<int32_t*>(s.last_idx);
+      }
+      d.dl_color = s.dL_dcolor;
+      d.dl_depth = s.dL_ddepth;
+      d.dl_alpha = s.dL_dalpha;
+      if (flags & RTGS_GRAD_MAP) {
+        d.g_means = s.g_means;
+        d.g_log_scales = s.g_log_scales;
+        d.g_quats = s.g_quats;
+        d.g_opac = s.g_opacity_logits;
+        d.g_colors = s.g_colors;
+        d.g_cov3d = (flags & RTGS_GRAD_COV3D) ? s.g_cov3d : nullptr;
+      }
+      d.g_pose6 = (flags & RTGS_GRAD_POSE) ? s.g_pose6 : nullptr;
+    }
+    t[i] = d;
+    gbase += s.g.n;
+    bbase += (int32_t)blocks_of(s.g.n);
+    tbase += (int32_t)tiles_of(s.cam.width, s.cam.height);
+    pbase += (int64_t)s.cam.width * s.cam.height;
+  }
+  e = hipMemcpyAsync(w.table, t, sizeof(SessionDev) * ns, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(session table)");
+  e = hipEventRecord(h->ring_ev[slot], st);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  B.sess = w.table;
+  B.n_sessions = ns;
+  B.n_total = gbase;
+  B.t_total = tbase;
+  B.b_total = bbase;
+  return RTGS_OK;
+}
+
+int32_t prepare(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws, uint64_t ws_bytes,
+                int64_t cap, WsLayout& L, WsPtrs& w) {
+  if (!h) return fail(RTGS_ERR_INVALID_ARG, "null handle");
+  if (!ss) return fail(RTGS_ERR_INVALID_ARG, "null sessions");
+  if (ns < 1 || ns > RTGS_MAX_SESSIONS)
+    return fail(RTGS_ERR_INVALID_ARG, "n_sessions %d outside [1, %d]", ns, RTGS_MAX_SESSIONS);
+  int32_t r = check_cap(cap);
+  if (r) return r;
+  std::vector<int32_t> n(ns), wd(ns), ht(ns);
+  for (int i = 0; i < ns; ++i) {
+    n[i] = ss[i].g.n;
+    wd[i] = ss[i].cam.width;
+    ht[i] = ss[i].cam.height;
+  }
+  Geometry g;
+  r = geometry(n.data(), wd.data(), ht.data(), ns, g);
+  if (r) return r;
+  if (!ws) return fail(RTGS_ERR_INVALID_ARG, "null workspace");
+  L = make_layout(g.n_total, g.t_total, g.b_total, cap, g.px_total);
+  if (ws_bytes < L.total)
+    return fail(RTGS_ERR_WORKSPACE, "workspace %llu bytes < required %llu",
+                (unsigned long long)ws_bytes, (unsigned long long)L.total);
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(RTGS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  w = ws_ptrs(ws, L);
+  return RTGS_OK;
+}
+
+rtgs_session single(const rtgs_gaussians* g, const rtgs_camera* cam, const uint8_t* pmask) {
+  rtgs_session s{};
+  s.g = *g;
+  s.cam = *cam;
+  s.pixel_mask = pmask;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rtgs_last_error(void) { return g_err.c_str(); }
+
+int32_t rtgs_create(rtgs_handle_t* out, int32_t device) {
+  if (!out) return fail(RTGS_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= count)
+    return fail(RTGS_ERR_INVALID_ARG, "device %d outside [0, %d)", device, count);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  auto* h = new rtgs_context();
+  h->device = device;
+  e = hipMalloc(&h->d_scalars, 64);
+  if (e == hipSuccess) e = hipMemset(h->d_scalars, 0, 64);
+  if (e == hipSuccess) e = hipMalloc(&h->d_prune, sizeof(uint32_t) * kPruneScratchWords);
+  if (e == hipSuccess)
+    e = hipHostMalloc(&h->h_ring, sizeof(SessionDev) * RTGS_MAX_SESSIONS * kRing,
+                      hipHostMallocDefault);
+  for (int i = 0; i < kRing && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&h->ring_ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    rtgs_destroy(h);
+    return hip_fail(e, "rtgs_create");
+  }
+  *out = h;
+  return RTGS_OK;
+}
+
+int32_t rtgs_destroy(rtgs_handle_t h) {
+  if (!h) return RTGS_OK;
+  (void)hipDeviceSynchronize();
+  for (int i = 0; i < kRing; ++i)
+    if (h->ring_ev[i]) (void)hipEventDestroy(h->ring_ev[i]);
+  if (h->h_ring) (void)hipHostFree(h->h_ring);
+  if (h->d_prune) (void)hipFree(h->d_prune);
+  if (h->d_scalars) (void)hipFree(h->d_scalars);
+  delete h;
+  return RTGS_OK;
+}
+
+int32_t rtgs_workspace_size_batched(const int32_t* n, const int32_t* width, const int32_t* height,
+                                    int32_t n_sessions, int64_t pair_capacity, int32_t flags,
+                                    uint64_t* bytes) {
+  (void)flags;
+  if (!n || !width || !height || !bytes) return fail(RTGS_ERR_INVALID_ARG, "null argument");
+  int32_t r = check_cap(pair_capacity);
+  if (r) return r;
+  Geometry g;
+  r = geometry(n, width, height, n_sessions, g);
+  if (r) return r;
+  *bytes = make_layout(g.n_total, g.t_total, g.b_total, pair_capacity, g.px_total).total;
+  return RTGS_OK;
+}
+
+int32_t rtgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t pair_capacity,
+                            int32_t flags, uint64_t* bytes) {
+  return rtgs_workspace_size_batched(&n, &width, &height, 1, pair_capacity, flags, bytes);
+}
+
+int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
+                           uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
+  if (flags & ~RTGS_FWD_SAVE_STATE) return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
+  WsLayout L;
+  WsPtrs w;
+  int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w);
+  if (r) return r;
+  for (int i = 0; i < ns; ++i)
+    if ((r = check_session(ss[i], i, true, flags))) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Batch B;
+  r = upload_table(h, ss, ns, w, st, true, flags, B);
+  if (r) return r;
+  hipError_t e = launch_forward_prep(B, w, h->d_scalars, st);
+  if (e == hipSuccess) e = launch_raster_fwd(B, w, flags & RTGS_FWD_SAVE_STATE, st);
+  if (e != hipSuccess) return hip_fail(e, "render_fwd launch");
+  h->last_stream = st;
+  h->used = true;
+  if (cap < h->min_cap) h->min_cap = cap;
+  return RTGS_OK;
+}
+
+int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
+                           uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
+  const int32_t known = RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_COV3D | RTGS_GRAD_RECOMPUTE_STATE;
+  if (flags & ~known) return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
+  if (!(flags & (RTGS_GRAD_POSE | RTGS_GRAD_MAP)))
+    return fail(RTGS_ERR_INVALID_ARG, "render_bwd needs RTGS_GRAD_POSE and/or RTGS_GRAD_MAP");
+  WsLayout L;
+  WsPtrs w;
+  int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w);
+  if (r) return r;
+  for (int i = 0; i < ns; ++i)
+    if ((r = check_session(ss[i], i, false, flags))) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Batch B;
+  r = upload_table(h, ss, ns, w, st, false, flags, B);
+  if (r) return r;
+  hipError_t e = hipSuccess;
+  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, 1, st);
+  if (e == hipSuccess) e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, st);
+  if (e == hipSuccess) e = launch_preprocess_bwd(B, w, flags, st);
+  if (e != hipSuccess) return hip_fail(e, "render_bwd launch");
+  h->last_stream = st;
+  h->used = true;
+  return RTGS_OK;
+}
+
+int32_t render_fwd(rtgs_handle_t h, const rtgs_gaussians* g, const rtgs_camera* cam,
+                   const uint8_t* pixel_mask, void* ws, uint64_t ws_bytes, int64_t cap,
+                   float* out_color, float* out_depth, float* out_alpha, float* final_T,
+                   int32_t* last_idx, uint8_t* visible_out, int32_t flags, void* stream) {
+  if (!g || !cam) return fail(RTGS_ERR_INVALID_ARG, "null gaussians or camera");
+  rtgs_session s = single(g, cam, pixel_mask);
+  s.color = out_color;
+  s.depth = out_depth;
+  s.alpha = out_alpha;
+  s.final_T = final_T;
+  s.last_idx = last_idx;
+  s.visible = visible_out;
+  return render_fwd_batched(h, &s, 1, ws, ws_bytes, cap, flags, stream);
+}
+
+int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g, const rtgs_camera* cam,
+                   const uint8_t* pixel_mask, void* ws, uint64_t ws_bytes, int64_t cap,
+                   const float* final_T, const int32_t* last_idx, const float* dL_dcolor,
+                   const float* dL_ddepth, const float* dL_dalpha, int32_t grad_flags,
+                   float* g_means, float* g_log_scales, float* g_quats, float* g_opacity_logits,
+                   float* g_colors, float* g_pose6, float* g_cov3d, void* stream) {
+  if (!g || !cam) return fail(RTGS_ERR_INVALID_ARG, "null gaussians or camera");
+  rtgs_session s = single(g, cam, pixel_mask);
+  s.final_T = const_cast<float*>(final_T);
+  s.last_idx = const_cast<int32_t*>(last_idx);
+  s.dL_dcolor = dL_dcolor;
+  s.dL_ddepth = dL_ddepth;
+  s.dL_dalpha = dL_dalpha;
+  s.g_means = g_means;
+  s.g_log_scales = g_log_scales;
+  s.g_quats = g_quats;
+  s.g_opacity_logits = g_opacity_logits;
+  s.g_colors = g_colors;
+  s.g_pose6 = g_pose6;
+  s.g_cov3d = g_cov3d;
+  return render_bwd_batched(h, &s, 1, ws, ws_bytes, cap, grad_flags, stream);
+}
+
+int32_t prune_by_grad(rtgs_handle_t h, const float* g_means, const float* g_cov3d,
+                      const uint8_t* visible, const uint8_t* mask_in, int32_t n, float lambda,
+                      float max_ratio, uint8_t* mask_out, int32_t* n_masked_dev,
+                      float* score_out, void* stream) {
+  if (!h) return fail(RTGS_ERR_INVALID_ARG, "null handle");
+  if (n < 0) return fail(RTGS_ERR_INVALID_ARG, "n = %d < 0", n);
+  if (n > 0 && (!g_means || !g_cov3d || !mask_out))
+    return fail(RTGS_ERR_INVALID_ARG, "null gradient or mask_out");
+  if (!(max_ratio >= 0.f && max_ratio <= 0.5f))
+    return fail(RTGS_ERR_INVALID_ARG, "max_ratio %g outside [0, 0.5]", (double)max_ratio);
+  if (!std::isfinite(lambda) || lambda < 0.f)
+    return fail(RTGS_ERR_INVALID_ARG, "lambda %g must be finite and >= 0", (double)lambda);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_prune(g_means, g_cov3d, visible, mask_in, n, lambda, max_ratio, mask_out,
+                              n_masked_dev, score_out, h->d_prune, st);
+  if (e != hipSuccess) return hip_fail(e, "prune_by_grad launch");
+  return RTGS_OK;
+}
+
+int32_t downsample_mask(const float* final_T, int32_t width, int32_t height, int32_t log2_ratio,
+                        uint8_t* mask_out, int32_t* n_active_dev, void* stream) {
+  if (!final_T || !mask_out) return fail(RTGS_ERR_INVALID_ARG, "null final_T or mask_out");
+  if (width <= 0 || height <= 0)
+    return fail(RTGS_ERR_INVALID_ARG, "image %d x %d", width, height);
+  if (log2_ratio < 0 || log2_ratio > 8)
+    return fail(RTGS_ERR_INVALID_ARG, "log2_ratio %d outside [0, 8]", log2_ratio);
+  hipError_t e = launch_downsample(final_T, width, height, log2_ratio, mask_out, n_active_dev,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "downsample_mask launch");
+  return RTGS_OK;
+}
+
+int32_t rtgs_downsample_log2_ratio(int32_t is_keyframe, int32_t n, int32_t k, int32_t m) {
+  if (is_keyframe) return 0;
+  if (n <= k || m < 2)
+    return fail(RTGS_ERR_INVALID_ARG, "non-keyframe needs n > k and m >= 2");
+  const double steps = (double)(n - k - 1) * std::log2((double)m);
+  const int j = 4 - (int)std::floor(steps + 1e-12);
+  return j < 2 ? 2 : j;
+}
+
+int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed, int32_t* state) {
+  if (!h) return fail(RTGS_ERR_INVALID_ARG, "null handle");
+  if (state) *state = RTGS_STATE_IDLE;
+  if (!h->used) {
+    if (pairs_needed) *pairs_needed = 0;
+    return RTGS_OK;
+  }
+  hipStream_t st = h->last_stream;
+  if (!blocking) {
+    hipError_t q = hipStreamQuery(st);
+    if (q == hipErrorNotReady) {
+      if (state) *state = RTGS_STATE_EXECUTING;
+      return RTGS_OK;
+    }
+    if (q != hipSuccess) return hip_fail(q, "hipStreamQuery");
+  }
+  unsigned long long got = 0, zero = 0;
+  hipError_t e = hipMemcpyAsync(&got, h->d_scalars, sizeof(got), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->d_scalars, &zero, sizeof(zero), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "rtgs_query");
+  if (pairs_needed) *pairs_needed = (int64_t)got;
+  const int64_t cap = h->min_cap;
+  h->min_cap = INT64_MAX;
+  if ((int64_t)got > cap)
+    return fail(RTGS_ERR_CAPACITY, "a render needed %llu pairs, capacity %lld",
+                (unsigned long long)got, (long long)cap);
+  return RTGS_OK;
+}
+
+int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width, const int32_t* height,
+                         int32_t n_sessions, int64_t pair_capacity, const void* ws,
+                         uint64_t ws_bytes, float* stage, int32_t* rect, int32_t* ranges,
+                         int32_t* ids, int64_t ids_capacity, void* stream) {
+  if (!n || !width || !height || !ws) return fail(RTGS_ERR_INVALID_ARG, "null argument");
+  int32_t r = check_cap(pair_capacity);
+  if (r) return r;
+  Geometry g;
+  r = geometry(n, width, height, n_sessions, g);
+  if (r) return r;
+  const WsLayout L = make_layout(g.n_total, g.t_total, g.b_total, pair_capacity, g.px_total);
+  if (ws_bytes < L.total) return fail(RTGS_ERR_WORKSPACE, "workspace too small");
+  const WsPtrs w = ws_ptrs(const_cast<void*>(ws), L);
+  Batch B{};
+  B.n_total = (int32_t)g.n_total;
+  B.t_total = (int32_t)g.t_total;
+  hipError_t e = launch_debug_stage(B, w, stage, rect, ranges, ids, ids_capacity,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rtgs_debug_stage launch");
+  return RTGS_OK;
+}
+
+int32_t rtgs_selftest_wave_sum(const float* in, float* out, int32_t n_waves, void* stream) {
+  if (n_waves < 0 || (n_waves > 0 && (!in || !out)))
+    return fail(RTGS_ERR_INVALID_ARG, "bad arguments");
+  hipError_t e = launch_wave_sum_test(in, out, n_waves, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "wave sum launch");
+  return RTGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,322 @@
+// Steps 1 and 2 of the forward pass (Sec. 2.1): projection of every Gaussian
+// (Step 1-1), tile intersection (Step 1-2) and per-tile depth sorting
+// (Step 2), for a batch of sessions sharing one tile space.
+//
+// Design for gfx950:
+//  * projection runs one thread per Gaussian in float64: it is HBM bound
+//    (56 B in, 64 B out per Gaussian), and float64 lets the raster kernels see
+//    pixel-space centres split as hi + lo float32 parts, so their float32
+//    compositing matches the float64 definition far below 1e-4;
+//  * binning is a counting sort by tile: atomics count pairs per tile, one
+//    scan turns counts into tile ranges, a second pass scatters
+//    (depth bits, id) keys into the ranges, then one workgroup per tile sorts
+//    its range in LDS (bitonic network on 64-bit keys; ranges beyond the LDS
+//    capacity sort in place in global memory).  No host sync is needed: the
+//    pair total stays on the device and a capacity overflow only drops pairs.
+#include "rtgs_internal.h"
+
+namespace rtgs {
+namespace {
+
+constexpr int kSortLds = 4096;    // 64-bit keys sorted in LDS per tile (32 KB)
+constexpr int kScanThreads = 1024;
+
+__global__ void k_init(uint32_t* tile_count, int t_total, long long* counters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= t_total) tile_count[i] = 0u;
+  if (i < 8) counters[i] = 0;
+}
+
+struct Proj {
+  double u, v, z, sxx, sxy, syy;
+  bool ok;
+};
+
+// Step 1-1 for one Gaussian in float64 (EWA, first order).
+__device__ __forceinline__ void project_one(const SessionDev& S, const float* vm, int li,
+                                            double& o, Proj& P) {
+  const double mx = S.means[3 * li + 0], my = S.means[3 * li + 1], mz = S.means[3 * li + 2];
+  const double qw = S.quats[4 * li + 0], qx = S.quats[4 * li + 1];
+  const double qy = S.quats[4 * li + 2], qz = S.quats[4 * li + 3];
+  const double s0 = exp((double)S.log_scales[3 * li + 0]);
+  const double s1 = exp((double)S.log_scales[3 * li + 1]);
+  const double s2 = exp((double)S.log_scales[3 * li + 2]);
+  o = 1.0 / (1.0 + exp(-(double)S.opac[li]));
+  P.ok = false;
+  // camera-space centre p = R_c mu + t_c
+  const double x = vm[0] * mx + vm[1] * my + vm[2] * mz + vm[3];
+  const double y = vm[4] * mx + vm[5] * my + vm[6] * mz + vm[7];
+  const double z = vm[8] * mx + vm[9] * my + vm[10] * mz + vm[11];
+  P.z = z;
+  if (!(z > kNearZ) || !(255.0 * o >= 1.0)) return;
+  if (S.gmask && S.gmask[li]) return;
+  // rotation of the normalised quaternion (w, x, y, z)
+  const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw * qn, a = qx * qn, b = qy * qn, c = qz * qn;
+  double R[9] = {1 - 2 * (b * b + c * c), 2 * (a * b - w * c), 2 * (a * c + w * b),
+                 2 * (a * b + w * c), 1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
+                 2 * (a * c - w * b), 2 * (b * c + w * a), 1 - 2 * (a * a + b * b)};
+  // M = R diag(s); Sigma = M M^T
+  const double ss[3] = {s0, s1, s2};
+  double M[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) M[3 * r + k] = R[3 * r + k] * ss[k];
+  // EWA Jacobian with the field-of-view clamp
+  const double limx = kFovClamp * 0.5 * S.width / S.fx;
+  const double limy = kFovClamp * 0.5 * S.height / S.fy;
+  const double rx = x / z, ry = y / z;
+  const double tx = fmin(limx, fmax(-limx, rx));
+  const double ty = fmin(limy, fmax(-limy, ry));
+  const double j00 = S.fx / z, j02 = -S.fx * tx / z;
+  const double j11 = S.fy / z, j12 = -S.fy * ty / z;
+  // T = J W (2x3), W = R_c
+  double T0[3], T1[3];
+  for (int k = 0; k < 3; ++k) {
+    T0[k] = j00 * vm[0 + k] + j02 * vm[8 + k];
+    T1[k] = j11 * vm[4 + k] + j12 * vm[8 + k];
+  }
+  // A = T M (2x3); Sigma' = A A^T + dilation
+  double A0[3], A1[3];
+  for (int k = 0; k < 3; ++k) {
+    A0[k] = T0[0] * M[0 + k] + T0[1] * M[3 + k] + T0[2] * M[6 + k];
+    A1[k] = T1[0] * M[0 + k] + T1[1] * M[3 + k] + T1[2] * M[6 + k];
+  }
+  P.sxx = A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2] + kDilation;
+  P.sxy = A0[0] * A1[0] + A0[1] * A1[1] + A0[2] * A1[2];
+  P.syy = A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2] + kDilation;
+  P.u = S.fx * rx + S.cx;
+  P.v = S.fy * ry + S.cy;
+  const double det = P.sxx * P.syy - P.sxy * P.sxy;
+  P.ok = det > 0.0;
+}
+
+__device__ __forceinline__ void split(double x, float& hi, float& lo) {
+  hi = (float)x;
+  lo = (float)(x - (double)hi);
+}
+
+// Step 1-1 + the tile rectangle of Step 1-2 + per-tile pair counts.
+__global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W) {
+  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                             [](const SessionDev& x) { return x.block_base; });
+  const SessionDev& S = B.sess[s];
+  const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
+  if (li >= S.n) return;
+  const int gid = S.gauss_base + li;
+  float vm[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) vm[k] = S.viewmat[k];
+  double o;
+  Proj P;
+  project_one(S, vm, li, o, P);
+  int4 rect = make_int4(0, 0, -1, -1);
+  if (P.ok) {
+    const double det = P.sxx * P.syy - P.sxy * P.sxy;
+    const double inv = 1.0 / det;
+    float uh, ul, vh, vl;
+    split(P.u, uh, ul);
+    split(P.v, vh, vl);
+    const float zf = (float)P.z;
+    W.rec0[gid] = make_float4(uh, vh, ul, vl);
+    W.rec1[gid] = make_float4((float)(P.syy * inv), (float)(-P.sxy * inv), (float)(P.sxx * inv),
+                              (float)o);
+    W.rec2[gid] = make_float4(S.colors[3 * li + 0], S.colors[3 * li + 1], S.colors[3 * li + 2], zf);
+    // bounding box of the alpha = 1/255 ellipse: d^T M d <= 2 ln(255 o)
+    const double t = 2.0 * log(255.0 * o);
+    const float ex = (float)sqrt(t * P.sxx);
+    const float ey = (float)sqrt(t * P.syy);
+    W.ext[gid] = make_float4(ex, ey, 0.f, 0.f);
+    // padded pixel range in float32, fixed operation order (see the replay)
+    const float lox = floorf((uh - ex) - 1.5f), hix = ceilf((uh + ex) + 0.5f);
+    const float loy = floorf((vh - ey) - 1.5f), hiy = ceilf((vh + ey) + 0.5f);
+    if (!(hix < 0.f || lox > (float)(S.width - 1) || hiy < 0.f || loy > (float)(S.height - 1))) {
+      const int i0 = (int)fmaxf(lox, 0.f), i1 = (int)fminf(hix, (float)(S.width - 1));
+      const int j0 = (int)fmaxf(loy, 0.f), j1 = (int)fminf(hiy, (float)(S.height - 1));
+      rect = make_int4(i0 / kTile, j0 / kTile, i1 / kTile, j1 / kTile);
+    }
+  } else {
+    W.rec0[gid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    W.rec1[gid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    W.rec2[gid] = make_float4(0.f, 0.f, 0.f, (float)P.z);
+    W.ext[gid] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  W.rect[gid] = rect;
+  const bool vis = rect.z >= rect.x;
+  if (S.visible) S.visible[li] = vis ? 1 : 0;
+  if (!vis) return;
+  uint32_t* cnt = W.tile_count + S.tile_base;
+  for (int ty = rect.y; ty <= rect.w; ++ty)
+    for (int tx = rect.x; tx <= rect.z; ++tx) atomicAdd(&cnt[ty * S.tiles_x + tx], 1u);
+}
+
+// Exclusive scan of the per-tile counts into tile_start[0..T]; resets the
+// scatter cursors; publishes the pair total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_total,
+                                                             unsigned long long* max_pairs) {
+  __shared__ uint32_t part[kScanThreads];
+  const int tid = threadIdx.x;
+  const int per = (t_total + kScanThreads - 1) / kScanThreads;
+  const int beg = min(tid * per, t_total), end = min(beg + per, t_total);
+  uint32_t sum = 0;
+  for (int i = beg; i < end; ++i) sum += W.tile_count[i];
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t add = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - sum;    // exclusive prefix of this thread's range
+  for (int i = beg; i < end; ++i) {
+    W.tile_start[i] = run;
+    run += W.tile_count[i];
+    W.tile_cursor[i] = 0u;
+  }
+  if (tid == kScanThreads - 1) {
+    const uint32_t total = part[tid];
+    W.tile_start[t_total] = total;
+    W.counters[0] = (long long)total;
+    atomicMax(max_pairs, (unsigned long long)total);
+  }
+}
+
+// Scatter (depth bits << 32 | id) keys into each tile's range.
+__global__ __launch_bounds__(kGaussPerBlock) void k_emit(Batch B, WsPtrs W) {
+  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                             [](const SessionDev& x) { return x.block_base; });
+  const SessionDev& S = B.sess[s];
+  const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
+  if (li >= S.n) return;
+  const int gid = S.gauss_base + li;
+  const int4 rect = W.rect[gid];
+  if (rect.z < rect.x) return;
+  const unsigned long long key =
+      ((unsigned long long)__float_as_uint(W.rec2[gid].w) << 32) | (unsigned)gid;
+  const int tb = S.tile_base;
+  for (int ty = rect.y; ty <= rect.w; ++ty)
+    for (int tx = rect.x; tx <= rect.z; ++tx) {
+      const int t = tb + ty * S.tiles_x + tx;
+      const uint32_t pos = W.tile_start[t] + atomicAdd(&W.tile_cursor[t], 1u);
+      if ((int64_t)pos < W.cap) W.keys[pos] = key;
+    }
+}
+
+// Bitonic sorting network on a[0..n) (ascending), all merges in the "flip"
+// form so that virtual +inf padding up to the next power of two never moves:
+// each compare-exchange puts the minimum at the lower index, hence a pair
+// whose upper index is >= n is left alone.
+template <typename P>
+__device__ void bitonic_sort(P a, int n) {
+  int npow = 1;
+  while (npow < n) npow <<= 1;
+  const int half = npow >> 1;
+  for (int k = 2; k <= npow; k <<= 1) {
+    const int hk = k >> 1;
+    for (int p = threadIdx.x; p < half; p += blockDim.x) {
+      const int r = p & (hk - 1);
+      const int i = (p / hk) * k + r;
+      const int j = i + k - 1 - 2 * r;
+      if (j < n) {
+        const unsigned long long x = a[i], y = a[j];
+        if (y < x) { a[i] = y; a[j] = x; }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int m = k >> 2; m >= 1; m >>= 1) {
+      for (int p = threadIdx.x; p < half; p += blockDim.x) {
+        const int i = (p / m) * 2 * m + (p & (m - 1));
+        const int j = i + m;
+        if (j < n) {
+          const unsigned long long x = a[i], y = a[j];
+          if (y < x) { a[i] = y; a[j] = x; }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
+}
+
+// One workgroup per tile: sort its keys, write the Gaussian ids in order.
+__global__ __launch_bounds__(kBlock) void k_sort_tiles(WsPtrs W) {
+  __shared__ unsigned long long sk[kSortLds];
+  const int t = blockIdx.x;
+  const int64_t cap = W.cap;
+  const int64_t st = min((int64_t)W.tile_start[t], cap);
+  const int64_t en = min((int64_t)W.tile_start[t + 1], cap);
+  const int n = (int)(en - st);
+  if (n <= 0) return;
+  if (n <= kSortLds) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sk[i] = W.keys[st + i];
+    __syncthreads();
+    bitonic_sort(sk, n);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) W.ids[st + i] = (uint32_t)sk[i];
+  } else {
+    unsigned long long* g = W.keys + st;
+    bitonic_sort(g, n);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) W.ids[st + i] = (uint32_t)g[i];
+  }
+}
+
+__global__ void k_debug_stage(Batch B, WsPtrs W, float* stage, int* rect, int* ranges, int* ids,
+                              int64_t ids_cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B.n_total) {
+    if (stage) {
+      const float4 r0 = W.rec0[i], r1 = W.rec1[i], r2 = W.rec2[i], e = W.ext[i];
+      float* o = stage + 12 * (int64_t)i;
+      o[0] = r0.x; o[1] = r0.y; o[2] = r1.x; o[3] = r1.y; o[4] = r1.z; o[5] = r1.w;
+      o[6] = r2.w; o[7] = e.x; o[8] = e.y; o[9] = r2.x; o[10] = r2.y; o[11] = r2.z;
+    }
+    if (rect) {
+      const int4 r = W.rect[i];
+      rect[4 * i + 0] = r.x; rect[4 * i + 1] = r.y; rect[4 * i + 2] = r.z; rect[4 * i + 3] = r.w;
+    }
+  }
+  if (i < B.t_total && ranges) {
+    ranges[2 * i] = (int)min((int64_t)W.tile_start[i], W.cap);
+    ranges[2 * i + 1] = (int)min((int64_t)W.tile_start[i + 1], W.cap);
+  }
+  if (ids) {
+    const int64_t total = min((int64_t)W.tile_start[B.t_total], min(W.cap, ids_cap));
+    for (int64_t k = i; k < total; k += (int64_t)gridDim.x * blockDim.x) ids[k] = (int)W.ids[k];
+  }
+}
+
+__global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
+  const int w = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (w >= n_waves) return;     // whole waves exit together
+  const float v = wave_sum_to_lane63(in[64 * w + (threadIdx.x & 63)]);
+  if ((threadIdx.x & 63) == 63) out[w] = v;
+}
+
+}  // namespace
+
+hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
+                               hipStream_t st) {
+  const int tn = b.t_total + 1;
+  k_init<<<(tn + 255) / 256, 256, 0, st>>>(w.tile_count, b.t_total, w.counters);
+  if (b.b_total > 0) k_preprocess<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+  k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, max_pairs);
+  if (b.b_total > 0) k_emit<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+  if (b.t_total > 0) k_sort_tiles<<<b.t_total, kBlock, 0, st>>>(w);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_stage(const Batch& b, const WsPtrs& w, float* stage, int* rect,
+                              int* ranges, int* ids, int64_t ids_cap, hipStream_t st) {
+  const int n = b.n_total > b.t_total ? b.n_total : b.t_total;
+  const int grid = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
+  k_debug_stage<<<grid, 256, 0, st>>>(b, w, stage, rect, ranges, ids, ids_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_wave_sum_test(const float* in, float* out, int n_waves, hipStream_t st) {
+  if (n_waves <= 0) return hipSuccess;
+  k_wave_sum_test<<<(n_waves + 3) / 4, 256, 0, st>>>(in, out, n_waves);
+  return hipGetLastError();
+}
+
+}  // namespace rtgs

@@ -1,0 +1,217 @@
+// Step 5, preprocessing backpropagation (Sec. 2.2): the per-Gaussian 2D
+// gradients merged by the raster backward are pushed through the EWA
+// projection to the map parameters, and in tracking summed over Gaussians to
+// the camera-pose gradient dL/dP (the paper's Preprocessing Engine and
+// Merging Tree, Secs. 5.1 and 5.4).
+//
+// One thread per Gaussian in float64 (HBM bound: ~48 B of 2D gradient and
+// 56 B of parameters in, up to 80 B out).  The pose partials are summed per
+// workgroup in LDS, then per session in a fixed order by a second kernel, so
+// the pose reduction adds no float atomics of its own.
+//
+// Chain (all derivatives exact for the forward of forward_prep.hip):
+//   conic (a, b, c) -> Sigma' :  dL/dSigma' = -M G_M M,  G_M = [[ga, gb/2],
+//                                [gb/2, gc]]
+//   Sigma' = A A^T + 0.3 I, A = T M, T = J W, M = R diag(s):
+//     dL/dA = 2 G' A,  dL/dM = T^T dL/dA,  dL/dT = dL/dA M^T
+//   T = J W:  dL/dJ = dL/dT W^T,  dL/dW|cov = J^T dL/dT
+//   J(p), u(p), v(p), z: dL/dp;  dL/dmu = W^T dL/dp
+//   pose (left perturbation at xi = 0): dL/drho = dL/dp,
+//     dL/dphi = p x dL/dp + vee(W (dL/dW)^T)
+//   M -> scales (dL/dl = s dL/ds) and R(q/|q|) -> quaternion.
+#include "rtgs_internal.h"
+
+namespace rtgs {
+namespace {
+
+__global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPtrs W, int flags) {
+  __shared__ double s_red[kGaussPerBlock / 64][6];
+  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                             [](const SessionDev& x) { return x.block_base; });
+  const SessionDev& S = B.sess[s];
+  const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
+  const bool want_map = (flags & RTGS_GRAD_MAP) != 0;
+  const bool want_cov = (flags & RTGS_GRAD_COV3D) != 0 && S.g_cov3d != nullptr;
+  double pose[6] = {0, 0, 0, 0, 0, 0};
+  if (li < S.n) {
+    const int gid = S.gauss_base + li;
+    const int4 rect = W.rect[gid];
+    double gm[3] = {0, 0, 0}, gl[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go_eta = 0;
+    double gcol[3] = {0, 0, 0}, gsig[6] = {0, 0, 0, 0, 0, 0};
+    if (rect.z >= rect.x) {
+      const float* g2 = W.grad2d + (int64_t)gid * kGrad2dStride;
+      const double gu = g2[0], gv = g2[1], ga = g2[2], gb = g2[3], gc = g2[4], go = g2[5];
+      gcol[0] = g2[6]; gcol[1] = g2[7]; gcol[2] = g2[8];
+      const double gdep = g2[9];
+      double vm[12];
+      for (int k = 0; k < 12; ++k) vm[k] = S.viewmat[k];
+      const double mx = S.means[3 * li], my = S.means[3 * li + 1], mz = S.means[3 * li + 2];
+      const double qw = S.quats[4 * li], qx = S.quats[4 * li + 1];
+      const double qy = S.quats[4 * li + 2], qz = S.quats[4 * li + 3];
+      const double sc[3] = {exp((double)S.log_scales[3 * li]), exp((double)S.log_scales[3 * li + 1]),
+                            exp((double)S.log_scales[3 * li + 2])};
+      const double o = 1.0 / (1.0 + exp(-(double)S.opac[li]));
+      const double x = vm[0] * mx + vm[1] * my + vm[2] * mz + vm[3];
+      const double y = vm[4] * mx + vm[5] * my + vm[6] * mz + vm[7];
+      const double z = vm[8] * mx + vm[9] * my + vm[10] * mz + vm[11];
+      const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+      const double w = qw / qn, a = qx / qn, b = qy / qn, c = qz / qn;
+      const double R[9] = {1 - 2 * (b * b + c * c), 2 * (a * b - w * c), 2 * (a * c + w * b),
+                           2 * (a * b + w * c), 1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
+                           2 * (a * c - w * b), 2 * (b * c + w * a), 1 - 2 * (a * a + b * b)};
+      double M[9];
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) M[3 * r + k] = R[3 * r + k] * sc[k];
+      const double limx = kFovClamp * 0.5 * S.width / S.fx;
+      const double limy = kFovClamp * 0.5 * S.height / S.fy;
+      const double rx = x / z, ry = y / z;
+      const bool inx = rx > -limx && rx < limx, iny = ry > -limy && ry < limy;
+      const double tx = fmin(limx, fmax(-limx, rx)), ty = fmin(limy, fmax(-limy, ry));
+      const double j00 = S.fx / z, j02 = -S.fx * tx / z, j11 = S.fy / z, j12 = -S.fy * ty / z;
+      double T0[3], T1[3], A0[3], A1[3];
+      for (int k = 0; k < 3; ++k) {
+        T0[k] = j00 * vm[k] + j02 * vm[8 + k];
+        T1[k] = j11 * vm[4 + k] + j12 * vm[8 + k];
+      }
+      for (int k = 0; k < 3; ++k) {
+        A0[k] = T0[0] * M[k] + T0[1] * M[3 + k] + T0[2] * M[6 + k];
+        A1[k] = T1[0] * M[k] + T1[1] * M[3 + k] + T1[2] * M[6 + k];
+      }
+      const double sxx = A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2] + kDilation;
+      const double sxy = A0[0] * A1[0] + A0[1] * A1[1] + A0[2] * A1[2];
+      const double syy = A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2] + kDilation;
+      const double inv = 1.0 / (sxx * syy - sxy * sxy);
+      const double ca = syy * inv, cb = -sxy * inv, cc = sxx * inv;
+      // dL/dSigma' (symmetric matrix entries)
+      const double Gxx = -(ga * ca * ca + gb * ca * cb + gc * cb * cb);
+      const double Gyy = -(ga * cb * cb + gb * cb * cc + gc * cc * cc);
+      const double Gxy = -(ga * ca * cb + 0.5 * gb * (ca * cc + cb * cb) + gc * cb * cc);
+      double dA0[3], dA1[3], dM[9], dT0[3], dT1[3];
+      for (int k = 0; k < 3; ++k) {
+        dA0[k] = 2.0 * (Gxx * A0[k] + Gxy * A1[k]);
+        dA1[k] = 2.0 * (Gxy * A0[k] + Gyy * A1[k]);
+      }
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) dM[3 * r + k] = T0[r] * dA0[k] + T1[r] * dA1[k];
+      for (int r = 0; r < 3; ++r) {
+        dT0[r] = dA0[0] * M[3 * r] + dA0[1] * M[3 * r + 1] + dA0[2] * M[3 * r + 2];
+        dT1[r] = dA1[0] * M[3 * r] + dA1[1] * M[3 * r + 1] + dA1[2] * M[3 * r + 2];
+      }
+      // T0 = j00 W0 + j02 W2, T1 = j11 W1 + j12 W2 (W rows)
+      const double dj00 = dT0[0] * vm[0] + dT0[1] * vm[1] + dT0[2] * vm[2];
+      const double dj02 = dT0[0] * vm[8] + dT0[1] * vm[9] + dT0[2] * vm[10];
+      const double dj11 = dT1[0] * vm[4] + dT1[1] * vm[5] + dT1[2] * vm[6];
+      const double dj12 = dT1[0] * vm[8] + dT1[1] * vm[9] + dT1[2] * vm[10];
+      double dW[9];
+      for (int k = 0; k < 3; ++k) {
+        dW[k] = j00 * dT0[k];
+        dW[3 + k] = j11 * dT1[k];
+        dW[6 + k] = j02 * dT0[k] + j12 * dT1[k];
+      }
+      // dL/dp from u, v, J and the depth output
+      const double z2 = z * z, z3 = z2 * z;
+      double gx = gu * S.fx / z + (inx ? dj02 * (-S.fx / z2) : 0.0);
+      double gy = gv * S.fy / z + (iny ? dj12 * (-S.fy / z2) : 0.0);
+      const double dj02dz = S.fx * tx / z2 + (inx ? S.fx * x / z3 : 0.0);
+      const double dj12dz = S.fy * ty / z2 + (iny ? S.fy * y / z3 : 0.0);
+      double gz = gdep - gu * S.fx * x / z2 - gv * S.fy * y / z2 - dj00 * S.fx / z2 -
+                  dj11 * S.fy / z2 + dj02 * dj02dz + dj12 * dj12dz;
+      // pose: rho = dL/dp; phi = p x dL/dp + vee(W dW^T)
+      pose[0] = gx; pose[1] = gy; pose[2] = gz;
+      double Bm[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          Bm[3 * i + j] = vm[4 * i] * dW[3 * j] + vm[4 * i + 1] * dW[3 * j + 1] +
+                          vm[4 * i + 2] * dW[3 * j + 2];
+      pose[3] = y * gz - z * gy + (Bm[5] - Bm[7]);
+      pose[4] = z * gx - x * gz + (Bm[6] - Bm[2]);
+      pose[5] = x * gy - y * gx + (Bm[1] - Bm[3]);
+      if (want_map) {
+        // dL/dmu = W^T dL/dp
+        for (int k = 0; k < 3; ++k) gm[k] = vm[k] * gx + vm[4 + k] * gy + vm[8 + k] * gz;
+        // M = R diag(s): dR[r][k] = dM[r][k] s_k, ds_k = sum_r R[r][k] dM[r][k]
+        double dR[9];
+        for (int r = 0; r < 3; ++r)
+          for (int k = 0; k < 3; ++k) dR[3 * r + k] = dM[3 * r + k] * sc[k];
+        for (int k = 0; k < 3; ++k)
+          gl[k] = sc[k] * (R[k] * dM[k] + R[3 + k] * dM[3 + k] + R[6 + k] * dM[6 + k]);
+        // R(w, a, b, c) -> unit-quaternion gradient
+        const double gw = 2 * (-c * dR[1] + b * dR[2] + c * dR[3] - a * dR[5] - b * dR[6] + a * dR[7]);
+        const double gx4 = 2 * (b * dR[1] + c * dR[2] + b * dR[3] - 2 * a * dR[4] - w * dR[5] +
+                                c * dR[6] + w * dR[7] - 2 * a * dR[8]);
+        const double gy4 = 2 * (-2 * b * dR[0] + a * dR[1] + w * dR[2] + a * dR[3] + c * dR[5] -
+                                w * dR[6] + c * dR[7] - 2 * b * dR[8]);
+        const double gz4 = 2 * (-2 * c * dR[0] - w * dR[1] + a * dR[2] + w * dR[3] - 2 * c * dR[4] +
+                                b * dR[5] + a * dR[6] + b * dR[7]);
+        const double dot = w * gw + a * gx4 + b * gy4 + c * gz4;
+        gq[0] = (gw - w * dot) / qn;
+        gq[1] = (gx4 - a * dot) / qn;
+        gq[2] = (gy4 - b * dot) / qn;
+        gq[3] = (gz4 - c * dot) / qn;
+        go_eta = go * o * (1.0 - o);
+        if (want_cov) {
+          // dL/dSigma = T^T G' T
+          double GT0[3], GT1[3];
+          for (int k = 0; k < 3; ++k) {
+            GT0[k] = Gxx * T0[k] + Gxy * T1[k];
+            GT1[k] = Gxy * T0[k] + Gyy * T1[k];
+          }
+          const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
+          for (int k = 0; k < 6; ++k) gsig[k] = T0[ii[k]] * GT0[jj[k]] + T1[ii[k]] * GT1[jj[k]];
+        }
+      }
+    }
+    if (want_map) {
+      if (S.g_means) for (int k = 0; k < 3; ++k) S.g_means[3 * li + k] = (float)gm[k];
+      if (S.g_log_scales) for (int k = 0; k < 3; ++k) S.g_log_scales[3 * li + k] = (float)gl[k];
+      if (S.g_quats) for (int k = 0; k < 4; ++k) S.g_quats[4 * li + k] = (float)gq[k];
+      if (S.g_opac) S.g_opac[li] = (float)go_eta;
+      if (S.g_colors) for (int k = 0; k < 3; ++k) S.g_colors[3 * li + k] = (float)gcol[k];
+      if (want_cov) for (int k = 0; k < 6; ++k) S.g_cov3d[6 * li + k] = (float)gsig[k];
+    }
+  }
+  // block partial of the pose gradient: wave shuffles, then the 4 waves in LDS
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k < 6; ++k) {
+    double v = pose[k];
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) s_red[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0;
+    for (int q = 0; q < kGaussPerBlock / 64; ++q) t += s_red[q][threadIdx.x];
+    W.pose_part[(int64_t)blockIdx.x * 8 + threadIdx.x] = t;
+  }
+}
+
+// One workgroup per session: fixed-order sum of its block partials.
+__global__ __launch_bounds__(256) void k_pose_reduce(Batch B, WsPtrs W) {
+  __shared__ double s_acc[256][6];
+  const SessionDev& S = B.sess[blockIdx.x];
+  const int b0 = S.block_base;
+  const int b1 = (blockIdx.x + 1 < (unsigned)B.n_sessions) ? B.sess[blockIdx.x + 1].block_base
+                                                           : B.b_total;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += 256)
+    for (int k = 0; k < 6; ++k) acc[k] += W.pose_part[(int64_t)b * 8 + k];
+  for (int k = 0; k < 6; ++k) s_acc[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int k = 0; k < 6; ++k) s_acc[threadIdx.x][k] += s_acc[threadIdx.x + off][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6 && S.g_pose6) S.g_pose6[threadIdx.x] = (float)s_acc[0][threadIdx.x];
+}
+
+}  // namespace
+
+hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st) {
+  if (b.b_total > 0) k_preprocess_bwd<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+  if ((grad_flags & RTGS_GRAD_POSE) && b.n_sessions > 0)
+    k_pose_reduce<<<b.n_sessions, 256, 0, st>>>(b, w);
+  return hipGetLastError();
+}
+
+}  // namespace rtgs

@@ -1,0 +1,276 @@
+// Step 3 (rendering: alpha computing, Eq. 2, and alpha blending, Eq. 3) and
+// Step 4 (rendering backpropagation, the exact derivative of Eq. 3 that
+// Eqs. 4-5 sketch) for a batch of sessions sharing one tile space.
+//
+// One workgroup per 16x16 tile, 256 lanes = 4 wave64; each wave owns an 8x8
+// quadrant, so a Gaussian whose padded bounding box misses a quadrant is
+// skipped by that whole wave (a wave-uniform branch; the GPU counterpart of
+// the paper's 4x4 subtiles).  Gaussian records of the tile's depth-sorted
+// list are staged through LDS in batches of 256.
+//
+// Forward: per lane, alpha = min(0.99, o exp(power)); skip alpha < 1/255;
+// stop before T would fall below 1e-4; saves final T and the position of the
+// last blended pair (the per-pixel state the backward reuses instead of
+// re-running the forward, the role of the paper's R&B buffer, Sec. 5.2).
+//
+// Backward: walks the list from the block's largest saved position down,
+// recovering T before each blended fragment as T / (1 - alpha) (Eq. 5 read
+// as the reverse recurrence) and the normalised suffix colour/depth; the
+// per-fragment 2D gradients of one list entry are summed over the wave with
+// DPP row shifts and broadcasts, and ten lanes then add the ten totals to the
+// Gaussian's accumulator with one global atomic instruction: the pixel ->
+// tile merge of the paper's Gradient Merging Unit (Sec. 5.3) done with
+// cross-lane operations.
+#include "rtgs_internal.h"
+
+namespace rtgs {
+namespace {
+
+__device__ __forceinline__ int tile_of_block(int t_total) {
+  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+  // band of tiles so neighbouring tiles share its L2.
+  const int per = (t_total + 7) >> 3;
+  return ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+}
+
+struct TileCtx {
+  int s;
+  int tile_x0, tile_y0;
+  int px, py;
+  bool inside;
+  int pix;
+  unsigned wbit;
+  int qx0, qy0;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile) {
+  TileCtx c;
+  c.s = find_session(B.sess, B.n_sessions, tile, [](const SessionDev& x) { return x.tile_base; });
+  const SessionDev& S = B.sess[c.s];
+  const int lt = tile - S.tile_base;
+  c.tile_x0 = (lt % S.tiles_x) * kTile;
+  c.tile_y0 = (lt / S.tiles_x) * kTile;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  c.qx0 = c.tile_x0 + (wave & 1) * 8;
+  c.qy0 = c.tile_y0 + (wave >> 1) * 8;
+  c.px = c.qx0 + (lane & 7);
+  c.py = c.qy0 + (lane >> 3);
+  c.inside = c.px < S.width && c.py < S.height;
+  c.pix = c.py * S.width + c.px;
+  c.wbit = 1u << wave;
+  return c;
+}
+
+// Bit w set when the padded bounding box of the alpha >= 1/255 ellipse meets
+// the 8x8 quadrant of wave w.
+__device__ __forceinline__ unsigned quad_mask(float4 r0, float4 ex, int tx0, int ty0) {
+  const float lox = floorf((r0.x - ex.x) - 1.5f), hix = ceilf((r0.x + ex.x) + 0.5f);
+  const float loy = floorf((r0.y - ex.y) - 1.5f), hiy = ceilf((r0.y + ex.y) + 0.5f);
+  unsigned m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const float qx = (float)(tx0 + (w & 1) * 8), qy = (float)(ty0 + (w >> 1) * 8);
+    const bool hit = hix >= qx && lox <= qx + 7.f && hiy >= qy && loy <= qy + 7.f;
+    m |= hit ? (1u << w) : 0u;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
+  __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock];
+  __shared__ unsigned s_m[kBlock];
+  const int tile = tile_of_block(B.t_total);
+  if (tile >= B.t_total) return;
+  const TileCtx c = tile_ctx(B, tile);
+  const SessionDev& S = B.sess[c.s];
+  const int tid = threadIdx.x;
+  const bool active = c.inside && (S.pmask == nullptr || S.pmask[c.pix] != 0);
+  const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
+  const int64_t start = min((int64_t)W.tile_start[tile], W.cap);
+  const int64_t end = min((int64_t)W.tile_start[tile + 1], W.cap);
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
+  int last = -1;
+  bool done = !active;
+  for (int64_t b0 = start; b0 < end; b0 += kBlock) {
+    if (__syncthreads_and(done)) break;
+    const int64_t e = b0 + tid;
+    if (e < end) {
+      const uint32_t g = W.ids[e];
+      const float4 r0 = W.rec0[g];
+      s_r0[tid] = r0;
+      s_r1[tid] = W.rec1[g];
+      s_r2[tid] = W.rec2[g];
+      s_m[tid] = quad_mask(r0, W.ext[g], c.tile_x0, c.tile_y0);
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kBlock, end - b0);
+    if (!done) {
+      for (int k = 0; k < cnt; ++k) {
+        if (!(s_m[k] & c.wbit)) continue;
+        const Frag f = frag_alpha(s_r0[k], s_r1[k], pxf, pyf);
+        if (f.alpha < kAlphaMin) continue;
+        const float tn = T * (1.f - f.alpha);
+        if (tn < kTMin) { done = true; break; }
+        const float w = f.alpha * T;
+        const float4 col = s_r2[k];
+        C0 = __builtin_fmaf(w, col.x, C0);
+        C1 = __builtin_fmaf(w, col.y, C1);
+        C2 = __builtin_fmaf(w, col.z, C2);
+        D = __builtin_fmaf(w, col.w, D);
+        T = tn;
+        last = (int)(b0 + k);
+      }
+    }
+    __syncthreads();
+  }
+  if (!c.inside) return;
+  const int64_t hw = (int64_t)S.width * S.height;
+  if (S.color) {
+    S.color[c.pix] = C0;
+    S.color[hw + c.pix] = C1;
+    S.color[2 * hw + c.pix] = C2;
+  }
+  if (S.depth) S.depth[c.pix] = D;
+  if (S.alpha) S.alpha[c.pix] = 1.f - T;
+  if (S.final_T) S.final_T[c.pix] = T;
+  if (S.last_idx) S.last_idx[c.pix] = last;
+}
+
+__global__ void k_zero(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// NV = 10 (all parameters) or 6 (pose only: u, v, a, b, c, z).
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
+  __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock];
+  __shared__ unsigned s_m[kBlock];
+  __shared__ uint32_t s_g[kBlock];
+  __shared__ int s_hi;
+  const int tile = tile_of_block(B.t_total);
+  if (tile >= B.t_total) return;
+  const TileCtx c = tile_ctx(B, tile);
+  const SessionDev& S = B.sess[c.s];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool active = c.inside && (S.pmask == nullptr || S.pmask[c.pix] != 0);
+  const int64_t hw = (int64_t)S.width * S.height;
+  int last = -1;
+  float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gD = 0.f, gA = 0.f;
+  if (active) {
+    last = S.last_idx[c.pix];
+    Tc = S.final_T[c.pix];
+    g0 = S.dl_color[c.pix];
+    g1 = S.dl_color[hw + c.pix];
+    g2 = S.dl_color[2 * hw + c.pix];
+    gD = S.dl_depth[c.pix];
+    if (S.dl_alpha) gA = S.dl_alpha[c.pix];
+  }
+  const float gAT = gA * Tc;        // dA/dalpha_j = T_final / (1 - alpha_j)
+  if (tid == 0) s_hi = -1;
+  __syncthreads();
+  if (last >= 0) atomicMax(&s_hi, last);
+  __syncthreads();
+  const int64_t start = min((int64_t)W.tile_start[tile], W.cap);
+  const int64_t end = min((int64_t)W.tile_start[tile + 1], W.cap);
+  // a saved position outside this tile's list (state of another forward) is
+  // never followed past the list
+  const int64_t hi = min((int64_t)s_hi, end - 1);
+  if (hi < start) return;
+  const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
+  float S0 = 0.f, S1 = 0.f, S2 = 0.f, Sz = 0.f;   // suffix sums normalised by T
+  for (int64_t bend = hi + 1; bend > start; bend -= kBlock) {
+    const int64_t b0 = bend - kBlock > start ? bend - kBlock : start;
+    const int cnt = (int)(bend - b0);
+    __syncthreads();
+    if (tid < cnt) {
+      const uint32_t g = W.ids[b0 + tid];
+      const float4 r0 = W.rec0[g];
+      s_r0[tid] = r0;
+      s_r1[tid] = W.rec1[g];
+      s_r2[tid] = W.rec2[g];
+      s_g[tid] = g;
+      s_m[tid] = quad_mask(r0, W.ext[g], c.tile_x0, c.tile_y0);
+    }
+    __syncthreads();
+    for (int k = cnt - 1; k >= 0; --k) {
+      if (!(s_m[k] & c.wbit)) continue;
+      float v[10];
+#pragma unroll
+      for (int i = 0; i < 10; ++i) v[i] = 0.f;
+      bool contrib = false;
+      if ((int64_t)b0 + k <= (int64_t)last) {
+        const float4 r1 = s_r1[k];
+        const Frag f = frag_alpha(s_r0[k], r1, pxf, pyf);
+        if (f.alpha >= kAlphaMin) {
+          contrib = true;
+          const float4 col = s_r2[k];
+          const float om = 1.f - f.alpha;
+          const float Tj = Tc / om;                     // T before this fragment
+          const float w = f.alpha * Tj;
+          float dla = (col.x - S0) * g0;
+          dla = __builtin_fmaf(col.y - S1, g1, dla);
+          dla = __builtin_fmaf(col.z - S2, g2, dla);
+          dla = __builtin_fmaf(col.w - Sz, gD, dla);
+          dla = __builtin_fmaf(Tj, dla, gAT / om);      // dL/dalpha
+          S0 = __builtin_fmaf(f.alpha, col.x, om * S0);
+          S1 = __builtin_fmaf(f.alpha, col.y, om * S1);
+          S2 = __builtin_fmaf(f.alpha, col.z, om * S2);
+          Sz = __builtin_fmaf(f.alpha, col.w, om * Sz);
+          Tc = Tj;
+          v[NV - 1] = w * gD;                           // depth slot (last)
+          if (NV == 10) {
+            v[6] = w * g0;
+            v[7] = w * g1;
+            v[8] = w * g2;
+          }
+          if (!(r1.w * f.e > kAlphaMax)) {              // not clamped
+            const float gp = f.alpha * dla;             // dL/dpower
+            if (NV == 10) v[5] = f.e * dla;              // dL/do
+            v[0] = -gp * __builtin_fmaf(r1.x, f.dx, r1.y * f.dy);
+            v[1] = -gp * __builtin_fmaf(r1.y, f.dx, r1.z * f.dy);
+            v[2] = -0.5f * gp * f.dx * f.dx;
+            v[3] = -gp * f.dx * f.dy;
+            v[4] = -0.5f * gp * f.dy * f.dy;
+          }
+        }
+      }
+      if (__ballot(contrib)) {
+        float tot[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) tot[i] = read_lane63(wave_sum_to_lane63(v[i]));
+        float mine = tot[0];
+#pragma unroll
+        for (int i = 1; i < NV; ++i) mine = lane == i ? tot[i] : mine;
+        if (lane < NV) {
+          // slots (u, v, a, b, c, o, r, g, b, z); pose only: v[5] is z -> slot 9
+          const int slot = (NV == 10 || lane < 5) ? lane : 9;
+          atomicAdd(&W.grad2d[(int64_t)s_g[k] * kGrad2dStride + slot], mine);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, int, hipStream_t st) {
+  if (b.t_total <= 0) return hipSuccess;
+  const int grid = 8 * ((b.t_total + 7) / 8);
+  k_raster_fwd<<<grid, kBlock, 0, st>>>(b, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st) {
+  const int64_t ng = (int64_t)b.n_total * kGrad2dStride;
+  if (ng > 0) k_zero<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(w.grad2d, ng);
+  if (b.t_total <= 0) return hipGetLastError();
+  const int grid = 8 * ((b.t_total + 7) / 8);
+  if (pose_only)
+    k_raster_bwd<6><<<grid, kBlock, 0, st>>>(b, w);
+  else
+    k_raster_bwd<10><<<grid, kBlock, 0, st>>>(b, w);
+  return hipGetLastError();
+}
+
+}  // namespace rtgs

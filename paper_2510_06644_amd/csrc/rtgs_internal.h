@@ -1,0 +1,212 @@
+// Internal declarations of librtgs: device-side session table, workspace
+// layout, launch wrappers and the device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rtgs.h"
+
+namespace rtgs {
+
+constexpr int kTile = 16;                 // tile edge in pixels (Sec. 2.1)
+constexpr int kBlock = 256;               // threads per workgroup
+constexpr int kGaussPerBlock = 256;       // Gaussians per block, per-Gaussian kernels
+constexpr float kAlphaMin = 1.0f / 255.0f;  // skip floor for a fragment
+constexpr float kAlphaMax = 0.99f;          // alpha clamp
+constexpr float kTMin = 1e-4f;              // early-termination transmittance
+constexpr double kNearZ = 0.2;
+constexpr double kDilation = 0.3;
+constexpr double kFovClamp = 1.3;
+constexpr int kGrad2dStride = 12;         // floats per Gaussian of 2D gradient
+
+// Device copy of one session (built on the host from rtgs_session).
+struct SessionDev {
+  // map
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opac;
+  const float* colors;
+  const uint8_t* gmask;
+  const float* viewmat;
+  const uint8_t* pmask;
+  // forward outputs
+  float* color;
+  float* depth;
+  float* alpha;
+  float* final_T;
+  int32_t* last_idx;
+  uint8_t* visible;
+  // backward
+  const float* dl_color;
+  const float* dl_depth;
+  const float* dl_alpha;
+  float* g_means;
+  float* g_log_scales;
+  float* g_quats;
+  float* g_opac;
+  float* g_colors;
+  float* g_pose6;
+  float* g_cov3d;
+  // geometry
+  int32_t n;
+  int32_t width;
+  int32_t height;
+  int32_t tiles_x;
+  int32_t tiles_y;
+  float fx, fy, cx, cy;
+  // offsets into the batch-global index spaces
+  int32_t gauss_base;   // first global Gaussian index
+  int32_t block_base;   // first per-Gaussian block
+  int32_t tile_base;    // first global tile
+  int32_t pad_;
+};
+
+// Offsets of the workspace regions (bytes from ws).
+struct WsLayout {
+  uint64_t table;       // SessionDev[RTGS_MAX_SESSIONS]
+  uint64_t counters;    // int64[8]: 0 pairs of this call
+  uint64_t rec0;        // float4[N]: u_hi, v_hi, u_lo, v_lo
+  uint64_t rec1;        // float4[N]: a, b, c, opacity
+  uint64_t rec2;        // float4[N]: r, g, b, z
+  uint64_t ext;         // float4[N]: e_x, e_y, -, -
+  uint64_t rect;        // int4[N]: tile rectangle
+  uint64_t grad2d;      // float[N][12]: dL/d(u, v, a, b, c, o, r, g, b, z)
+  uint64_t pose_part;   // double[B][8]: per-block pose partial sums
+  uint64_t tile_count;  // uint32[T + 1]
+  uint64_t tile_start;  // uint32[T + 1]
+  uint64_t tile_cursor; // uint32[T]
+  uint64_t keys;        // uint64[cap]
+  uint64_t ids;         // uint32[cap]
+  uint64_t state_t;     // float[pixels]: recomputed final T
+  uint64_t state_last;  // int32[pixels]: recomputed last position
+  uint64_t total;       // bytes
+  int64_t n_total;
+  int64_t t_total;
+  int64_t b_total;
+  int64_t cap;
+};
+
+WsLayout make_layout(int64_t n_total, int64_t t_total, int64_t b_total, int64_t cap,
+                     int64_t px_total);
+
+// Pointers derived from a workspace.
+struct WsPtrs {
+  SessionDev* table;
+  long long* counters;
+  float4* rec0;
+  float4* rec1;
+  float4* rec2;
+  float4* ext;
+  int4* rect;
+  float* grad2d;
+  double* pose_part;
+  uint32_t* tile_count;
+  uint32_t* tile_start;
+  uint32_t* tile_cursor;
+  unsigned long long* keys;
+  uint32_t* ids;
+  float* state_t;
+  int32_t* state_last;
+  int64_t cap;
+};
+
+WsPtrs ws_ptrs(void* ws, const WsLayout& L);
+
+// Batch geometry passed by value to every kernel.
+struct Batch {
+  const SessionDev* sess;
+  int32_t n_sessions;
+  int32_t n_total;      // Gaussians over all sessions
+  int32_t t_total;      // tiles over all sessions
+  int32_t b_total;      // per-Gaussian blocks over all sessions
+};
+
+// ---- launch wrappers (defined in the .hip files) ----
+hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
+                               hipStream_t st);
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, int save_state, hipStream_t st);
+hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int recompute, hipStream_t st);
+hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st);
+hipError_t launch_prune(const float* g_means, const float* g_cov3d, const uint8_t* visible,
+                        const uint8_t* mask_in, int n, float lambda, float ratio,
+                        uint8_t* mask_out, int* n_masked, float* score_out, uint32_t* scratch,
+                        hipStream_t st);
+hipError_t launch_downsample(const float* final_T, int w, int h, int j, uint8_t* mask_out,
+                             int* n_active, hipStream_t st);
+hipError_t launch_debug_stage(const Batch& b, const WsPtrs& w, float* stage, int* rect,
+                              int* ranges, int* ids, int64_t ids_cap, hipStream_t st);
+hipError_t launch_wave_sum_test(const float* in, float* out, int n_waves, hipStream_t st);
+
+constexpr int kPruneScratchWords = 4096;
+
+// ---- device helpers ----
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+
+// Session owning a block, by binary search over a monotone base field.
+template <typename F>
+__device__ __forceinline__ int find_session(const SessionDev* s, int n, int key, F base) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (base(s[mid]) <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// DPP control words (GFX9 encoding).
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, BOUND_ZERO));
+}
+
+// Sum over the 64 lanes of a wavefront; the total lands in lane 63 (other
+// lanes hold partial sums).  Inclusive row scans by shifted adds within each
+// 16-lane row, then the row totals are carried across rows by broadcasts.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_f<kDppRowShr1, 0xf, true>(v);
+  v += dpp_f<kDppRowShr2, 0xf, true>(v);
+  v += dpp_f<kDppRowShr4, 0xf, true>(v);
+  v += dpp_f<kDppRowShr8, 0xf, true>(v);
+  v += dpp_f<kDppRowBcast15, 0xa, false>(v);
+  v += dpp_f<kDppRowBcast31, 0xc, false>(v);
+  return v;
+}
+
+__device__ __forceinline__ float read_lane63(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Raster-side alpha of one (pixel, Gaussian) pair: the same instructions in
+// the forward and the backward so both take the same skip decisions.
+// r0 = (u_hi, v_hi, u_lo, v_lo), r1 = (a, b, c, opacity).
+struct Frag {
+  float dx, dy, e, alpha;   // e = exp(power), alpha = min(0.99, o e)
+};
+
+__device__ __forceinline__ Frag frag_alpha(float4 r0, float4 r1, float px, float py) {
+  Frag f;
+  f.dx = (r0.x - px) + r0.z;
+  f.dy = (r0.y - py) + r0.w;
+  const float qa = r1.x * f.dx;
+  const float qc = r1.z * f.dy;
+  // power = -0.5 (a dx^2 + c dy^2) - b dx dy
+  const float quad = __builtin_fmaf(qa, f.dx, qc * f.dy);
+  const float power = __builtin_fmaf(-0.5f, quad, -(r1.y * f.dx) * f.dy);
+  f.e = __expf(power);
+  f.alpha = fminf(kAlphaMax, r1.w * f.e);
+  return f;
+}
+
+#endif
+
+}  // namespace rtgs

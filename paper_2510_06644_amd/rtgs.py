@@ -1,0 +1,471 @@
+"""ctypes binding of librtgs (include/rtgs.h): argument marshalling only.
+
+Every step of the rasterizer runs in the HIP library; this module turns torch
+tensors into device pointers and the current HIP stream into a handle.  There
+is no fallback: if librtgs.so is missing or a tensor is not on the GPU the
+call raises.
+
+The entry points keep the C names (``render_fwd``, ``render_bwd``,
+``render_fwd_batched``, ``render_bwd_batched``, ``prune_by_grad``,
+``downsample_mask``, ``rtgs_query`` ...).  ``Renderer`` adds workspace and
+pair-capacity management on top.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librtgs.so")
+
+RTGS_OK = 0
+RTGS_ERR_INVALID_ARG = -1
+RTGS_ERR_CAPACITY = -2
+RTGS_ERR_HIP = -3
+RTGS_ERR_WORKSPACE = -4
+RTGS_FWD_SAVE_STATE = 1
+RTGS_GRAD_POSE = 1
+RTGS_GRAD_MAP = 2
+RTGS_GRAD_COV3D = 4
+RTGS_GRAD_RECOMPUTE_STATE = 8
+RTGS_STATE_IDLE = 0
+RTGS_STATE_EXECUTING = 1
+RTGS_MAX_SESSIONS = 64
+
+EXPORTS = (
+    "rtgs_last_error", "rtgs_create", "rtgs_destroy", "rtgs_workspace_size",
+    "rtgs_workspace_size_batched", "render_fwd", "render_bwd", "render_fwd_batched",
+    "render_bwd_batched", "prune_by_grad", "downsample_mask", "rtgs_downsample_log2_ratio",
+    "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum",
+)
+
+vp = ctypes.c_void_p
+i32 = ctypes.c_int32
+i64 = ctypes.c_int64
+u64 = ctypes.c_uint64
+f32 = ctypes.c_float
+
+
+class CGaussians(ctypes.Structure):
+    _fields_ = [("means", vp), ("log_scales", vp), ("quats", vp), ("opacity_logits", vp),
+                ("colors", vp), ("gauss_mask", vp), ("n", i32)]
+
+
+class CCamera(ctypes.Structure):
+    _fields_ = [("width", i32), ("height", i32), ("fx", f32), ("fy", f32), ("cx", f32),
+                ("cy", f32), ("viewmat", vp)]
+
+
+class CSession(ctypes.Structure):
+    _fields_ = [("g", CGaussians), ("cam", CCamera), ("pixel_mask", vp),
+                ("color", vp), ("depth", vp), ("alpha", vp), ("final_T", vp), ("last_idx", vp),
+                ("visible", vp), ("dL_dcolor", vp), ("dL_ddepth", vp), ("dL_dalpha", vp),
+                ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
+                ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_cov3d", vp)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+class RtgsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librtgs error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load librtgs.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -c 'import __graft_entry__ as g; g.build()'`")
+            L = ctypes.CDLL(LIB_PATH)
+            L.rtgs_last_error.restype = ctypes.c_char_p
+            L.rtgs_create.argtypes = [ctypes.POINTER(vp), i32]
+            L.rtgs_destroy.argtypes = [vp]
+            L.rtgs_workspace_size.argtypes = [i32, i32, i32, i64, i32, ctypes.POINTER(u64)]
+            L.rtgs_workspace_size_batched.argtypes = [vp, vp, vp, i32, i64, i32,
+                                                      ctypes.POINTER(u64)]
+            L.render_fwd.argtypes = [vp, ctypes.POINTER(CGaussians), ctypes.POINTER(CCamera), vp,
+                                     vp, u64, i64, vp, vp, vp, vp, vp, vp, i32, vp]
+            L.render_bwd.argtypes = [vp, ctypes.POINTER(CGaussians), ctypes.POINTER(CCamera), vp,
+                                     vp, u64, i64, vp, vp, vp, vp, vp, i32,
+                                     vp, vp, vp, vp, vp, vp, vp, vp]
+            L.render_fwd_batched.argtypes = [vp, ctypes.POINTER(CSession), i32, vp, u64, i64,
+                                             i32, vp]
+            L.render_bwd_batched.argtypes = [vp, ctypes.POINTER(CSession), i32, vp, u64, i64,
+                                             i32, vp]
+            L.prune_by_grad.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp]
+            L.downsample_mask.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+            L.rtgs_downsample_log2_ratio.argtypes = [i32, i32, i32, i32]
+            L.rtgs_query.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+            L.rtgs_debug_stage.argtypes = [vp, vp, vp, i32, i64, vp, u64, vp, vp, vp, vp, i64,
+                                           vp]
+            L.rtgs_selftest_wave_sum.argtypes = [vp, vp, i32, vp]
+            for name in EXPORTS:
+                getattr(L, name).restype = getattr(L, name).restype or i32
+            L.rtgs_last_error.restype = ctypes.c_char_p
+            _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != RTGS_OK:
+        raise RtgsError(code, lib().rtgs_last_error().decode())
+    return code
+
+
+def _p(t):
+    """Device pointer of a tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("librtgs takes GPU tensors only")
+    if not t.is_contiguous():
+        raise ValueError("librtgs takes contiguous tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(t, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Handle:
+    """Owns an rtgs_handle_t (one per stream)."""
+
+    def __init__(self, device: int = 0):
+        self.ptr = ctypes.c_void_p()
+        _check(lib().rtgs_create(ctypes.byref(self.ptr), int(device)))
+        self.device = device
+
+    def close(self):
+        if self.ptr:
+            lib().rtgs_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------- C entry points
+def rtgs_workspace_size(n, width, height, pair_capacity, flags=0):
+    out = u64()
+    _check(lib().rtgs_workspace_size(int(n), int(width), int(height), int(pair_capacity),
+                                     int(flags), ctypes.byref(out)))
+    return int(out.value)
+
+
+def rtgs_workspace_size_batched(ns, widths, heights, pair_capacity, flags=0):
+    k = len(ns)
+    a = (i32 * k)(*ns)
+    w = (i32 * k)(*widths)
+    h = (i32 * k)(*heights)
+    out = u64()
+    _check(lib().rtgs_workspace_size_batched(a, w, h, k, int(pair_capacity), int(flags),
+                                             ctypes.byref(out)))
+    return int(out.value)
+
+
+@dataclasses.dataclass
+class Cam:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+
+def _gauss(means, log_scales, quats, opacity_logits, colors, gauss_mask):
+    n = means.shape[0]
+    _f32(means, (n, 3), "means")
+    _f32(log_scales, (n, 3), "log_scales")
+    _f32(quats, (n, 4), "quats")
+    _f32(opacity_logits, (n,), "opacity_logits")
+    _f32(colors, (n, 3), "colors")
+    if gauss_mask is not None and (gauss_mask.dtype != torch.uint8 or gauss_mask.numel() != n):
+        raise ValueError("gauss_mask must be uint8 [n]")
+    return CGaussians(_p(means), _p(log_scales), _p(quats), _p(opacity_logits), _p(colors),
+                      _p(gauss_mask), n)
+
+
+def _cam(cam: Cam, viewmat):
+    _f32(viewmat, None, "viewmat")
+    if viewmat.numel() != 12:
+        raise ValueError("viewmat must hold 12 floats (3x4 row-major)")
+    return CCamera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx),
+                   float(cam.cy), _p(viewmat))
+
+
+def render_fwd(handle, means, log_scales, quats, opacity_logits, colors, viewmat, cam,
+               ws, pair_capacity, out_color, out_depth, out_alpha, final_T=None, last_idx=None,
+               visible=None, gauss_mask=None, pixel_mask=None, flags=RTGS_FWD_SAVE_STATE,
+               stream=None):
+    g = _gauss(means, log_scales, quats, opacity_logits, colors, gauss_mask)
+    c = _cam(cam, viewmat)
+    _check(lib().render_fwd(handle.ptr, ctypes.byref(g), ctypes.byref(c), _p(pixel_mask),
+                            _p(ws), ws.numel() * ws.element_size(), int(pair_capacity),
+                            _p(out_color), _p(out_depth), _p(out_alpha), _p(final_T),
+                            _p(last_idx), _p(visible), int(flags), _stream(stream)))
+
+
+def render_bwd(handle, means, log_scales, quats, opacity_logits, colors, viewmat, cam, ws,
+               pair_capacity, final_T, last_idx, dL_dcolor, dL_ddepth, dL_dalpha=None,
+               grad_flags=RTGS_GRAD_POSE | RTGS_GRAD_MAP, g_means=None, g_log_scales=None,
+               g_quats=None, g_opacity_logits=None, g_colors=None, g_pose6=None, g_cov3d=None,
+               gauss_mask=None, pixel_mask=None, stream=None):
+    g = _gauss(means, log_scales, quats, opacity_logits, colors, gauss_mask)
+    c = _cam(cam, viewmat)
+    _check(lib().render_bwd(handle.ptr, ctypes.byref(g), ctypes.byref(c), _p(pixel_mask),
+                            _p(ws), ws.numel() * ws.element_size(), int(pair_capacity),
+                            _p(final_T), _p(last_idx), _p(dL_dcolor), _p(dL_ddepth),
+                            _p(dL_dalpha), int(grad_flags), _p(g_means), _p(g_log_scales),
+                            _p(g_quats), _p(g_opacity_logits), _p(g_colors), _p(g_pose6),
+                            _p(g_cov3d), _stream(stream)))
+
+
+def make_sessions(items):
+    """items: list of dicts with keys of CSession (tensors or None) plus
+    'scene' (means, log_scales, quats, opacity_logits, colors), 'viewmat',
+    'cam' (Cam), optional 'gauss_mask'."""
+    arr = (CSession * len(items))()
+    keep = []
+    for i, it in enumerate(items):
+        sc = it["scene"]
+        s = arr[i]
+        s.g = _gauss(*sc, it.get("gauss_mask"))
+        s.cam = _cam(it["cam"], it["viewmat"])
+        for name in ("pixel_mask", "color", "depth", "alpha", "final_T", "last_idx", "visible",
+                     "dL_dcolor", "dL_ddepth", "dL_dalpha", "g_means", "g_log_scales", "g_quats",
+                     "g_opacity_logits", "g_colors", "g_pose6", "g_cov3d"):
+            t = it.get(name)
+            setattr(s, name, _p(t))
+            keep.append(t)
+    return arr, keep
+
+
+def render_fwd_batched(handle, sessions, ws, pair_capacity, flags=RTGS_FWD_SAVE_STATE,
+                       stream=None):
+    arr, _keep = make_sessions(sessions)
+    _check(lib().render_fwd_batched(handle.ptr, arr, len(sessions), _p(ws),
+                                    ws.numel() * ws.element_size(), int(pair_capacity),
+                                    int(flags), _stream(stream)))
+
+
+def render_bwd_batched(handle, sessions, ws, pair_capacity,
+                       grad_flags=RTGS_GRAD_POSE | RTGS_GRAD_MAP, stream=None):
+    arr, _keep = make_sessions(sessions)
+    _check(lib().render_bwd_batched(handle.ptr, arr, len(sessions), _p(ws),
+                                    ws.numel() * ws.element_size(), int(pair_capacity),
+                                    int(grad_flags), _stream(stream)))
+
+
+def prune_by_grad(handle, g_means, g_cov3d, visible, mask_in, lam, max_ratio, mask_out,
+                  n_masked=None, score_out=None, stream=None):
+    n = g_means.shape[0]
+    _check(lib().prune_by_grad(handle.ptr, _p(g_means), _p(g_cov3d), _p(visible), _p(mask_in),
+                               n, float(lam), float(max_ratio), _p(mask_out), _p(n_masked),
+                               _p(score_out), _stream(stream)))
+
+
+def downsample_mask(final_T, log2_ratio, mask_out, n_active=None, stream=None):
+    h, w = final_T.shape
+    _check(lib().downsample_mask(_p(final_T), w, h, int(log2_ratio), _p(mask_out),
+                                 _p(n_active), _stream(stream)))
+
+
+def rtgs_downsample_log2_ratio(is_keyframe, n, k, m=2):
+    r = lib().rtgs_downsample_log2_ratio(int(bool(is_keyframe)), int(n), int(k), int(m))
+    if r < 0:
+        _check(r)
+    return r
+
+
+def rtgs_query(handle, blocking=True):
+    """(status, pairs_needed, state); status is RTGS_OK or RTGS_ERR_CAPACITY."""
+    pairs = i64()
+    state = i32()
+    code = lib().rtgs_query(handle.ptr, int(bool(blocking)), ctypes.byref(pairs),
+                            ctypes.byref(state))
+    if code not in (RTGS_OK, RTGS_ERR_CAPACITY):
+        _check(code)
+    return code, int(pairs.value), int(state.value)
+
+
+def rtgs_debug_stage(ns, widths, heights, pair_capacity, ws, stage=None, rect=None,
+                     ranges=None, ids=None, stream=None):
+    k = len(ns)
+    a = (i32 * k)(*ns)
+    w = (i32 * k)(*widths)
+    h = (i32 * k)(*heights)
+    _check(lib().rtgs_debug_stage(a, w, h, k, int(pair_capacity), _p(ws),
+                                  ws.numel() * ws.element_size(), _p(stage), _p(rect),
+                                  _p(ranges), _p(ids), 0 if ids is None else ids.numel(),
+                                  _stream(stream)))
+
+
+def rtgs_selftest_wave_sum(inp, out, stream=None):
+    _check(lib().rtgs_selftest_wave_sum(_p(inp), _p(out), out.numel(), _stream(stream)))
+
+
+# --------------------------------------------------------------------------- managed renderer
+def _tiles(w, h):
+    return ((w + 15) // 16) * ((h + 15) // 16)
+
+
+class Renderer:
+    """Workspace + pair-capacity management around render_fwd / render_bwd.
+
+    check="every": after each forward, a blocking rtgs_query verifies the
+    pair capacity and re-renders with a larger buffer if it overflowed (one
+    host sync per forward).  check="deferred": no per-call sync; call
+    ``verify()`` at a point of your choosing (it raises if any forward since
+    the last verify overflowed, after growing the capacity)."""
+
+    def __init__(self, device=0, check="every", pairs_per_gaussian=12.0, min_capacity=1 << 16):
+        self.handle = Handle(device)
+        self.device = torch.device("cuda", device)
+        self.check = check
+        self.ppg = pairs_per_gaussian
+        self.min_cap = min_capacity
+        self.cap = 0
+        self.ws = None
+
+    def _ensure(self, ns, ws_, hs, cap):
+        cap = max(int(cap), self.min_cap)
+        if cap > self.cap:
+            self.cap = cap
+        need = rtgs_workspace_size_batched(ns, ws_, hs, self.cap)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        return self.ws, self.cap
+
+    def workspace(self, ns, widths, heights):
+        est = int(self.ppg * sum(ns)) + 4 * sum(_tiles(w, h) for w, h in zip(widths, heights))
+        return self._ensure(ns, widths, heights, max(self.cap, est))
+
+    def grow(self, needed):
+        self.cap = max(self.cap, int(needed * 1.25) + 1024)
+
+    def verify(self):
+        code, pairs, _ = rtgs_query(self.handle, True)
+        if code == RTGS_ERR_CAPACITY:
+            self.grow(pairs)
+            raise RtgsError(code, f"pair capacity exceeded: {pairs} needed")
+        return pairs
+
+    # ------------------------------------------------------------------ managed calls
+    def forward(self, scene, viewmat, cam: Cam, gauss_mask=None, pixel_mask=None,
+                save_state=True, stream=None):
+        """Render one frame; returns a FwdState (outputs + the workspace the
+        matching backward needs).  Each forward gets its own workspace from
+        torch's caching allocator, so several forwards may await backward."""
+        n = scene[0].shape[0]
+        dev = scene[0].device
+        h, w = cam.height, cam.width
+        est = int(self.ppg * n) + 4 * _tiles(w, h)
+        cap = max(self.cap, est, self.min_cap)
+        while True:
+            need = rtgs_workspace_size(n, w, h, cap)
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            out = FwdState(ws=ws, cap=cap, cam=cam, n=n,
+                           color=torch.empty(3, h, w, device=dev),
+                           depth=torch.empty(h, w, device=dev),
+                           alpha=torch.empty(h, w, device=dev),
+                           final_T=torch.empty(h, w, device=dev) if save_state else None,
+                           last_idx=(torch.empty(h, w, dtype=torch.int32, device=dev)
+                                     if save_state else None),
+                           visible=torch.empty(n, dtype=torch.uint8, device=dev))
+            render_fwd(self.handle, *scene, viewmat, cam, ws, cap, out.color, out.depth,
+                       out.alpha, out.final_T, out.last_idx, out.visible, gauss_mask=gauss_mask,
+                       pixel_mask=pixel_mask,
+                       flags=RTGS_FWD_SAVE_STATE if save_state else 0, stream=stream)
+            self.cap = max(self.cap, cap)
+            if self.check != "every":
+                return out
+            code, pairs, _ = rtgs_query(self.handle, True)
+            out.pairs = pairs
+            if code == RTGS_OK:
+                return out
+            self.grow(pairs)
+            cap = self.cap
+
+    def backward(self, scene, viewmat, cam: Cam, st: "FwdState", dL_dcolor, dL_ddepth,
+                 dL_dalpha=None, pose=True, map_grads=True, cov3d=False, gauss_mask=None,
+                 pixel_mask=None, stream=None):
+        n = st.n
+        dev = scene[0].device
+        flags = (RTGS_GRAD_POSE if pose else 0) | (RTGS_GRAD_MAP if map_grads else 0)
+        flags |= RTGS_GRAD_COV3D if cov3d else 0
+        if st.final_T is None:
+            flags |= RTGS_GRAD_RECOMPUTE_STATE
+        g = {}
+        if map_grads:
+            g["means"] = torch.empty(n, 3, device=dev)
+            g["log_scales"] = torch.empty(n, 3, device=dev)
+            g["quats"] = torch.empty(n, 4, device=dev)
+            g["opacity_logits"] = torch.empty(n, device=dev)
+            g["colors"] = torch.empty(n, 3, device=dev)
+        if cov3d:
+            g["cov3d"] = torch.empty(n, 6, device=dev)
+        if pose:
+            g["pose"] = torch.empty(6, device=dev)
+        render_bwd(self.handle, *scene, viewmat, cam, st.ws, st.cap, st.final_T, st.last_idx,
+                   dL_dcolor.contiguous(), dL_ddepth.contiguous(),
+                   None if dL_dalpha is None else dL_dalpha.contiguous(), flags,
+                   g.get("means"), g.get("log_scales"), g.get("quats"), g.get("opacity_logits"),
+                   g.get("colors"), g.get("pose"), g.get("cov3d"), gauss_mask=gauss_mask,
+                   pixel_mask=pixel_mask, stream=stream)
+        return g
+
+
+@dataclasses.dataclass
+class FwdState:
+    ws: torch.Tensor
+    cap: int
+    cam: Cam
+    n: int
+    color: torch.Tensor
+    depth: torch.Tensor
+    alpha: torch.Tensor
+    final_T: torch.Tensor | None
+    last_idx: torch.Tensor | None
+    visible: torch.Tensor
+    pairs: int = -1
+
+    def stage(self):
+        """Forward intermediates for tests: dict of numpy arrays."""
+        n, w, h = self.n, self.cam.width, self.cam.height
+        dev = self.ws.device
+        t = _tiles(w, h)
+        stage = torch.empty(max(n, 1), 12, device=dev)
+        rect = torch.empty(max(n, 1), 4, dtype=torch.int32, device=dev)
+        ranges = torch.empty(t, 2, dtype=torch.int32, device=dev)
+        ids = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
+        rtgs_debug_stage([n], [w], [h], self.cap, self.ws, stage, rect, ranges, ids)
+        torch.cuda.synchronize()
+        rng = ranges.cpu().numpy()
+        total = int(rng[:, 1].max()) if t else 0
+        return {"stage": stage.cpu().numpy()[:n], "rect": rect.cpu().numpy()[:n],
+                "ranges": rng, "ids": ids.cpu().numpy()[:total]}
