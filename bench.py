@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Benchmark of the differentiable Gaussian-splatting rasterizer on one MI355X.
+
+Headline: mapping iterations per second at 1200x680 with 300,000 Gaussians
+(scales log-normal(-4.5, 0.7), 20% near-transparent), full resolution, no
+pruning.  One step = render_fwd + L1 colour / 0.5 L1 depth loss + render_bwd
+to every Gaussian parameter + an Adam update of the map, i.e. one mapping
+iteration of the SLAM back end; inputs are resident in HBM.
+
+Also reported on the same line: the roofline of the dominant kernel (timed
+with HIP events on its own stream inside the timed region), a per-stage
+breakdown, the as-written variant (gradient pruning with ratio 0.5 after
+iteration 30 and a 1-in-4 alpha-based pixel mask), and the CPU oracle timed
+on a bounded pixel sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd iters/s at 1200x680/300k Gaussians; served p50/p99 frame latency"
+
+# Algorithmic FP32 operations per unit of work of the reverse compositing
+# (raster_bwd): alpha re-evaluation of a list entry up to the pixel's last
+# blended fragment, and the gradient of one blended fragment including the
+# ten additions that merge it into its Gaussian.  Counted from the operations
+# the method must perform (an FMA counts as two).
+FLOP_BWD_PER_ENTRY = 18
+FLOP_BWD_PER_BLEND = 65
+FLOP_FWD_PER_ENTRY = 18
+FLOP_FWD_PER_BLEND = 12
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(spec_name="c2", seed_offset=0):
+    import torch
+    from paper_2510_06644_amd import rtgs, synth
+    spec = synth.CONFIGS[spec_name]
+    cam = synth.make_camera(spec.width, spec.height)
+    sc = synth.make_scene(spec, cam)
+    tgt = synth.perturb_scene(sc, spec.seed + 500)
+    dev = torch.device("cuda", 0)
+    params = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in sc.arrays()]
+    target_scene = tuple(torch.from_numpy(a).to(dev) for a in tgt.arrays())
+    view = torch.from_numpy(synth.identity_viewmat()).to(dev)
+    rc = rtgs.Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+    return spec, cam, sc, params, target_scene, view, rc
+
+
+def render_target(R, target_scene, view, rc, seed):
+    import torch
+    st = R.forward(target_scene, view, rc)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    tc = st.color + 0.01 * torch.randn(st.color.shape, generator=g, device="cuda")
+    td = st.depth + 0.01 * torch.randn(st.depth.shape, generator=g, device="cuda")
+    return tc, td
+
+
+def make_optimizer(params):
+    import torch
+    lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)
+    return torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in zip(params, lrs)],
+                            eps=1e-15, foreach=True)
+
+
+def l1_grads(color, depth, tc, td, pixel_mask=None):
+    """dL/dC, dL/dD of L = mean|C - C^| / 3 ... over active pixels (Eq. 6 reading)."""
+    import torch
+    if pixel_mask is None:
+        n = color.shape[1] * color.shape[2]
+        gc = torch.sign(color - tc) * (1.0 / (3 * n))
+        gd = torch.sign(depth - td) * (0.5 / n)
+    else:
+        m = pixel_mask.to(color.dtype)
+        n = m.sum().clamp(min=1.0)
+        gc = torch.sign(color - tc) * m / (3 * n)
+        gd = torch.sign(depth - td) * m * (0.5 / n)
+    return gc, gd
+
+
+def mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=None, pixel_mask=None,
+                 cov3d=False):
+    scene = tuple(p.detach() for p in params)
+    st = R.forward(scene, view, rc, gauss_mask=gauss_mask, pixel_mask=pixel_mask)
+    gc, gd = l1_grads(st.color, st.depth, tc, td, pixel_mask)
+    g = R.backward(scene, view, rc, st, gc, gd, pose=False, map_grads=True, cov3d=cov3d,
+                   gauss_mask=gauss_mask, pixel_mask=pixel_mask)
+    for p, k in zip(params, ("means", "log_scales", "quats", "opacity_logits", "colors")):
+        p.grad = g[k]
+    opt.step()
+    return st, g
+
+
+def work_counts(R, params, view, rc):
+    """Per-pixel work counts of one forward (fragments blended, list entries
+    visited up to the stop, entries up to the last blended) and pair count."""
+    import torch
+    from paper_2510_06644_amd import rtgs
+    n = params[0].shape[0]
+    h, w = rc.height, rc.width
+    cap = max(R.cap, 1 << 16)
+    ws = torch.empty(rtgs.rtgs_workspace_size(n, w, h, cap), dtype=torch.uint8, device="cuda")
+    out = dict(scene=tuple(p.detach() for p in params), viewmat=view, cam=rc,
+               color=torch.empty(3, h, w, device="cuda"), depth=torch.empty(h, w, device="cuda"),
+               alpha=torch.empty(h, w, device="cuda"),
+               stats=torch.zeros(3, h, w, dtype=torch.int32, device="cuda"))
+    rtgs.render_fwd_batched(R.handle, [out], ws, cap, flags=rtgs.RTGS_FWD_STATS)
+    code, pairs, _ = rtgs.rtgs_query(R.handle, True)
+    assert code == rtgs.RTGS_OK, "capacity"
+    s = out["stats"].to(torch.int64).sum((1, 2)).cpu().numpy()
+    return {"blended": int(s[0]), "visited": int(s[1]), "visited_to_last": int(s[2]),
+            "pairs": int(pairs)}
+
+
+def timed_loop(R, params, view, rc, opt, tc, td, steps, profile_stages=None, **kw):
+    import torch
+    from paper_2510_06644_amd import rtgs
+    if profile_stages:
+        rtgs.rtgs_profile_enable(R.handle, profile_stages)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        mapping_step(R, params, view, rc, opt, tc, td, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = {}
+    if profile_stages:
+        prof = rtgs.rtgs_profile_read(R.handle)
+        rtgs.rtgs_profile_enable(R.handle, [])
+    R.verify()
+    return e0.elapsed_time(e1) / steps, wall / steps, prof
+
+
+def as_written_variant(R, params, view, rc, opt, tc, td, iters=60):
+    """60 iterations: full frame for iteration 1, then a 1-in-4 pixel mask from
+    iteration 1's final transmittance; gradient pruning (ratio 0.5) after
+    iteration 30, the mask kept for the remaining iterations."""
+    import torch
+    from paper_2510_06644_amd import rtgs
+    n = params[0].shape[0]
+    h, w = rc.height, rc.width
+    pmask = torch.empty(h, w, dtype=torch.uint8, device="cuda")
+    gmask = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    newmask = torch.empty_like(gmask)
+    n_masked = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st, _ = mapping_step(R, params, view, rc, opt, tc, td)
+    rtgs.downsample_mask(st.final_T, 2, pmask)
+    use_gmask = None
+    for it in range(2, iters + 1):
+        st, g = mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=use_gmask,
+                             pixel_mask=pmask, cov3d=(it == 30))
+        if it == 30:
+            rtgs.prune_by_grad(R.handle, g["means"], g["cov3d"], st.visible, gmask, 0.8, 0.5,
+                               newmask, n_masked)
+            use_gmask = newmask
+    e1.record()
+    torch.cuda.synchronize()
+    R.verify()
+    return {"iters": iters, "ms_per_iter": e0.elapsed_time(e1) / iters,
+            "iters_per_s": 1000.0 * iters / e0.elapsed_time(e1),
+            "wall_ms_per_iter": 1000 * (time.perf_counter() - t0) / iters,
+            "pruned": int(n_masked.item()), "active_pixels": int(pmask.sum().item())}
+
+
+def cpu_baseline(sc, cam, sample=192, seed=5):
+    """The float64 oracle, fwd + bwd to every parameter and the pose, on a
+    random sample of pixels of the same frame, scaled to a full frame."""
+    import torch
+    import oracle
+    from paper_2510_06644_amd import synth
+    rng = np.random.default_rng(seed)
+    pix = np.sort(rng.choice(cam.width * cam.height, sample, replace=False))
+    gc, gd, ga = synth.upstream_grads(cam.width, cam.height, seed)
+    gcs = gc.reshape(3, -1)[:, pix]
+    gds = gd.reshape(-1)[pix]
+    t0 = time.perf_counter()
+    oracle.render_with_grads(sc.arrays(), synth.identity_viewmat(),
+                             (cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy), gcs, gds,
+                             pixels=pix, chunk=16)
+    dt = time.perf_counter() - t0
+    full = dt * (cam.width * cam.height) / sample
+    return {"value": 1.0 / full, "unit": "iters/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{sample} random pixels of the 1200x680 frame against all 300,000 "
+                      f"Gaussians, fwd+bwd in float64 ({dt:.1f} s), scaled by pixel count",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variant", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=384)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this path has no multi-GPU mode "
+              f"(--gpus {args.gpus} requested).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2510_06644_amd import rtgs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    spec, cam, sc, params, target_scene, view, rc = setup("c2")
+    R = rtgs.Renderer(0, check="deferred")
+    tc, td = render_target(R, target_scene, view, rc, spec.seed)
+    R.verify()
+    opt = make_optimizer(params)
+    log("warmup")
+    for _ in range(args.warmup):
+        mapping_step(R, params, view, rc, opt, tc, td)
+    torch.cuda.synchronize()
+    try:
+        R.verify()
+    except rtgs.RtgsError:
+        for _ in range(2):
+            mapping_step(R, params, view, rc, opt, tc, td)
+        R.verify()
+    counts0 = work_counts(R, params, view, rc)
+    log(f"counts {counts0}")
+
+    log("timed")
+    ms, wall_ms, prof = timed_loop(R, params, view, rc, opt, tc, td, args.steps,
+                                   profile_stages=["raster_bwd"])
+    counts1 = work_counts(R, params, view, rc)
+    cnt = {k: 0.5 * (counts0[k] + counts1[k]) for k in counts0}
+    bwd_ms = prof["raster_bwd"][0] / prof["raster_bwd"][1]
+    flops = FLOP_BWD_PER_ENTRY * cnt["visited_to_last"] + FLOP_BWD_PER_BLEND * cnt["blended"]
+    achieved = flops / (bwd_ms * 1e-3) / 1e12
+    roof = {"kernel": "raster_bwd", "bound": "alu", "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None, "avg_ms": bwd_ms, "launches": prof["raster_bwd"][1],
+            "flops_per_launch": flops}
+    log("stage breakdown")
+    _, _, stages = timed_loop(R, params, view, rc, opt, tc, td, 10,
+                              profile_stages=list(rtgs.STAGES))
+    stages_ms = {k: v[0] / v[1] for k, v in stages.items()}
+    fwd_ms = stages_ms.get("raster_fwd", float("nan"))
+    fwd_flops = FLOP_FWD_PER_ENTRY * cnt["visited"] + FLOP_FWD_PER_BLEND * cnt["blended"]
+
+    variant = None
+    if not args.no_variant:
+        log("as-written variant")
+        spec2, cam2, sc2, params2, tscene2, view2, rc2 = setup("c2")
+        R2 = rtgs.Renderer(0, check="deferred")
+        tc2, td2 = render_target(R2, tscene2, view2, rc2, spec2.seed)
+        R2.verify()
+        opt2 = make_optimizer(params2)
+        for _ in range(3):
+            mapping_step(R2, params2, view2, rc2, opt2, tc2, td2)
+        R2.cap = R.cap
+        variant = as_written_variant(R2, params2, view2, rc2, opt2, tc2, td2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline(sc, cam, sample=args.cpu_sample)
+    line = {
+        "metric": METRIC,
+        "value": 1000.0 / ms,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "width": cam.width, "height": cam.height,
+                   "gaussians": spec.n, "step": "render_fwd + L1 loss + render_bwd (all map "
+                   "parameters) + Adam", "pixels": "full resolution", "prune": False},
+        "roofline": roof,
+        "raster_fwd_roofline": {"bound": "alu", "avg_ms": fwd_ms,
+                                "achieved": fwd_flops / (fwd_ms * 1e-3) / 1e12,
+                                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"},
+        "stages_ms": stages_ms,
+        "work": cnt,
+        "host_wall_ms_per_step": 1000.0 * wall_ms,
+        "as_written": variant,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

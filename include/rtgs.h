@@ -56,6 +56,8 @@ extern "C" {
 
 /* ---- render_fwd flags ---- */
 #define RTGS_FWD_SAVE_STATE   1   /* write final_T and last_idx (saved state)  */
+#define RTGS_FWD_STATS        2   /* write per-pixel work counts (sessions'
+                                     `stats`; render_fwd_batched only)         */
 
 /* ---- render_bwd flags ---- */
 #define RTGS_GRAD_POSE        1   /* write g_pose6                             */
@@ -108,6 +110,10 @@ typedef struct {
   float* final_T;              /* [H][W] saved transmittance */
   int32_t* last_idx;           /* [H][W] position of the last blended pair, -1 */
   uint8_t* visible;            /* [n] 1 if projected and on screen, or NULL */
+  int32_t* stats;              /* [3][H][W] with RTGS_FWD_STATS: fragments
+                                  blended; list entries visited up to the stop
+                                  (or the list end); list entries up to the
+                                  last blended one.  NULL otherwise. */
   /* backward inputs */
   const float* dL_dcolor;      /* [3][H][W] */
   const float* dL_ddepth;      /* [H][W] */
@@ -256,6 +262,17 @@ int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width,
                          uint64_t ws_bytes, float* stage, int32_t* rect,
                          int32_t* ranges, int32_t* ids, int64_t ids_capacity,
                          void* stream);
+
+/* Stage profiler (HIP events on the stream each kernel is launched on).
+ * Stages: 0 init, 1 preprocess, 2 scan, 3 emit, 4 sort, 5 raster_fwd,
+ * 6 zero, 7 raster_bwd, 8 preprocess_bwd, 9 pose_reduce.  After
+ * rtgs_profile_enable(h, mask) every launch of a stage whose bit is set is
+ * bracketed by two events; rtgs_profile_read waits for them and returns per
+ * stage the summed milliseconds and the launch count (HOST arrays of
+ * RTGS_PROFILE_STAGES entries), then clears.  mask = 0 disables. */
+#define RTGS_PROFILE_STAGES 16
+int32_t rtgs_profile_enable(rtgs_handle_t h, int32_t stage_mask);
+int32_t rtgs_profile_read(rtgs_handle_t h, double* total_ms, int64_t* launches);
 
 /* Test hook for the wavefront reduction used by the backward merge: out[w] =
  * sum of in[64 w .. 64 w + 63] for each wave w of n_waves. */

@@ -48,8 +48,62 @@ int64_t blocks_of(int n) { return (n + kGaussPerBlock - 1) / kGaussPerBlock; }
 
 }  // namespace
 
+namespace {
+
+// HIP-event stage timer owned by a handle.
+struct EventTimer : StageTimer {
+  int mask = 0;
+  std::vector<hipEvent_t> pool;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<int> open_stage;
+  std::vector<hipEvent_t> open_ev;
+  hipError_t err = hipSuccess;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) err = r;
+    return e;
+  }
+  void begin(int stage, hipStream_t st) override {
+    if (!(mask & (1 << stage))) return;
+    hipEvent_t e = get();
+    if (e && hipEventRecord(e, st) != hipSuccess) err = hipErrorUnknown;
+    open_stage.push_back(stage);
+    open_ev.push_back(e);
+  }
+  void end(int stage, hipStream_t st) override {
+    if (!(mask & (1 << stage))) return;
+    hipEvent_t e = get();
+    if (e && hipEventRecord(e, st) != hipSuccess) err = hipErrorUnknown;
+    hipEvent_t a = open_ev.back();
+    open_ev.pop_back();
+    open_stage.pop_back();
+    recs.push_back({stage, a, e});
+  }
+  ~EventTimer() override {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
 struct rtgs_context {
   int device = 0;
+  EventTimer timer;
   unsigned long long* d_scalars = nullptr;   // [0] largest pair count since last query
   uint32_t* d_prune = nullptr;               // prune scratch
   SessionDev* h_ring = nullptr;              // pinned [kRing][RTGS_MAX_SESSIONS]
@@ -214,6 +268,7 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
       d.final_T = (flags & RTGS_FWD_SAVE_STATE) ? s.final_T : nullptr;
       d.last_idx = (flags & RTGS_FWD_SAVE_STATE) ? s.last_idx : nullptr;
       d.visible = s.visible;
+      d.stats = (flags & RTGS_FWD_STATS) ? s.stats : nullptr;
     } else {
       if (flags & RTGS_GRAD_RECOMPUTE_STATE) {
         d.final_T = w.state_t + pbase;
@@ -356,19 +411,24 @@ int32_t rtgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t pa
 
 int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
-  if (flags & ~RTGS_FWD_SAVE_STATE) return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
+  if (flags & ~(RTGS_FWD_SAVE_STATE | RTGS_FWD_STATS))
+    return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
   WsLayout L;
   WsPtrs w;
   int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w);
   if (r) return r;
-  for (int i = 0; i < ns; ++i)
+  for (int i = 0; i < ns; ++i) {
     if ((r = check_session(ss[i], i, true, flags))) return r;
+    if ((flags & RTGS_FWD_STATS) && !ss[i].stats)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: RTGS_FWD_STATS needs stats", i);
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   Batch B;
   r = upload_table(h, ss, ns, w, st, true, flags, B);
   if (r) return r;
-  hipError_t e = launch_forward_prep(B, w, h->d_scalars, st);
-  if (e == hipSuccess) e = launch_raster_fwd(B, w, flags & RTGS_FWD_SAVE_STATE, st);
+  StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
+  hipError_t e = launch_forward_prep(B, w, h->d_scalars, st, tm);
+  if (e == hipSuccess) e = launch_raster_fwd(B, w, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_fwd launch");
   h->last_stream = st;
   h->used = true;
@@ -392,10 +452,11 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   Batch B;
   r = upload_table(h, ss, ns, w, st, false, flags, B);
   if (r) return r;
+  StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
   hipError_t e = hipSuccess;
-  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, 1, st);
-  if (e == hipSuccess) e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, st);
-  if (e == hipSuccess) e = launch_preprocess_bwd(B, w, flags, st);
+  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, st, tm);
+  if (e == hipSuccess) e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, st, tm);
+  if (e == hipSuccess) e = launch_preprocess_bwd(B, w, flags, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_bwd launch");
   h->last_stream = st;
   h->used = true;
@@ -531,6 +592,37 @@ int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width, const int32_t* 
   hipError_t e = launch_debug_stage(B, w, stage, rect, ranges, ids, ids_capacity,
                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "rtgs_debug_stage launch");
+  return RTGS_OK;
+}
+
+int32_t rtgs_profile_enable(rtgs_handle_t h, int32_t stage_mask) {
+  if (!h) return fail(RTGS_ERR_INVALID_ARG, "null handle");
+  h->timer.mask = stage_mask & ((1 << RTGS_PROFILE_STAGES) - 1);
+  return RTGS_OK;
+}
+
+int32_t rtgs_profile_read(rtgs_handle_t h, double* total_ms, int64_t* launches) {
+  if (!h || !total_ms || !launches) return fail(RTGS_ERR_INVALID_ARG, "null argument");
+  for (int i = 0; i < RTGS_PROFILE_STAGES; ++i) {
+    total_ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  EventTimer& t = h->timer;
+  hipError_t e = t.err;
+  t.err = hipSuccess;
+  for (auto& r : t.recs) {
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e == hipSuccess && r.stage < RTGS_PROFILE_STAGES) {
+      total_ms[r.stage] += ms;
+      launches[r.stage] += 1;
+    }
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.recs.clear();
+  if (e != hipSuccess) return hip_fail(e, "rtgs_profile_read");
   return RTGS_OK;
 }
 

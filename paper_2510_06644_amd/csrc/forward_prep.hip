@@ -295,13 +295,28 @@ __global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
 }  // namespace
 
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
-                               hipStream_t st) {
+                               hipStream_t st, StageTimer* tm) {
   const int tn = b.t_total + 1;
-  k_init<<<(tn + 255) / 256, 256, 0, st>>>(w.tile_count, b.t_total, w.counters);
-  if (b.b_total > 0) k_preprocess<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
-  k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, max_pairs);
-  if (b.b_total > 0) k_emit<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
-  if (b.t_total > 0) k_sort_tiles<<<b.t_total, kBlock, 0, st>>>(w);
+  {
+    Scope sc(tm, kStInit, st);
+    k_init<<<(tn + 255) / 256, 256, 0, st>>>(w.tile_count, b.t_total, w.counters);
+  }
+  if (b.b_total > 0) {
+    Scope sc(tm, kStPreprocess, st);
+    k_preprocess<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+  }
+  {
+    Scope sc(tm, kStScan, st);
+    k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, max_pairs);
+  }
+  if (b.b_total > 0) {
+    Scope sc(tm, kStEmit, st);
+    k_emit<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+  }
+  if (b.t_total > 0) {
+    Scope sc(tm, kStSort, st);
+    k_sort_tiles<<<b.t_total, kBlock, 0, st>>>(w);
+  }
   return hipGetLastError();
 }
 

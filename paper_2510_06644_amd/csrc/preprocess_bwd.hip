@@ -207,10 +207,16 @@ __global__ __launch_bounds__(256) void k_pose_reduce(Batch B, WsPtrs W) {
 
 }  // namespace
 
-hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st) {
-  if (b.b_total > 0) k_preprocess_bwd<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
-  if ((grad_flags & RTGS_GRAD_POSE) && b.n_sessions > 0)
+hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st,
+                                 StageTimer* tm) {
+  if (b.b_total > 0) {
+    Scope sc(tm, kStPreprocessBwd, st);
+    k_preprocess_bwd<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+  }
+  if ((grad_flags & RTGS_GRAD_POSE) && b.n_sessions > 0) {
+    Scope sc(tm, kStPoseReduce, st);
     k_pose_reduce<<<b.n_sessions, 256, 0, st>>>(b, w);
+  }
   return hipGetLastError();
 }
 

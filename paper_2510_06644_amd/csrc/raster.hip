@@ -90,6 +90,8 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   const int64_t end = min((int64_t)W.tile_start[tile + 1], W.cap);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   int last = -1;
+  int64_t stop = end;           // list position where the pixel stopped
+  int nblend = 0;
   bool done = !active;
   for (int64_t b0 = start; b0 < end; b0 += kBlock) {
     if (__syncthreads_and(done)) break;
@@ -110,7 +112,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         const Frag f = frag_alpha(s_r0[k], s_r1[k], pxf, pyf);
         if (f.alpha < kAlphaMin) continue;
         const float tn = T * (1.f - f.alpha);
-        if (tn < kTMin) { done = true; break; }
+        if (tn < kTMin) {
+          done = true;
+          stop = b0 + k;
+          break;
+        }
         const float w = f.alpha * T;
         const float4 col = s_r2[k];
         C0 = __builtin_fmaf(w, col.x, C0);
@@ -119,6 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         D = __builtin_fmaf(w, col.w, D);
         T = tn;
         last = (int)(b0 + k);
+        ++nblend;
       }
     }
     __syncthreads();
@@ -134,6 +141,13 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   if (S.alpha) S.alpha[c.pix] = 1.f - T;
   if (S.final_T) S.final_T[c.pix] = T;
   if (S.last_idx) S.last_idx[c.pix] = last;
+  if (S.stats) {
+    // work counts: fragments blended, list entries up to the stop (or the end
+    // of the list), list entries up to the last blended one
+    S.stats[c.pix] = nblend;
+    S.stats[hw + c.pix] = active ? (int)(min(stop + 1, end) - start) : 0;
+    S.stats[2 * hw + c.pix] = last >= 0 ? (int)(last - start + 1) : 0;
+  }
 }
 
 __global__ void k_zero(float* p, int64_t n) {
@@ -254,18 +268,24 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
 
 }  // namespace
 
-hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, int, hipStream_t st) {
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, hipStream_t st, StageTimer* tm) {
   if (b.t_total <= 0) return hipSuccess;
   const int grid = 8 * ((b.t_total + 7) / 8);
+  Scope sc(tm, kStRasterFwd, st);
   k_raster_fwd<<<grid, kBlock, 0, st>>>(b, w);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st) {
+hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st,
+                             StageTimer* tm) {
   const int64_t ng = (int64_t)b.n_total * kGrad2dStride;
-  if (ng > 0) k_zero<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(w.grad2d, ng);
+  if (ng > 0) {
+    Scope sc(tm, kStZero, st);
+    k_zero<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(w.grad2d, ng);
+  }
   if (b.t_total <= 0) return hipGetLastError();
   const int grid = 8 * ((b.t_total + 7) / 8);
+  Scope sc(tm, kStRasterBwd, st);
   if (pose_only)
     k_raster_bwd<6><<<grid, kBlock, 0, st>>>(b, w);
   else

@@ -38,6 +38,7 @@ struct SessionDev {
   float* final_T;
   int32_t* last_idx;
   uint8_t* visible;
+  int32_t* stats;       // [3][H][W] or null: blended, entries visited, entries to last
   // backward
   const float* dl_color;
   const float* dl_depth;
@@ -123,12 +124,39 @@ struct Batch {
   int32_t b_total;      // per-Gaussian blocks over all sessions
 };
 
+// Stages that the handle's profiler can bracket with HIP events.
+enum Stage {
+  kStInit = 0, kStPreprocess, kStScan, kStEmit, kStSort, kStRasterFwd, kStZero, kStRasterBwd,
+  kStPreprocessBwd, kStPoseReduce, kStPrune, kStDownsample, kStCount
+};
+
+// Records HIP events around kernel launches of the enabled stages.
+struct StageTimer {
+  virtual void begin(int stage, hipStream_t st) = 0;
+  virtual void end(int stage, hipStream_t st) = 0;
+  virtual ~StageTimer() = default;
+};
+
+struct Scope {
+  StageTimer* t;
+  int stage;
+  hipStream_t st;
+  Scope(StageTimer* t_, int s_, hipStream_t st_) : t(t_), stage(s_), st(st_) {
+    if (t) t->begin(stage, st);
+  }
+  ~Scope() {
+    if (t) t->end(stage, st);
+  }
+};
+
 // ---- launch wrappers (defined in the .hip files) ----
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
-                               hipStream_t st);
-hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, int save_state, hipStream_t st);
-hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int recompute, hipStream_t st);
-hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st);
+                               hipStream_t st, StageTimer* tm);
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, hipStream_t st, StageTimer* tm);
+hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st,
+                             StageTimer* tm);
+hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st,
+                                 StageTimer* tm);
 hipError_t launch_prune(const float* g_means, const float* g_cov3d, const uint8_t* visible,
                         const uint8_t* mask_in, int n, float lambda, float ratio,
                         uint8_t* mask_out, int* n_masked, float* score_out, uint32_t* scratch,

@@ -28,6 +28,10 @@ RTGS_ERR_CAPACITY = -2
 RTGS_ERR_HIP = -3
 RTGS_ERR_WORKSPACE = -4
 RTGS_FWD_SAVE_STATE = 1
+RTGS_FWD_STATS = 2
+RTGS_PROFILE_STAGES = 16
+STAGES = ("init", "preprocess", "scan", "emit", "sort", "raster_fwd", "zero", "raster_bwd",
+          "preprocess_bwd", "pose_reduce")
 RTGS_GRAD_POSE = 1
 RTGS_GRAD_MAP = 2
 RTGS_GRAD_COV3D = 4
@@ -40,7 +44,8 @@ EXPORTS = (
     "rtgs_last_error", "rtgs_create", "rtgs_destroy", "rtgs_workspace_size",
     "rtgs_workspace_size_batched", "render_fwd", "render_bwd", "render_fwd_batched",
     "render_bwd_batched", "prune_by_grad", "downsample_mask", "rtgs_downsample_log2_ratio",
-    "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum",
+    "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum", "rtgs_profile_enable",
+    "rtgs_profile_read",
 )
 
 vp = ctypes.c_void_p
@@ -63,7 +68,7 @@ class CCamera(ctypes.Structure):
 class CSession(ctypes.Structure):
     _fields_ = [("g", CGaussians), ("cam", CCamera), ("pixel_mask", vp),
                 ("color", vp), ("depth", vp), ("alpha", vp), ("final_T", vp), ("last_idx", vp),
-                ("visible", vp), ("dL_dcolor", vp), ("dL_ddepth", vp), ("dL_dalpha", vp),
+                ("visible", vp), ("stats", vp), ("dL_dcolor", vp), ("dL_ddepth", vp), ("dL_dalpha", vp),
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
                 ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_cov3d", vp)]
 
@@ -109,6 +114,9 @@ def lib():
             L.rtgs_debug_stage.argtypes = [vp, vp, vp, i32, i64, vp, u64, vp, vp, vp, vp, i64,
                                            vp]
             L.rtgs_selftest_wave_sum.argtypes = [vp, vp, i32, vp]
+            L.rtgs_profile_enable.argtypes = [vp, i32]
+            L.rtgs_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(i64)]
             for name in EXPORTS:
                 getattr(L, name).restype = getattr(L, name).restype or i32
             L.rtgs_last_error.restype = ctypes.c_char_p
@@ -257,6 +265,7 @@ def make_sessions(items):
         s.g = _gauss(*sc, it.get("gauss_mask"))
         s.cam = _cam(it["cam"], it["viewmat"])
         for name in ("pixel_mask", "color", "depth", "alpha", "final_T", "last_idx", "visible",
+                     "stats",
                      "dL_dcolor", "dL_ddepth", "dL_dalpha", "g_means", "g_log_scales", "g_quats",
                      "g_opacity_logits", "g_colors", "g_pose6", "g_cov3d"):
             t = it.get(name)
@@ -323,6 +332,22 @@ def rtgs_debug_stage(ns, widths, heights, pair_capacity, ws, stage=None, rect=No
                                   ws.numel() * ws.element_size(), _p(stage), _p(rect),
                                   _p(ranges), _p(ids), 0 if ids is None else ids.numel(),
                                   _stream(stream)))
+
+
+def rtgs_profile_enable(handle, stages):
+    """Enable HIP-event timing for the named stages (iterable of names)."""
+    mask = 0
+    for s in stages:
+        mask |= 1 << STAGES.index(s)
+    _check(lib().rtgs_profile_enable(handle.ptr, mask))
+
+
+def rtgs_profile_read(handle):
+    """{stage: (total_ms, launches)} for stages with launches; clears."""
+    ms = (ctypes.c_double * RTGS_PROFILE_STAGES)()
+    cnt = (i64 * RTGS_PROFILE_STAGES)()
+    _check(lib().rtgs_profile_read(handle.ptr, ms, cnt))
+    return {STAGES[i]: (ms[i], int(cnt[i])) for i in range(len(STAGES)) if cnt[i] > 0}
 
 
 def rtgs_selftest_wave_sum(inp, out, stream=None):
