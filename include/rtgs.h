@@ -60,7 +60,7 @@ extern "C" {
                                      `stats`; render_fwd_batched only)         */
 
 /* ---- render_bwd flags ---- */
-#define RTGS_GRAD_POSE        1   /* write g_pose6                             */
+#define RTGS_GRAD_POSE        1   /* write g_pose6 and/or g_viewmat            */
 #define RTGS_GRAD_MAP         2   /* write the five per-Gaussian gradients     */
 #define RTGS_GRAD_COV3D       4   /* also write g_cov3d (needs RTGS_GRAD_MAP)  */
 #define RTGS_GRAD_RECOMPUTE_STATE 8 /* final_T/last_idx were not saved: the
@@ -125,6 +125,7 @@ typedef struct {
   float* g_opacity_logits;     /* [n] */
   float* g_colors;             /* [n][3] */
   float* g_pose6;              /* [6] (rho, phi) */
+  float* g_viewmat;            /* [12] dL/d(viewmat entries), row-major 3x4 */
   float* g_cov3d;              /* [n][6] (xx, xy, xz, yy, yz, zz) */
 } rtgs_session;
 
@@ -174,7 +175,12 @@ int32_t render_fwd(rtgs_handle_t h, const rtgs_gaussians* g,
  * per-pixel gradients merged per Gaussian, then pushed through the projection
  * to the map parameters and to the pose.  The pose gradient is the derivative
  * with respect to xi = (rho, phi) of Exp(xi) * viewmat at xi = 0 (left
- * perturbation; rho translation, phi rotation).  g_cov3d is dL/dSigma of the
+ * perturbation; rho translation, phi rotation).  g_viewmat is the gradient
+ * with respect to the 12 entries of viewmat taken as independent variables
+ * (dL/dR = sum_k dL/dp_k mu_k^T + covariance term, dL/dt = sum_k dL/dp_k),
+ * from which g_pose6 follows: rho part dL/dt, phi part the axial vector of
+ * the antisymmetric part of dL/dR R^T + dL/dt t^T.  With RTGS_GRAD_POSE at
+ * least one of g_pose6, g_viewmat must be non-NULL.  g_cov3d is dL/dSigma of the
  * world-frame covariance (symmetric, stored as xx, xy, xz, yy, yz, zz), the
  * input of the importance score.  dL_dalpha may be NULL.
  * The arguments g, cam, pixel_mask, ws and pair_capacity must be those of the
@@ -188,7 +194,7 @@ int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g,
                    const float* dL_dalpha, int32_t grad_flags,
                    float* g_means, float* g_log_scales, float* g_quats,
                    float* g_opacity_logits, float* g_colors, float* g_pose6,
-                   float* g_cov3d, void* stream);
+                   float* g_viewmat, float* g_cov3d, void* stream);
 
 /* Batched forward / backward over n_sessions (<= RTGS_MAX_SESSIONS): one
  * launch per stage for all sessions, one tile space and one sort.  `sessions`
@@ -265,7 +271,8 @@ int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width,
 
 /* Stage profiler (HIP events on the stream each kernel is launched on).
  * Stages: 0 init, 1 preprocess, 2 scan, 3 emit, 4 sort, 5 raster_fwd,
- * 6 zero, 7 raster_bwd, 8 preprocess_bwd, 9 pose_reduce.  After
+ * 6 (unused), 7 raster_bwd, 8 preprocess_bwd, 9 pose_reduce, 10 bin_count,
+ * 11 merge.  After
  * rtgs_profile_enable(h, mask) every launch of a stage whose bit is set is
  * bracketed by two events; rtgs_profile_read waits for them and returns per
  * stage the summed milliseconds and the launch count (HOST arrays of

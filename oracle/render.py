@@ -58,6 +58,7 @@ class Grads:
     colors: torch.Tensor
     pose: torch.Tensor          # [6] (rho, phi)
     cov3d: torch.Tensor         # [N,3,3] dL/dSigma (world frame)
+    viewmat: torch.Tensor       # [3,4] dL/d(view-matrix entries)
     stage2d: dict               # u, v, a, b, c, o, z: [N]; rgb: [N,3]
 
 
@@ -134,7 +135,7 @@ def render_with_grads(scene, viewmat, cam, g_color, g_depth, g_alpha=None,
     `pixels` is given).  Returns (RenderOut, Grads)."""
     params = [_t(x).clone().requires_grad_(True) for x in scene]
     xi = torch.zeros(6, dtype=F64, requires_grad=True)
-    vm = _t(viewmat)
+    vm = _t(viewmat).clone().requires_grad_(True)
     w, h = cam[0], cam[1]
     gm = None if gauss_mask is None else torch.as_tensor(gauss_mask)
     cov3d, opac, proj = _stage(params, vm, cam, gm, xi)
@@ -185,7 +186,7 @@ def render_with_grads(scene, viewmat, cam, g_color, g_depth, g_alpha=None,
                     last_id.reshape(shape), n_bl.reshape(shape),
                     flags.reshape(shape), proj)
     g = Grads(params[0].grad, params[1].grad, params[2].grad, params[3].grad,
-              params[4].grad, xi.grad, cov3d.grad, stage_grads)
+              params[4].grad, xi.grad, cov3d.grad, vm.grad, stage_grads)
     return out, g
 
 

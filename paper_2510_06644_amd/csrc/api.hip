@@ -36,15 +36,13 @@ constexpr uint64_t kAlign = 256;
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-struct Geometry {
-  int64_t n_total = 0, t_total = 0, b_total = 0, px_total = 0;
-};
-
 int64_t tiles_of(int w, int h) {
   return (int64_t)((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
 }
 
 int64_t blocks_of(int n) { return (n + kGaussPerBlock - 1) / kGaussPerBlock; }
+
+int64_t chunks_of(int n) { return (n + kChunk - 1) / kChunk; }
 
 }  // namespace
 
@@ -116,7 +114,7 @@ struct rtgs_context {
 
 namespace rtgs {
 
-WsLayout make_layout(int64_t n, int64_t t, int64_t b, int64_t cap, int64_t px) {
+WsLayout make_layout(const Counts& c, int64_t cap) {
   WsLayout L{};
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -124,26 +122,32 @@ WsLayout make_layout(int64_t n, int64_t t, int64_t b, int64_t cap, int64_t px) {
     off = align_up(off + bytes);
     return at;
   };
+  const uint64_t n = (uint64_t)c.n_total, t = (uint64_t)c.t_total;
   L.table = take(sizeof(SessionDev) * RTGS_MAX_SESSIONS);
   L.counters = take(64);
-  L.rec0 = take(16 * (uint64_t)n);
-  L.rec1 = take(16 * (uint64_t)n);
-  L.rec2 = take(16 * (uint64_t)n);
-  L.ext = take(16 * (uint64_t)n);
-  L.rect = take(16 * (uint64_t)n);
-  L.grad2d = take(4 * (uint64_t)kGrad2dStride * n);
-  L.pose_part = take(64 * (uint64_t)b);
-  L.tile_count = take(4 * (uint64_t)(t + 1));
-  L.tile_start = take(4 * (uint64_t)(t + 1));
-  L.tile_cursor = take(4 * (uint64_t)(t + 1));
+  L.rec0 = take(16 * n);
+  L.rec1 = take(16 * n);
+  L.rec2 = take(16 * n);
+  L.ext = take(16 * n);
+  L.rect = take(16 * n);
+  L.cnt = take(4 * n);
+  L.goff = take(4 * n);
+  L.grad2d = take(40 * n);
+  L.pose_part = take(128 * (uint64_t)c.b_total);
+  L.chunk_total = take(4 * (uint64_t)(c.c_total + 1));
+  L.chunk_off = take(4 * (uint64_t)(c.c_total + 1));
+  L.hist = take(4 * (uint64_t)c.h_total);
+  L.tile_count = take(4 * (t + 1));
+  L.tile_start = take(4 * (t + 1));
   L.keys = take(8 * (uint64_t)cap);
   L.ids = take(4 * (uint64_t)cap);
-  L.state_t = take(4 * (uint64_t)px);
-  L.state_last = take(4 * (uint64_t)px);
+  L.partial = take(4 * 10 * (uint64_t)cap);
+  L.state_t = take(4 * (uint64_t)c.px_total);
+  L.state_last = take(4 * (uint64_t)c.px_total);
   L.total = off;
-  L.n_total = n;
-  L.t_total = t;
-  L.b_total = b;
+  L.n_total = c.n_total;
+  L.t_total = c.t_total;
+  L.b_total = c.b_total;
   L.cap = cap;
   return L;
 }
@@ -158,13 +162,18 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.rec2 = reinterpret_cast<float4*>(base + L.rec2);
   w.ext = reinterpret_cast<float4*>(base + L.ext);
   w.rect = reinterpret_cast<int4*>(base + L.rect);
+  w.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
+  w.goff = reinterpret_cast<uint32_t*>(base + L.goff);
   w.grad2d = reinterpret_cast<float*>(base + L.grad2d);
   w.pose_part = reinterpret_cast<double*>(base + L.pose_part);
+  w.chunk_total = reinterpret_cast<uint32_t*>(base + L.chunk_total);
+  w.chunk_off = reinterpret_cast<uint32_t*>(base + L.chunk_off);
+  w.hist = reinterpret_cast<uint32_t*>(base + L.hist);
   w.tile_count = reinterpret_cast<uint32_t*>(base + L.tile_count);
   w.tile_start = reinterpret_cast<uint32_t*>(base + L.tile_start);
-  w.tile_cursor = reinterpret_cast<uint32_t*>(base + L.tile_cursor);
   w.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
   w.ids = reinterpret_cast<uint32_t*>(base + L.ids);
+  w.partial = reinterpret_cast<float*>(base + L.partial);
   w.state_t = reinterpret_cast<float*>(base + L.state_t);
   w.state_last = reinterpret_cast<int32_t*>(base + L.state_last);
   w.cap = L.cap;
@@ -175,19 +184,27 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
 
 namespace {
 
-int32_t geometry(const int32_t* n, const int32_t* w, const int32_t* h, int32_t ns, Geometry& g) {
+int32_t geometry(const int32_t* n, const int32_t* w, const int32_t* h, int32_t ns, Counts& g) {
   if (ns < 1 || ns > RTGS_MAX_SESSIONS)
     return fail(RTGS_ERR_INVALID_ARG, "n_sessions %d outside [1, %d]", ns, RTGS_MAX_SESSIONS);
   for (int s = 0; s < ns; ++s) {
     if (n[s] < 0) return fail(RTGS_ERR_INVALID_ARG, "session %d: n = %d < 0", s, n[s]);
     if (w[s] <= 0 || h[s] <= 0)
       return fail(RTGS_ERR_INVALID_ARG, "session %d: image %d x %d", s, w[s], h[s]);
+    const int64_t t = tiles_of(w[s], h[s]);
+    if (t > kMaxTilesPerSession)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: %lld tiles > %d (image too large)", s,
+                  (long long)t, kMaxTilesPerSession);
     g.n_total += n[s];
-    g.t_total += tiles_of(w[s], h[s]);
+    g.t_total += t;
     g.b_total += blocks_of(n[s]);
+    g.c_total += chunks_of(n[s]);
+    g.h_total += chunks_of(n[s]) * t;
     g.px_total += (int64_t)w[s] * h[s];
+    if (t > g.t_max) g.t_max = t;
   }
-  if (g.n_total > INT32_MAX / 2 || g.t_total > INT32_MAX / 2 || g.px_total > INT32_MAX / 2)
+  if (g.n_total > INT32_MAX / 2 || g.t_total > INT32_MAX / 2 || g.px_total > INT32_MAX / 2 ||
+      g.h_total > INT32_MAX)
     return fail(RTGS_ERR_INVALID_ARG, "batch too large");
   return RTGS_OK;
 }
@@ -220,8 +237,8 @@ int32_t check_session(const rtgs_session& s, int idx, bool fwd, int32_t flags) {
     if ((flags & RTGS_GRAD_MAP) && g.n > 0 &&
         (!s.g_means || !s.g_log_scales || !s.g_quats || !s.g_opacity_logits || !s.g_colors))
       return fail(RTGS_ERR_INVALID_ARG, "session %d: null map gradient output", idx);
-    if ((flags & RTGS_GRAD_POSE) && !s.g_pose6)
-      return fail(RTGS_ERR_INVALID_ARG, "session %d: null pose gradient output", idx);
+    if ((flags & RTGS_GRAD_POSE) && !s.g_pose6 && !s.g_viewmat)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: POSE needs g_pose6 and/or g_viewmat", idx);
     if ((flags & RTGS_GRAD_COV3D) && (!(flags & RTGS_GRAD_MAP) || (g.n > 0 && !s.g_cov3d)))
       return fail(RTGS_ERR_INVALID_ARG, "session %d: COV3D needs MAP and g_cov3d", idx);
   }
@@ -236,8 +253,8 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
   hipError_t e = hipEventSynchronize(h->ring_ev[slot]);
   if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
   SessionDev* t = h->h_ring + (size_t)slot * RTGS_MAX_SESSIONS;
-  int32_t gbase = 0, bbase = 0, tbase = 0;
-  int64_t pbase = 0;
+  int32_t gbase = 0, bbase = 0, tbase = 0, cbase = 0, tmax = 0;
+  int64_t pbase = 0, hbase = 0;
   for (int i = 0; i < ns; ++i) {
     const rtgs_session& s = ss[i];
     SessionDev d{};
@@ -261,6 +278,8 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
     d.gauss_base = gbase;
     d.block_base = bbase;
     d.tile_base = tbase;
+    d.chunk_base = cbase;
+    d.hist_base = hbase;
     if (fwd) {
       d.color = s.color;
       d.depth = s.depth;
@@ -289,11 +308,16 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
         d.g_cov3d = (flags & RTGS_GRAD_COV3D) ? s.g_cov3d : nullptr;
       }
       d.g_pose6 = (flags & RTGS_GRAD_POSE) ? s.g_pose6 : nullptr;
+      d.g_viewmat = (flags & RTGS_GRAD_POSE) ? s.g_viewmat : nullptr;
     }
     t[i] = d;
     gbase += s.g.n;
     bbase += (int32_t)blocks_of(s.g.n);
-    tbase += (int32_t)tiles_of(s.cam.width, s.cam.height);
+    const int32_t ts = (int32_t)tiles_of(s.cam.width, s.cam.height);
+    tbase += ts;
+    cbase += (int32_t)chunks_of(s.g.n);
+    hbase += chunks_of(s.g.n) * ts;
+    if (ts > tmax) tmax = ts;
     pbase += (int64_t)s.cam.width * s.cam.height;
   }
   e = hipMemcpyAsync(w.table, t, sizeof(SessionDev) * ns, hipMemcpyHostToDevice, st);
@@ -305,6 +329,8 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
   B.n_total = gbase;
   B.t_total = tbase;
   B.b_total = bbase;
+  B.c_total = cbase;
+  B.t_max = tmax;
   return RTGS_OK;
 }
 
@@ -322,11 +348,11 @@ int32_t prepare(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws, u
     wd[i] = ss[i].cam.width;
     ht[i] = ss[i].cam.height;
   }
-  Geometry g;
+  Counts g;
   r = geometry(n.data(), wd.data(), ht.data(), ns, g);
   if (r) return r;
   if (!ws) return fail(RTGS_ERR_INVALID_ARG, "null workspace");
-  L = make_layout(g.n_total, g.t_total, g.b_total, cap, g.px_total);
+  L = make_layout(g, cap);
   if (ws_bytes < L.total)
     return fail(RTGS_ERR_WORKSPACE, "workspace %llu bytes < required %llu",
                 (unsigned long long)ws_bytes, (unsigned long long)L.total);
@@ -397,10 +423,10 @@ int32_t rtgs_workspace_size_batched(const int32_t* n, const int32_t* width, cons
   if (!n || !width || !height || !bytes) return fail(RTGS_ERR_INVALID_ARG, "null argument");
   int32_t r = check_cap(pair_capacity);
   if (r) return r;
-  Geometry g;
+  Counts g;
   r = geometry(n, width, height, n_sessions, g);
   if (r) return r;
-  *bytes = make_layout(g.n_total, g.t_total, g.b_total, pair_capacity, g.px_total).total;
+  *bytes = make_layout(g, pair_capacity).total;
   return RTGS_OK;
 }
 
@@ -483,7 +509,8 @@ int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g, const rtgs_camera* 
                    const float* final_T, const int32_t* last_idx, const float* dL_dcolor,
                    const float* dL_ddepth, const float* dL_dalpha, int32_t grad_flags,
                    float* g_means, float* g_log_scales, float* g_quats, float* g_opacity_logits,
-                   float* g_colors, float* g_pose6, float* g_cov3d, void* stream) {
+                   float* g_colors, float* g_pose6, float* g_viewmat, float* g_cov3d,
+                   void* stream) {
   if (!g || !cam) return fail(RTGS_ERR_INVALID_ARG, "null gaussians or camera");
   rtgs_session s = single(g, cam, pixel_mask);
   s.final_T = const_cast<float*>(final_T);
@@ -497,6 +524,7 @@ int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g, const rtgs_camera* 
   s.g_opacity_logits = g_opacity_logits;
   s.g_colors = g_colors;
   s.g_pose6 = g_pose6;
+  s.g_viewmat = g_viewmat;
   s.g_cov3d = g_cov3d;
   return render_bwd_batched(h, &s, 1, ws, ws_bytes, cap, grad_flags, stream);
 }
@@ -580,10 +608,10 @@ int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width, const int32_t* 
   if (!n || !width || !height || !ws) return fail(RTGS_ERR_INVALID_ARG, "null argument");
   int32_t r = check_cap(pair_capacity);
   if (r) return r;
-  Geometry g;
+  Counts g;
   r = geometry(n, width, height, n_sessions, g);
   if (r) return r;
-  const WsLayout L = make_layout(g.n_total, g.t_total, g.b_total, pair_capacity, g.px_total);
+  const WsLayout L = make_layout(g, pair_capacity);
   if (ws_bytes < L.total) return fail(RTGS_ERR_WORKSPACE, "workspace too small");
   const WsPtrs w = ws_ptrs(const_cast<void*>(ws), L);
   Batch B{};

@@ -7,12 +7,18 @@
 //    (56 B in, 64 B out per Gaussian), and float64 lets the raster kernels see
 //    pixel-space centres split as hi + lo float32 parts, so their float32
 //    compositing matches the float64 definition far below 1e-4;
-//  * binning is a counting sort by tile: atomics count pairs per tile, one
-//    scan turns counts into tile ranges, a second pass scatters
-//    (depth bits, id) keys into the ranges, then one workgroup per tile sorts
-//    its range in LDS (bitonic network on 64-bit keys; ranges beyond the LDS
-//    capacity sort in place in global memory).  No host sync is needed: the
-//    pair total stays on the device and a capacity overflow only drops pairs.
+//  * binning is a counting sort by tile without global atomics (device-scope
+//    atomics cross the XCDs and serialise): each workgroup takes a chunk of
+//    2048 Gaussians and counts its (tile, Gaussian) pairs per tile in an LDS
+//    histogram; a column scan over chunks turns the counts into per
+//    (chunk, tile) offsets; a second pass over the chunk scatters
+//    (depth bits, id) keys through LDS-atomic cursors.  The same pass writes
+//    each Gaussian's first slot in Gaussian-major pair order, which the
+//    backward uses to merge gradients without atomics.  Then one workgroup
+//    per tile sorts its range in LDS (bitonic network on 64-bit keys; ranges
+//    beyond the LDS capacity sort in place in global memory).  No host sync:
+//    the pair total stays on the device and a capacity overflow only drops
+//    pairs.
 #include "rtgs_internal.h"
 
 namespace rtgs {
@@ -21,10 +27,8 @@ namespace {
 constexpr int kSortLds = 4096;    // 64-bit keys sorted in LDS per tile (32 KB)
 constexpr int kScanThreads = 1024;
 
-__global__ void k_init(uint32_t* tile_count, int t_total, long long* counters) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i <= t_total) tile_count[i] = 0u;
-  if (i < 8) counters[i] = 0;
+__global__ void k_init(long long* counters) {
+  if (threadIdx.x < 8) counters[threadIdx.x] = 0;
 }
 
 struct Proj {
@@ -143,22 +147,107 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
   W.rect[gid] = rect;
   const bool vis = rect.z >= rect.x;
   if (S.visible) S.visible[li] = vis ? 1 : 0;
-  if (!vis) return;
-  uint32_t* cnt = W.tile_count + S.tile_base;
-  for (int ty = rect.y; ty <= rect.w; ++ty)
-    for (int tx = rect.x; tx <= rect.z; ++tx) atomicAdd(&cnt[ty * S.tiles_x + tx], 1u);
+  W.cnt[gid] = vis ? (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1)) : 0u;
 }
 
-// Exclusive scan of the per-tile counts into tile_start[0..T]; resets the
-// scatter cursors; publishes the pair total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_total,
-                                                             unsigned long long* max_pairs) {
-  __shared__ uint32_t part[kScanThreads];
+// In-chunk exclusive offsets of the Gaussians' tile counts, in local index
+// order, into s_off[0..kChunk); returns the chunk's pair total.  Local index
+// i = j * 256 + thread for round j.
+__device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, uint32_t* s_off,
+                                  uint32_t* s_wave) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int j = 0; j < kChunk / kBlock; ++j) {
+    const int i = j * kBlock + (int)threadIdx.x;
+    const int li = c * kChunk + i;
+    const uint32_t n = li < S.n ? W.cnt[S.gauss_base + li] : 0u;
+    uint32_t x = n;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      before += q < wave ? s_wave[q] : 0u;
+      tot += s_wave[q];
+    }
+    s_off[i] = carry + before + x - n;
+    carry += tot;
+    __syncthreads();
+  }
+  return carry;
+}
+
+// Pair m of the chunk -> (local Gaussian index, tile index within the session).
+__device__ __forceinline__ int chunk_pair(const SessionDev& S, const WsPtrs& W, int c,
+                                          const uint32_t* s_off, uint32_t m, int& tile) {
+  int lo = 0, hi = kChunk - 1;          // last i with s_off[i] <= m
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= m) lo = mid; else hi = mid - 1;
+  }
+  const int gid = S.gauss_base + c * kChunk + lo;
+  const int4 r = W.rect[gid];
+  const int w = r.z - r.x + 1;
+  const int k = (int)(m - s_off[lo]);
+  tile = (r.y + k / w) * S.tiles_x + (r.x + k % w);
+  return lo;
+}
+
+// Per chunk of 2048 Gaussians: pair counts per tile of the session (LDS
+// histogram), and the chunk's pair total.
+__global__ __launch_bounds__(kBlock) void k_chunk_hist(Batch B, WsPtrs W) {
+  extern __shared__ uint32_t s_hist[];
+  __shared__ uint32_t s_off[kChunk];
+  __shared__ uint32_t s_wave[kBlock / 64];
+  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                             [](const SessionDev& x) { return x.chunk_base; });
+  const SessionDev& S = B.sess[s];
+  const int c = (int)blockIdx.x - S.chunk_base;
+  const int ts = S.tiles_x * S.tiles_y;
+  for (int t = threadIdx.x; t < ts; t += kBlock) s_hist[t] = 0u;
+  const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
+  // pairs are dealt evenly over the threads, whatever the Gaussians' sizes
+  for (uint32_t m = threadIdx.x; m < total; m += kBlock) {
+    int tile;
+    chunk_pair(S, W, c, s_off, m, tile);
+    atomicAdd(&s_hist[tile], 1u);
+  }
+  __syncthreads();
+  uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
+  for (int t = threadIdx.x; t < ts; t += kBlock) h[t] = s_hist[t];
+  if (threadIdx.x == 0) W.chunk_total[blockIdx.x] = total;
+}
+
+// One thread per tile: exclusive scan of its counts over the session's
+// chunks (in place), and the tile's pair count.
+__global__ __launch_bounds__(kBlock) void k_tile_scan(Batch B, WsPtrs W) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= B.t_total) return;
+  const int s = find_session(B.sess, B.n_sessions, t,
+                             [](const SessionDev& x) { return x.tile_base; });
+  const SessionDev& S = B.sess[s];
+  const int ts = S.tiles_x * S.tiles_y;
+  const int nc = (S.n + kChunk - 1) / kChunk;
+  uint32_t* h = W.hist + S.hist_base + (t - S.tile_base);
+  uint32_t run = 0;
+  for (int c = 0; c < nc; ++c) {
+    const uint32_t v = h[(int64_t)c * ts];
+    h[(int64_t)c * ts] = run;
+    run += v;
+  }
+  W.tile_count[t] = run;
+}
+
+// Exclusive scan of n values in[0..n) into out[0..n]; out[n] = total.
+__device__ uint32_t block_scan_1024(const uint32_t* in, uint32_t* out, int n, uint32_t* part) {
   const int tid = threadIdx.x;
-  const int per = (t_total + kScanThreads - 1) / kScanThreads;
-  const int beg = min(tid * per, t_total), end = min(beg + per, t_total);
+  const int per = (n + kScanThreads - 1) / kScanThreads;
+  const int beg = min(tid * per, n), end = min(beg + per, n);
   uint32_t sum = 0;
-  for (int i = beg; i < end; ++i) sum += W.tile_count[i];
+  for (int i = beg; i < end; ++i) sum += in[i];
   part[tid] = sum;
   __syncthreads();
   for (int off = 1; off < kScanThreads; off <<= 1) {
@@ -167,39 +256,61 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_tot
     part[tid] += add;
     __syncthreads();
   }
-  uint32_t run = part[tid] - sum;    // exclusive prefix of this thread's range
+  uint32_t run = part[tid] - sum;
   for (int i = beg; i < end; ++i) {
-    W.tile_start[i] = run;
-    run += W.tile_count[i];
-    W.tile_cursor[i] = 0u;
+    const uint32_t v = in[i];
+    out[i] = run;
+    run += v;
   }
-  if (tid == kScanThreads - 1) {
-    const uint32_t total = part[tid];
-    W.tile_start[t_total] = total;
+  const uint32_t total = part[kScanThreads - 1];
+  if (tid == 0) out[n] = total;
+  __syncthreads();
+  return total;
+}
+
+// Tile ranges (scan of the per-tile counts), chunk offsets (scan of the
+// per-chunk totals), and the pair total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_total, int c_total,
+                                                             unsigned long long* max_pairs) {
+  __shared__ uint32_t part[kScanThreads];
+  const uint32_t total = block_scan_1024(W.tile_count, W.tile_start, t_total, part);
+  block_scan_1024(W.chunk_total, W.chunk_off, c_total, part);
+  if (threadIdx.x == 0) {
     W.counters[0] = (long long)total;
     atomicMax(max_pairs, (unsigned long long)total);
   }
 }
 
-// Scatter (depth bits << 32 | id) keys into each tile's range.
-__global__ __launch_bounds__(kGaussPerBlock) void k_emit(Batch B, WsPtrs W) {
+// Per chunk: each Gaussian's first Gaussian-major slot, then
+// (depth bits << 32 | id) keys scattered into the tile ranges through LDS
+// cursors, pairs dealt evenly over the threads.
+__global__ __launch_bounds__(kBlock) void k_emit(Batch B, WsPtrs W) {
+  extern __shared__ uint32_t s_cur[];
+  __shared__ uint32_t s_off[kChunk];
+  __shared__ uint32_t s_wave[kBlock / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
-                             [](const SessionDev& x) { return x.block_base; });
+                             [](const SessionDev& x) { return x.chunk_base; });
   const SessionDev& S = B.sess[s];
-  const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
-  if (li >= S.n) return;
-  const int gid = S.gauss_base + li;
-  const int4 rect = W.rect[gid];
-  if (rect.z < rect.x) return;
-  const unsigned long long key =
-      ((unsigned long long)__float_as_uint(W.rec2[gid].w) << 32) | (unsigned)gid;
-  const int tb = S.tile_base;
-  for (int ty = rect.y; ty <= rect.w; ++ty)
-    for (int tx = rect.x; tx <= rect.z; ++tx) {
-      const int t = tb + ty * S.tiles_x + tx;
-      const uint32_t pos = W.tile_start[t] + atomicAdd(&W.tile_cursor[t], 1u);
-      if ((int64_t)pos < W.cap) W.keys[pos] = key;
-    }
+  const int c = (int)blockIdx.x - S.chunk_base;
+  const int ts = S.tiles_x * S.tiles_y;
+  const uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
+  for (int t = threadIdx.x; t < ts; t += kBlock) s_cur[t] = W.tile_start[S.tile_base + t] + h[t];
+  const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
+  const uint32_t base = W.chunk_off[blockIdx.x];
+  for (int j = 0; j < kChunk / kBlock; ++j) {
+    const int i = j * kBlock + (int)threadIdx.x;
+    const int li = c * kChunk + i;
+    if (li < S.n) W.goff[S.gauss_base + li] = base + s_off[i];
+  }
+  for (uint32_t m = threadIdx.x; m < total; m += kBlock) {
+    int tile;
+    const int i = chunk_pair(S, W, c, s_off, m, tile);
+    const int gid = S.gauss_base + c * kChunk + i;
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint(W.rec2[gid].w) << 32) | (unsigned)gid;
+    const uint32_t pos = atomicAdd(&s_cur[tile], 1u);
+    if ((int64_t)pos < W.cap) W.keys[pos] = key;
+  }
 }
 
 // Bitonic sorting network on a[0..n) (ascending), all merges in the "flip"
@@ -296,22 +407,27 @@ __global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
 
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
                                hipStream_t st, StageTimer* tm) {
-  const int tn = b.t_total + 1;
+  const size_t lds = sizeof(uint32_t) * (size_t)(b.t_max > 0 ? b.t_max : 1);
   {
     Scope sc(tm, kStInit, st);
-    k_init<<<(tn + 255) / 256, 256, 0, st>>>(w.tile_count, b.t_total, w.counters);
+    k_init<<<1, 64, 0, st>>>(w.counters);
   }
   if (b.b_total > 0) {
     Scope sc(tm, kStPreprocess, st);
     k_preprocess<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
   }
+  if (b.c_total > 0) {
+    Scope sc(tm, kStBinCount, st);
+    k_chunk_hist<<<b.c_total, kBlock, lds, st>>>(b, w);
+  }
   {
     Scope sc(tm, kStScan, st);
-    k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, max_pairs);
+    k_tile_scan<<<(b.t_total + kBlock - 1) / kBlock, kBlock, 0, st>>>(b, w);
+    k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, b.c_total, max_pairs);
   }
-  if (b.b_total > 0) {
+  if (b.c_total > 0) {
     Scope sc(tm, kStEmit, st);
-    k_emit<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+    k_emit<<<b.c_total, kBlock, lds, st>>>(b, w);
   }
   if (b.t_total > 0) {
     Scope sc(tm, kStSort, st);

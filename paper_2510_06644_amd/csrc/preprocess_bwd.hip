@@ -4,8 +4,10 @@
 // the camera-pose gradient dL/dP (the paper's Preprocessing Engine and
 // Merging Tree, Secs. 5.1 and 5.4).
 //
-// One thread per Gaussian in float64 (HBM bound: ~48 B of 2D gradient and
-// 56 B of parameters in, up to 80 B out).  The pose partials are summed per
+// One thread per Gaussian in float64 (HBM bound: 40 B of merged 2D gradient
+// per (tile, Gaussian) pair and 56 B of parameters in, up to 80 B out).  The
+// Gaussian's 2D gradient is the fixed-order sum of its pair slots (the
+// tile -> Gaussian merge, the role of the paper's Stage Buffer).  The pose partials are summed per
 // workgroup in LDS, then per session in a fixed order by a second kernel, so
 // the pose reduction adds no float atomics of its own.
 //
@@ -16,30 +18,73 @@
 //     dL/dA = 2 G' A,  dL/dM = T^T dL/dA,  dL/dT = dL/dA M^T
 //   T = J W:  dL/dJ = dL/dT W^T,  dL/dW|cov = J^T dL/dT
 //   J(p), u(p), v(p), z: dL/dp;  dL/dmu = W^T dL/dp
-//   pose (left perturbation at xi = 0): dL/drho = dL/dp,
-//     dL/dphi = p x dL/dp + vee(W (dL/dW)^T)
+//   view matrix [W | t]: dL/dW = dL/dW|cov + dL/dp mu^T, dL/dt = dL/dp,
+//     summed over Gaussians; the pose (left perturbation at xi = 0) is then
+//     dL/drho = dL/dt and dL/dphi = the axial vector of the antisymmetric
+//     part of A = dL/dW W^T + dL/dt t^T: (A21 - A12, A02 - A20, A10 - A01)
 //   M -> scales (dL/dl = s dL/ds) and R(q/|q|) -> quaternion.
 #include "rtgs_internal.h"
 
 namespace rtgs {
 namespace {
 
+// Tile -> Gaussian merge: 16 lanes (one DPP row) per Gaussian sum its pair
+// slots, strided, then a fixed DPP tree; lane 15 of the row stores the NV
+// totals.  Balanced however many tiles a Gaussian touches, deterministic.
+template <int NV>
+__global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
+  const int gid = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int sub = threadIdx.x & 15;
+  float acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.f;
+  if (gid < B.n_total) {
+    const int64_t first = W.goff[gid], n = W.cnt[gid];
+    for (int64_t k = sub; k < n && first + k < W.cap; k += 16) {
+      const float* p = W.partial + (first + k) * NV;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += p[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    float v = acc[i];
+    v += dpp_f<kDppRowShr1, 0xf, true>(v);
+    v += dpp_f<kDppRowShr2, 0xf, true>(v);
+    v += dpp_f<kDppRowShr4, 0xf, true>(v);
+    v += dpp_f<kDppRowShr8, 0xf, true>(v);
+    acc[i] = v;
+  }
+  if (sub == 15 && gid < B.n_total) {
+    float* d = W.grad2d + (int64_t)gid * 10;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) d[i] = acc[i];
+  }
+}
+
 __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPtrs W, int flags) {
-  __shared__ double s_red[kGaussPerBlock / 64][6];
+  __shared__ double s_red[kGaussPerBlock / 64][12];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.block_base; });
   const SessionDev& S = B.sess[s];
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
   const bool want_map = (flags & RTGS_GRAD_MAP) != 0;
   const bool want_cov = (flags & RTGS_GRAD_COV3D) != 0 && S.g_cov3d != nullptr;
-  double pose[6] = {0, 0, 0, 0, 0, 0};
+  double pose[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // dL/dW (9), dL/dt (3)
   if (li < S.n) {
     const int gid = S.gauss_base + li;
     const int4 rect = W.rect[gid];
     double gm[3] = {0, 0, 0}, gl[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go_eta = 0;
     double gcol[3] = {0, 0, 0}, gsig[6] = {0, 0, 0, 0, 0, 0};
     if (rect.z >= rect.x) {
-      const float* g2 = W.grad2d + (int64_t)gid * kGrad2dStride;
+      float g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      const float* m = W.grad2d + (int64_t)gid * 10;
+      if (flags & RTGS_GRAD_MAP) {
+        for (int i = 0; i < 10; ++i) g2[i] = m[i];
+      } else {
+        for (int i = 0; i < 5; ++i) g2[i] = m[i];
+        g2[9] = m[5];
+      }
       const double gu = g2[0], gv = g2[1], ga = g2[2], gb = g2[3], gc = g2[4], go = g2[5];
       gcol[0] = g2[6]; gcol[1] = g2[7]; gcol[2] = g2[8];
       const double gdep = g2[9];
@@ -116,16 +161,12 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
       const double dj12dz = S.fy * ty / z2 + (iny ? S.fy * y / z3 : 0.0);
       double gz = gdep - gu * S.fx * x / z2 - gv * S.fy * y / z2 - dj00 * S.fx / z2 -
                   dj11 * S.fy / z2 + dj02 * dj02dz + dj12 * dj12dz;
-      // pose: rho = dL/dp; phi = p x dL/dp + vee(W dW^T)
-      pose[0] = gx; pose[1] = gy; pose[2] = gz;
-      double Bm[9];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          Bm[3 * i + j] = vm[4 * i] * dW[3 * j] + vm[4 * i + 1] * dW[3 * j + 1] +
-                          vm[4 * i + 2] * dW[3 * j + 2];
-      pose[3] = y * gz - z * gy + (Bm[5] - Bm[7]);
-      pose[4] = z * gx - x * gz + (Bm[6] - Bm[2]);
-      pose[5] = x * gy - y * gx + (Bm[1] - Bm[3]);
+      // view matrix: dL/dW = dL/dW|cov + dL/dp mu^T, dL/dt = dL/dp
+      const double gp3[3] = {gx, gy, gz}, mu[3] = {mx, my, mz};
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) pose[3 * i + j] = dW[3 * i + j] + gp3[i] * mu[j];
+        pose[9 + i] = gp3[i];
+      }
       if (want_map) {
         // dL/dmu = W^T dL/dp
         for (int k = 0; k < 3; ++k) gm[k] = vm[k] * gx + vm[4 + k] * gy + vm[8 + k] * gz;
@@ -172,43 +213,74 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
   }
   // block partial of the pose gradient: wave shuffles, then the 4 waves in LDS
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < 12; ++k) {
     double v = pose[k];
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) s_red[wave][k] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 6) {
+  if (threadIdx.x < 12) {
     double t = 0;
     for (int q = 0; q < kGaussPerBlock / 64; ++q) t += s_red[q][threadIdx.x];
-    W.pose_part[(int64_t)blockIdx.x * 8 + threadIdx.x] = t;
+    W.pose_part[(int64_t)blockIdx.x * 16 + threadIdx.x] = t;
   }
 }
 
-// One workgroup per session: fixed-order sum of its block partials.
+// One workgroup per session: fixed-order sum of its block partials into the
+// view-matrix gradient, and the pose (left-perturbation) gradient from it.
 __global__ __launch_bounds__(256) void k_pose_reduce(Batch B, WsPtrs W) {
-  __shared__ double s_acc[256][6];
+  __shared__ double s_acc[256][12];
   const SessionDev& S = B.sess[blockIdx.x];
   const int b0 = S.block_base;
   const int b1 = (blockIdx.x + 1 < (unsigned)B.n_sessions) ? B.sess[blockIdx.x + 1].block_base
                                                            : B.b_total;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = b0 + (int)threadIdx.x; b < b1; b += 256)
-    for (int k = 0; k < 6; ++k) acc[k] += W.pose_part[(int64_t)b * 8 + k];
-  for (int k = 0; k < 6; ++k) s_acc[threadIdx.x][k] = acc[k];
+    for (int k = 0; k < 12; ++k) acc[k] += W.pose_part[(int64_t)b * 16 + k];
+  for (int k = 0; k < 12; ++k) s_acc[threadIdx.x][k] = acc[k];
   __syncthreads();
   for (int off = 128; off >= 1; off >>= 1) {
     if ((int)threadIdx.x < off)
-      for (int k = 0; k < 6; ++k) s_acc[threadIdx.x][k] += s_acc[threadIdx.x + off][k];
+      for (int k = 0; k < 12; ++k) s_acc[threadIdx.x][k] += s_acc[threadIdx.x + off][k];
     __syncthreads();
   }
-  if (threadIdx.x < 6 && S.g_pose6) S.g_pose6[threadIdx.x] = (float)s_acc[0][threadIdx.x];
+  if (threadIdx.x == 0) {
+    const double* g = s_acc[0];        // dL/dW row-major (9), dL/dt (3)
+    if (S.g_viewmat)
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) S.g_viewmat[4 * i + j] = (float)g[3 * i + j];
+        S.g_viewmat[4 * i + 3] = (float)g[9 + i];
+      }
+    if (S.g_pose6) {
+      double vm[12];
+      for (int k = 0; k < 12; ++k) vm[k] = S.viewmat[k];
+      double A[9];                     // A = dL/dW W^T + dL/dt t^T
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          A[3 * i + j] = g[3 * i] * vm[4 * j] + g[3 * i + 1] * vm[4 * j + 1] +
+                         g[3 * i + 2] * vm[4 * j + 2] + g[9 + i] * vm[4 * j + 3];
+      S.g_pose6[0] = (float)g[9];
+      S.g_pose6[1] = (float)g[10];
+      S.g_pose6[2] = (float)g[11];
+      S.g_pose6[3] = (float)(A[7] - A[5]);
+      S.g_pose6[4] = (float)(A[2] - A[6]);
+      S.g_pose6[5] = (float)(A[3] - A[1]);
+    }
+  }
 }
 
 }  // namespace
 
 hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st,
                                  StageTimer* tm) {
+  if (b.n_total > 0) {
+    Scope sc(tm, kStMerge, st);
+    const int grid = (b.n_total + 15) / 16;
+    if (grad_flags & RTGS_GRAD_MAP)
+      k_merge<10><<<grid, 256, 0, st>>>(b, w);
+    else
+      k_merge<6><<<grid, 256, 0, st>>>(b, w);
+  }
   if (b.b_total > 0) {
     Scope sc(tm, kStPreprocessBwd, st);
     k_preprocess_bwd<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);

@@ -17,10 +17,13 @@
 // recovering T before each blended fragment as T / (1 - alpha) (Eq. 5 read
 // as the reverse recurrence) and the normalised suffix colour/depth; the
 // per-fragment 2D gradients of one list entry are summed over the wave with
-// DPP row shifts and broadcasts, and ten lanes then add the ten totals to the
-// Gaussian's accumulator with one global atomic instruction: the pixel ->
-// tile merge of the paper's Gradient Merging Unit (Sec. 5.3) done with
-// cross-lane operations.
+// DPP row shifts and broadcasts, the four waves' sums are added in LDS in a
+// fixed order, and the tile's total for that Gaussian is stored in the
+// pair's own slot: the pixel -> tile merge of the paper's Gradient Merging
+// Unit (Sec. 5.3) done with cross-lane operations.  The tile -> Gaussian
+// merge (its Stage Buffer) is a segmented sum over the Gaussian's slots in
+// the preprocessing backward; no float atomics anywhere, so gradients are
+// bitwise reproducible.
 #include "rtgs_internal.h"
 
 namespace rtgs {
@@ -150,23 +153,33 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   }
 }
 
-__global__ void k_zero(float* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.f;
+constexpr int kBwdBatch = 128;           // list entries staged per batch
+constexpr int kPartStride = kBwdBatch + 1;  // odd row stride: conflict-free LDS writes
+
+// Gaussian-major slot of the pair (Gaussian g, tile (tx, ty)): g's first slot
+// plus the tile's row-major index inside g's tile rectangle.
+__device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx, int ty) {
+  const int4 r = W.rect[g];
+  return (int64_t)W.goff[g] + (ty - r.y) * (r.z - r.x + 1) + (tx - r.x);
 }
 
-// NV = 10 (all parameters) or 6 (pose only: u, v, a, b, c, z).
+// NV = 10 (all parameters: u, v, a, b, c, o, r, g, b, z) or 6 (pose only:
+// u, v, a, b, c, z).  Each (tile, Gaussian) pair gets the sum of its pixels'
+// gradients in slot pair_slot(); the sum is formed in a fixed order (DPP
+// tree inside each wave, then the four waves in order), so the result is
+// bitwise reproducible and no float atomics are used.
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
-  __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock];
-  __shared__ unsigned s_m[kBlock];
-  __shared__ uint32_t s_g[kBlock];
+  __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch];
+  __shared__ unsigned s_m[kBwdBatch];
+  __shared__ float s_part[4][NV][kPartStride];
   __shared__ int s_hi;
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
   const TileCtx c = tile_ctx(B, tile);
   const SessionDev& S = B.sess[c.s];
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ltx = c.tile_x0 / kTile, lty = c.tile_y0 / kTile;
   const bool active = c.inside && (S.pmask == nullptr || S.pmask[c.pix] != 0);
   const int64_t hw = (int64_t)S.width * S.height;
   int last = -1;
@@ -190,11 +203,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   // a saved position outside this tile's list (state of another forward) is
   // never followed past the list
   const int64_t hi = min((int64_t)s_hi, end - 1);
-  if (hi < start) return;
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
   float S0 = 0.f, S1 = 0.f, S2 = 0.f, Sz = 0.f;   // suffix sums normalised by T
-  for (int64_t bend = hi + 1; bend > start; bend -= kBlock) {
-    const int64_t b0 = bend - kBlock > start ? bend - kBlock : start;
+  for (int64_t bend = hi + 1; bend > start; bend -= kBwdBatch) {
+    const int64_t b0 = bend - kBwdBatch > start ? bend - kBwdBatch : start;
     const int cnt = (int)(bend - b0);
     __syncthreads();
     if (tid < cnt) {
@@ -203,65 +215,83 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
       s_r0[tid] = r0;
       s_r1[tid] = W.rec1[g];
       s_r2[tid] = W.rec2[g];
-      s_g[tid] = g;
       s_m[tid] = quad_mask(r0, W.ext[g], c.tile_x0, c.tile_y0);
     }
     __syncthreads();
     for (int k = cnt - 1; k >= 0; --k) {
-      if (!(s_m[k] & c.wbit)) continue;
-      float v[10];
+      float mine = 0.f;
+      if (s_m[k] & c.wbit) {
+        float v[NV];
 #pragma unroll
-      for (int i = 0; i < 10; ++i) v[i] = 0.f;
-      bool contrib = false;
-      if ((int64_t)b0 + k <= (int64_t)last) {
-        const float4 r1 = s_r1[k];
-        const Frag f = frag_alpha(s_r0[k], r1, pxf, pyf);
-        if (f.alpha >= kAlphaMin) {
-          contrib = true;
-          const float4 col = s_r2[k];
-          const float om = 1.f - f.alpha;
-          const float Tj = Tc / om;                     // T before this fragment
-          const float w = f.alpha * Tj;
-          float dla = (col.x - S0) * g0;
-          dla = __builtin_fmaf(col.y - S1, g1, dla);
-          dla = __builtin_fmaf(col.z - S2, g2, dla);
-          dla = __builtin_fmaf(col.w - Sz, gD, dla);
-          dla = __builtin_fmaf(Tj, dla, gAT / om);      // dL/dalpha
-          S0 = __builtin_fmaf(f.alpha, col.x, om * S0);
-          S1 = __builtin_fmaf(f.alpha, col.y, om * S1);
-          S2 = __builtin_fmaf(f.alpha, col.z, om * S2);
-          Sz = __builtin_fmaf(f.alpha, col.w, om * Sz);
-          Tc = Tj;
-          v[NV - 1] = w * gD;                           // depth slot (last)
-          if (NV == 10) {
-            v[6] = w * g0;
-            v[7] = w * g1;
-            v[8] = w * g2;
-          }
-          if (!(r1.w * f.e > kAlphaMax)) {              // not clamped
-            const float gp = f.alpha * dla;             // dL/dpower
-            if (NV == 10) v[5] = f.e * dla;              // dL/do
-            v[0] = -gp * __builtin_fmaf(r1.x, f.dx, r1.y * f.dy);
-            v[1] = -gp * __builtin_fmaf(r1.y, f.dx, r1.z * f.dy);
-            v[2] = -0.5f * gp * f.dx * f.dx;
-            v[3] = -gp * f.dx * f.dy;
-            v[4] = -0.5f * gp * f.dy * f.dy;
+        for (int i = 0; i < NV; ++i) v[i] = 0.f;
+        bool contrib = false;
+        if ((int64_t)b0 + k <= (int64_t)last) {
+          const float4 r1 = s_r1[k];
+          const Frag f = frag_alpha(s_r0[k], r1, pxf, pyf);
+          if (f.alpha >= kAlphaMin) {
+            contrib = true;
+            const float4 col = s_r2[k];
+            const float om = 1.f - f.alpha;
+            const float Tj = Tc / om;                     // T before this fragment
+            const float w = f.alpha * Tj;
+            float dla = (col.x - S0) * g0;
+            dla = __builtin_fmaf(col.y - S1, g1, dla);
+            dla = __builtin_fmaf(col.z - S2, g2, dla);
+            dla = __builtin_fmaf(col.w - Sz, gD, dla);
+            dla = __builtin_fmaf(Tj, dla, gAT / om);      // dL/dalpha
+            S0 = __builtin_fmaf(f.alpha, col.x, om * S0);
+            S1 = __builtin_fmaf(f.alpha, col.y, om * S1);
+            S2 = __builtin_fmaf(f.alpha, col.z, om * S2);
+            Sz = __builtin_fmaf(f.alpha, col.w, om * Sz);
+            Tc = Tj;
+            v[NV - 1] = w * gD;                           // depth slot (last)
+            if (NV == 10) {
+              v[6] = w * g0;
+              v[7] = w * g1;
+              v[8] = w * g2;
+            }
+            if (!(r1.w * f.e > kAlphaMax)) {              // not clamped
+              const float gp = f.alpha * dla;             // dL/dpower
+              if (NV == 10) v[5] = f.e * dla;              // dL/do
+              v[0] = -gp * __builtin_fmaf(r1.x, f.dx, r1.y * f.dy);
+              v[1] = -gp * __builtin_fmaf(r1.y, f.dx, r1.z * f.dy);
+              v[2] = -0.5f * gp * f.dx * f.dx;
+              v[3] = -gp * f.dx * f.dy;
+              v[4] = -0.5f * gp * f.dy * f.dy;
+            }
           }
         }
-      }
-      if (__ballot(contrib)) {
-        float tot[NV];
+        if (__ballot(contrib)) {
+          float tot[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) tot[i] = read_lane63(wave_sum_to_lane63(v[i]));
-        float mine = tot[0];
+          for (int i = 0; i < NV; ++i) tot[i] = read_lane63(wave_sum_to_lane63(v[i]));
 #pragma unroll
-        for (int i = 1; i < NV; ++i) mine = lane == i ? tot[i] : mine;
-        if (lane < NV) {
-          // slots (u, v, a, b, c, o, r, g, b, z); pose only: v[5] is z -> slot 9
-          const int slot = (NV == 10 || lane < 5) ? lane : 9;
-          atomicAdd(&W.grad2d[(int64_t)s_g[k] * kGrad2dStride + slot], mine);
+          for (int i = 0; i < NV; ++i) mine = lane == i ? tot[i] : mine;
         }
       }
+      if (lane < NV) s_part[wave][lane][k] = mine;
+    }
+    __syncthreads();
+    if (tid < cnt) {
+      const uint32_t g = W.ids[b0 + tid];
+      const int64_t slot = pair_slot(W, g, ltx, lty);
+      if (slot < W.cap) {
+        float* dst = W.partial + slot * NV;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+          dst[i] = ((s_part[0][i][tid] + s_part[1][i][tid]) + s_part[2][i][tid]) + s_part[3][i][tid];
+      }
+    }
+  }
+  // pairs after the last blended fragment of every pixel carry no gradient
+  const int64_t z0 = hi + 1 > start ? hi + 1 : start;
+  for (int64_t pos = z0 + tid; pos < end; pos += kBlock) {
+    const uint32_t g = W.ids[pos];
+    const int64_t slot = pair_slot(W, g, ltx, lty);
+    if (slot < W.cap) {
+      float* dst = W.partial + slot * NV;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) dst[i] = 0.f;
     }
   }
 }
@@ -278,11 +308,6 @@ hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, hipStream_t st, St
 
 hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st,
                              StageTimer* tm) {
-  const int64_t ng = (int64_t)b.n_total * kGrad2dStride;
-  if (ng > 0) {
-    Scope sc(tm, kStZero, st);
-    k_zero<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(w.grad2d, ng);
-  }
   if (b.t_total <= 0) return hipGetLastError();
   const int grid = 8 * ((b.t_total + 7) / 8);
   Scope sc(tm, kStRasterBwd, st);

@@ -18,7 +18,8 @@ constexpr float kTMin = 1e-4f;              // early-termination transmittance
 constexpr double kNearZ = 0.2;
 constexpr double kDilation = 0.3;
 constexpr double kFovClamp = 1.3;
-constexpr int kGrad2dStride = 12;         // floats per Gaussian of 2D gradient
+constexpr int kChunk = 2048;              // Gaussians per binning chunk (8 per thread)
+constexpr int kMaxTilesPerSession = 12288; // LDS tile histogram of one session (48 KB)
 
 // Device copy of one session (built on the host from rtgs_session).
 struct SessionDev {
@@ -49,6 +50,7 @@ struct SessionDev {
   float* g_opac;
   float* g_colors;
   float* g_pose6;
+  float* g_viewmat;
   float* g_cov3d;
   // geometry
   int32_t n;
@@ -61,7 +63,8 @@ struct SessionDev {
   int32_t gauss_base;   // first global Gaussian index
   int32_t block_base;   // first per-Gaussian block
   int32_t tile_base;    // first global tile
-  int32_t pad_;
+  int32_t chunk_base;   // first binning chunk
+  int64_t hist_base;    // first entry of this session's [chunk][tile] counts
 };
 
 // Offsets of the workspace regions (bytes from ws).
@@ -73,13 +76,18 @@ struct WsLayout {
   uint64_t rec2;        // float4[N]: r, g, b, z
   uint64_t ext;         // float4[N]: e_x, e_y, -, -
   uint64_t rect;        // int4[N]: tile rectangle
-  uint64_t grad2d;      // float[N][12]: dL/d(u, v, a, b, c, o, r, g, b, z)
-  uint64_t pose_part;   // double[B][8]: per-block pose partial sums
+  uint64_t cnt;         // uint32[N]: tiles touched
+  uint64_t goff;        // uint32[N]: first slot of the Gaussian's pairs, Gaussian-major
+  uint64_t grad2d;      // float[N][10]: merged dL/d(u, v, a, b, c, o, r, g, b, z)
+  uint64_t pose_part;   // double[B][16]: per-block view-matrix gradient partial sums
+  uint64_t chunk_total; // uint32[C + 1]: pairs per chunk
+  uint64_t chunk_off;   // uint32[C + 1]: exclusive scan of chunk_total
+  uint64_t hist;        // uint32[sum_s C_s T_s]: per (chunk, tile) counts, then offsets
   uint64_t tile_count;  // uint32[T + 1]
   uint64_t tile_start;  // uint32[T + 1]
-  uint64_t tile_cursor; // uint32[T]
   uint64_t keys;        // uint64[cap]
   uint64_t ids;         // uint32[cap]
+  uint64_t partial;     // float[cap][10]: per (tile, Gaussian) merged 2D gradient
   uint64_t state_t;     // float[pixels]: recomputed final T
   uint64_t state_last;  // int32[pixels]: recomputed last position
   uint64_t total;       // bytes
@@ -89,8 +97,12 @@ struct WsLayout {
   int64_t cap;
 };
 
-WsLayout make_layout(int64_t n_total, int64_t t_total, int64_t b_total, int64_t cap,
-                     int64_t px_total);
+struct Counts {
+  int64_t n_total = 0, t_total = 0, b_total = 0, c_total = 0, h_total = 0, px_total = 0;
+  int64_t t_max = 0;
+};
+
+WsLayout make_layout(const Counts& c, int64_t cap);
 
 // Pointers derived from a workspace.
 struct WsPtrs {
@@ -101,13 +113,18 @@ struct WsPtrs {
   float4* rec2;
   float4* ext;
   int4* rect;
+  uint32_t* cnt;
+  uint32_t* goff;
   float* grad2d;
   double* pose_part;
+  uint32_t* chunk_total;
+  uint32_t* chunk_off;
+  uint32_t* hist;
   uint32_t* tile_count;
   uint32_t* tile_start;
-  uint32_t* tile_cursor;
   unsigned long long* keys;
   uint32_t* ids;
+  float* partial;
   float* state_t;
   int32_t* state_last;
   int64_t cap;
@@ -122,12 +139,14 @@ struct Batch {
   int32_t n_total;      // Gaussians over all sessions
   int32_t t_total;      // tiles over all sessions
   int32_t b_total;      // per-Gaussian blocks over all sessions
+  int32_t c_total;      // binning chunks over all sessions
+  int32_t t_max;        // largest tile count of one session
 };
 
 // Stages that the handle's profiler can bracket with HIP events.
 enum Stage {
   kStInit = 0, kStPreprocess, kStScan, kStEmit, kStSort, kStRasterFwd, kStZero, kStRasterBwd,
-  kStPreprocessBwd, kStPoseReduce, kStPrune, kStDownsample, kStCount
+  kStPreprocessBwd, kStPoseReduce, kStBinCount, kStMerge, kStCount
 };
 
 // Records HIP events around kernel launches of the enabled stages.

@@ -31,7 +31,7 @@ RTGS_FWD_SAVE_STATE = 1
 RTGS_FWD_STATS = 2
 RTGS_PROFILE_STAGES = 16
 STAGES = ("init", "preprocess", "scan", "emit", "sort", "raster_fwd", "zero", "raster_bwd",
-          "preprocess_bwd", "pose_reduce")
+          "preprocess_bwd", "pose_reduce", "bin_count", "merge")
 RTGS_GRAD_POSE = 1
 RTGS_GRAD_MAP = 2
 RTGS_GRAD_COV3D = 4
@@ -70,7 +70,8 @@ class CSession(ctypes.Structure):
                 ("color", vp), ("depth", vp), ("alpha", vp), ("final_T", vp), ("last_idx", vp),
                 ("visible", vp), ("stats", vp), ("dL_dcolor", vp), ("dL_ddepth", vp), ("dL_dalpha", vp),
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
-                ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_cov3d", vp)]
+                ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_viewmat", vp),
+                ("g_cov3d", vp)]
 
 
 _lib = None
@@ -102,7 +103,7 @@ def lib():
                                      vp, u64, i64, vp, vp, vp, vp, vp, vp, i32, vp]
             L.render_bwd.argtypes = [vp, ctypes.POINTER(CGaussians), ctypes.POINTER(CCamera), vp,
                                      vp, u64, i64, vp, vp, vp, vp, vp, i32,
-                                     vp, vp, vp, vp, vp, vp, vp, vp]
+                                     vp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.render_fwd_batched.argtypes = [vp, ctypes.POINTER(CSession), i32, vp, u64, i64,
                                              i32, vp]
             L.render_bwd_batched.argtypes = [vp, ctypes.POINTER(CSession), i32, vp, u64, i64,
@@ -242,7 +243,7 @@ def render_bwd(handle, means, log_scales, quats, opacity_logits, colors, viewmat
                pair_capacity, final_T, last_idx, dL_dcolor, dL_ddepth, dL_dalpha=None,
                grad_flags=RTGS_GRAD_POSE | RTGS_GRAD_MAP, g_means=None, g_log_scales=None,
                g_quats=None, g_opacity_logits=None, g_colors=None, g_pose6=None, g_cov3d=None,
-               gauss_mask=None, pixel_mask=None, stream=None):
+               gauss_mask=None, pixel_mask=None, stream=None, g_viewmat=None):
     g = _gauss(means, log_scales, quats, opacity_logits, colors, gauss_mask)
     c = _cam(cam, viewmat)
     _check(lib().render_bwd(handle.ptr, ctypes.byref(g), ctypes.byref(c), _p(pixel_mask),
@@ -250,7 +251,7 @@ def render_bwd(handle, means, log_scales, quats, opacity_logits, colors, viewmat
                             _p(final_T), _p(last_idx), _p(dL_dcolor), _p(dL_ddepth),
                             _p(dL_dalpha), int(grad_flags), _p(g_means), _p(g_log_scales),
                             _p(g_quats), _p(g_opacity_logits), _p(g_colors), _p(g_pose6),
-                            _p(g_cov3d), _stream(stream)))
+                            _p(g_viewmat), _p(g_cov3d), _stream(stream)))
 
 
 def make_sessions(items):
@@ -267,7 +268,7 @@ def make_sessions(items):
         for name in ("pixel_mask", "color", "depth", "alpha", "final_T", "last_idx", "visible",
                      "stats",
                      "dL_dcolor", "dL_ddepth", "dL_dalpha", "g_means", "g_log_scales", "g_quats",
-                     "g_opacity_logits", "g_colors", "g_pose6", "g_cov3d"):
+                     "g_opacity_logits", "g_colors", "g_pose6", "g_viewmat", "g_cov3d"):
             t = it.get(name)
             setattr(s, name, _p(t))
             keep.append(t)
@@ -456,12 +457,13 @@ class Renderer:
             g["cov3d"] = torch.empty(n, 6, device=dev)
         if pose:
             g["pose"] = torch.empty(6, device=dev)
+            g["viewmat"] = torch.empty(3, 4, device=dev)
         render_bwd(self.handle, *scene, viewmat, cam, st.ws, st.cap, st.final_T, st.last_idx,
                    dL_dcolor.contiguous(), dL_ddepth.contiguous(),
                    None if dL_dalpha is None else dL_dalpha.contiguous(), flags,
                    g.get("means"), g.get("log_scales"), g.get("quats"), g.get("opacity_logits"),
                    g.get("colors"), g.get("pose"), g.get("cov3d"), gauss_mask=gauss_mask,
-                   pixel_mask=pixel_mask, stream=stream)
+                   pixel_mask=pixel_mask, stream=stream, g_viewmat=g.get("viewmat"))
         return g
 
 

@@ -144,13 +144,16 @@ def test_backward_all_gradients_c0(renderer, posed):
     e1, e2 = rel_err(g["pose"], ref.pose.numpy()), norm_err(g["pose"], ref.pose.numpy())
     say(f"  pose: rel {e1:.2e} norm {e2:.2e}  {g['pose']}  {ref.pose.numpy()}")
     assert e1 < GRAD_TOL and e2 < GRAD_TOL
+    e1 = rel_err(g["viewmat"], ref.viewmat.numpy())
+    say(f"  viewmat: rel {e1:.2e}")
+    assert e1 < GRAD_TOL
 
 
 def test_backward_pose_only_matches_full(renderer):
     say("test_backward_pose_only")
     sc, cam, view = _case("c0", synth.pose_offset(33, 0.02, 1.0))
     g, ref, _ = _grad_case(renderer, sc, cam, view, map_grads=False, alpha_grad=False)
-    assert set(g) == {"pose"}
+    assert set(g) == {"pose", "viewmat"}
     assert rel_err(g["pose"], ref.pose.numpy()) < GRAD_TOL
 
 

@@ -402,3 +402,19 @@ def test_ambiguity_flags_mark_threshold_cases():
     assert out.flags.sum() < 10
     far = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam), band_alpha=1e-9)
     assert not far.flags[32, 32]
+
+
+def test_pose_gradient_is_the_left_perturbation_of_the_viewmat_gradient():
+    # dL/drho = dL/dt and dL/dphi = axial vector of the antisymmetric part of
+    # dL/dR R^T + dL/dt t^T (chain rule of T <- (I + xi^) T at xi = 0)
+    sc = _c0_small(n=150, seed=13)
+    view = oracle.apply_left(torch.tensor(synth.pose_offset(6, 0.05, 3.0)),
+                             torch.tensor(_eye_view())).numpy()
+    rng = np.random.default_rng(6)
+    _, g = oracle.render_with_grads(sc.arrays(), view, cam_tuple(CAM64),
+                                    rng.normal(size=(3, 64, 64)), rng.normal(size=(64, 64)))
+    gv = g.viewmat.numpy()
+    a = gv[:, :3] @ view[:, :3].T + np.outer(gv[:, 3], view[:, 3])
+    assert np.allclose(g.pose[:3].numpy(), gv[:, 3], rtol=1e-12, atol=1e-10)
+    assert np.allclose(g.pose[3:].numpy(), [a[2, 1] - a[1, 2], a[0, 2] - a[2, 0], a[1, 0] - a[0, 1]],
+                       rtol=1e-10, atol=1e-8)
