@@ -1,0 +1,611 @@
+"""Serving many SLAM sessions on one GPU with continuous batching.
+
+Each session keeps its Gaussian map, pose and optimiser state resident in HBM.
+Frames arrive per session (a seeded Poisson process); a frame needs
+``track_iters`` tracking iterations (gradients to the pose only) and, on
+keyframes (every ``keyframe_every``-th frame), ``map_iters`` mapping
+iterations (gradients to every Gaussian parameter) afterwards (Sec. 2.2:
+tracking on every frame, mapping on keyframes).  Non-keyframes may be
+rendered on a pixel mask chosen by the dynamic-downsampling schedule
+(Sec. 4.2) from the session's last transmittance image.
+
+Continuous batching at iteration granularity: every engine step runs one
+iteration of every admitted frame, all tracking frames in one batched
+render_fwd / render_bwd pair (one launch per stage for all sessions, one tile
+space, one sort) and all mapping frames in another.  Frames that arrive while
+others run join at the next step, as batch slots and memory free up.
+Admission is by HBM budget: a session opens only if its resident footprint
+fits, and a frame joins a step only while the step's workspace stays within
+the workspace budget.  The engine never waits for the GPU between steps; each
+step records an event, and a frame's completion time is the GPU time of the
+event of its last iteration.
+
+``mode="serial"`` serves the same trace one session-frame at a time (FIFO,
+single-session launches, no overlap): the baseline for the batched mode.
+
+Executors: ``GpuExecutor`` runs the HIP library; ``FakeExecutor`` models
+iteration cost on the CPU (tests of admission, batching and fairness without
+a GPU).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import heapq
+import math
+import time
+
+import numpy as np
+
+from . import synth
+
+# --------------------------------------------------------------------------- workload
+
+
+@dataclasses.dataclass(frozen=True)
+class SessionSpec:
+    width: int
+    height: int
+    n: int
+    kind: str = "c0"          # scene distribution (synth.CONFIGS key)
+    seed: int = 0
+
+    @property
+    def pixels(self):
+        return self.width * self.height
+
+
+def serving_mix(seed=4000):
+    """The 16-session mix: 6 x (320x240, 20k), 6 x (640x480, 100k),
+    4 x (1200x680, 500k)."""
+    out = []
+    k = 0
+    for count, w, h, n, kind in synth.SERVING_CLASSES:
+        for _ in range(count):
+            out.append(SessionSpec(w, h, n, kind, seed + k))
+            k += 1
+    return out
+
+
+@dataclasses.dataclass
+class Frame:
+    session: int
+    index: int
+    arrival: float
+    keyframe: bool
+    track_left: int
+    map_left: int
+    log2_ratio: int = 0
+    started: float = -1.0
+    done_event: object = None
+    done_time: float = -1.0
+
+    @property
+    def remaining(self):
+        return self.track_left + self.map_left
+
+    @property
+    def phase(self):
+        return "track" if self.track_left > 0 else "map"
+
+
+def poisson_trace(n_sessions, rate_hz, duration_s, seed):
+    """Per-session exponential inter-arrival times; list of (t, session, index)
+    sorted by time."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ev = []
+    for s in range(n_sessions):
+        t, i = 0.0, 0
+        while True:
+            t += rng.exponential(1.0 / rate_hz)
+            if t >= duration_s:
+                break
+            ev.append((t, s, i))
+            i += 1
+    ev.sort()
+    return ev
+
+
+@dataclasses.dataclass
+class ServeConfig:
+    track_iters: int = 10
+    map_iters: int = 20
+    keyframe_every: int = 8
+    downsample: bool = False        # dynamic downsampling of non-keyframes
+    m: int = 2                      # resolution growth factor of the schedule
+    max_batch: int = 16             # frames per engine step
+    hbm_budget: float = 200e9       # resident maps + optimiser state (bytes)
+    ws_budget: float = 40e9         # per-step workspace (bytes)
+    mode: str = "batched"           # or "serial"
+
+
+# --------------------------------------------------------------------------- engine
+
+
+class Engine:
+    """Admission + continuous batching over an executor."""
+
+    def __init__(self, specs, executor, cfg: ServeConfig, clock=None):
+        self.specs = list(specs)
+        self.ex = executor
+        self.cfg = cfg
+        self.clock = clock or getattr(executor, "clock", time.perf_counter)
+        self.open = [False] * len(self.specs)
+        self.pending = collections.deque()     # frames waiting (arrived)
+        self.active = []                       # frames admitted, in progress
+        self.finished = []
+        self.resident = 0.0
+        self.max_resident = 0.0
+        self.steps = 0
+        self.iters = 0
+        self.batch_sizes = []
+        self.last_key = [-1] * len(self.specs)
+
+    # ---- admission -------------------------------------------------------
+    def _try_open(self, s):
+        """Make session s resident, evicting idle sessions (no frame admitted
+        or waiting) to host memory if the HBM budget requires it."""
+        if self.open[s]:
+            return True
+        need = self.ex.session_bytes(self.specs[s])
+        if self.resident + need > self.cfg.hbm_budget:
+            waiting = {f.session for f in self.pending} | {f.session for f in self.active}
+            for v in range(len(self.specs)):
+                if self.resident + need <= self.cfg.hbm_budget:
+                    break
+                if self.open[v] and v not in waiting:
+                    self.close_session(v)
+            if self.resident + need > self.cfg.hbm_budget:
+                return False
+        self.ex.open_session(s, self.specs[s])
+        self.resident += need
+        self.max_resident = max(self.max_resident, self.resident)
+        self.open[s] = True
+        return True
+
+    def close_session(self, s):
+        if self.open[s]:
+            self.ex.close_session(s)
+            self.resident -= self.ex.session_bytes(self.specs[s])
+            self.open[s] = False
+
+    def submit(self, t, s, index):
+        key = index % self.cfg.keyframe_every == 0
+        j = 0
+        if self.cfg.downsample and not key:
+            k = self.last_key[s] if self.last_key[s] >= 0 else index - 1
+            j = _log2_ratio(index, k, self.cfg.m)
+        if key:
+            self.last_key[s] = index
+        self.pending.append(Frame(s, index, t, key, self.cfg.track_iters,
+                                  self.cfg.map_iters if key else 0, j))
+
+    def _admit(self, now):
+        cap = 1 if self.cfg.mode == "serial" else self.cfg.max_batch
+        ws = sum(self.ex.step_bytes(self.specs[f.session], f) for f in self.active)
+        busy = {f.session for f in self.active}
+        keep = collections.deque()
+        while self.pending and len(self.active) < cap:
+            f = self.pending.popleft()
+            if f.session in busy:             # a session's frames run in order
+                keep.append(f)
+                continue
+            need = self.ex.step_bytes(self.specs[f.session], f)
+            if ws + need > self.cfg.ws_budget and self.active:
+                keep.append(f)
+                continue
+            if not self._try_open(f.session):
+                keep.append(f)
+                continue
+            f.started = now
+            self.ex.start_frame(f, self.specs[f.session])
+            self.active.append(f)
+            busy.add(f.session)
+            ws += need
+        keep.extend(self.pending)
+        self.pending = keep
+
+    # ---- one engine step ---------------------------------------------------
+    def step(self, now):
+        self._admit(now)
+        if not self.active:
+            return False
+        groups = {"track": [], "map": []}
+        for f in self.active:
+            groups[f.phase].append(f)
+        for phase in ("track", "map"):
+            g = groups[phase]
+            if not g:
+                continue
+            ev = self.ex.run_iteration(phase, g, [self.specs[f.session] for f in g])
+            for f in g:
+                if phase == "track":
+                    f.track_left -= 1
+                else:
+                    f.map_left -= 1
+                if f.remaining == 0:
+                    f.done_event = ev
+            self.iters += len(g)
+        self.steps += 1
+        self.batch_sizes.append(len(self.active))
+        still = []
+        for f in self.active:
+            if f.remaining == 0:
+                self.ex.finish_frame(f, self.specs[f.session])
+                self.finished.append(f)
+            else:
+                still.append(f)
+        self.active = still
+        return True
+
+    def preopen(self):
+        """Open (make resident) every session the HBM budget admits."""
+        for s in range(len(self.specs)):
+            self._try_open(s)
+
+    def run(self, trace, warmup_s=0.0):
+        """Open-loop: frames are submitted when their arrival time passes; the
+        report leaves out frames that arrived in the first warmup_s seconds."""
+        self.preopen()
+        self.ex.start_clock()
+        t0 = self.clock()
+        i = 0
+        while True:
+            now = self.clock() - t0
+            while i < len(trace) and trace[i][0] <= now:
+                t, s, idx = trace[i]
+                self.submit(t, s, idx)
+                i += 1
+            if not self.step(now):
+                if i >= len(trace) and not self.pending:
+                    break
+                if i < len(trace):
+                    wait = trace[i][0] - (self.clock() - t0)
+                    if wait > 0:
+                        self.ex.idle(wait)
+        self.ex.sync()
+        for f in self.finished:
+            f.done_time = self.ex.event_time(f.done_event)
+        return self.report(warmup_s=warmup_s)
+
+    def report(self, warmup_s=0.0):
+        lat = {}
+        for f in self.finished:
+            if f.arrival < warmup_s:
+                continue
+            key = f"{self.specs[f.session].width}x{self.specs[f.session].height}"
+            lat.setdefault(key, []).append(f.done_time - f.arrival)
+        every = [x for v in lat.values() for x in v]
+        span = max((f.done_time for f in self.finished), default=0.0)
+
+        def pct(v, q):
+            return float(np.percentile(np.asarray(v) * 1e3, q)) if v else float("nan")
+
+        return {
+            "frames": len(self.finished),
+            "p50_ms": pct(every, 50), "p99_ms": pct(every, 99),
+            "per_class": {k: {"frames": len(v), "p50_ms": pct(v, 50), "p99_ms": pct(v, 99)}
+                          for k, v in sorted(lat.items())},
+            "iters": self.iters, "steps": self.steps,
+            "iters_per_s": self.iters / span if span > 0 else float("nan"),
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "span_s": span,
+            "max_resident_bytes": self.max_resident,
+        }
+
+
+def _log2_ratio(n, k, m):
+    """Downsampling schedule of Sec. 4.2 for non-keyframe n after keyframe k."""
+    if n <= k:
+        return 0
+    return max(2, 4 - int(math.floor((n - k - 1) * math.log2(m) + 1e-12)))
+
+
+# --------------------------------------------------------------------------- fake executor
+
+
+class FakeExecutor:
+    """CPU model of the GPU: an iteration of a batch costs
+    launch + sum over frames of (a * pixels + b * gaussians), with a higher
+    per-launch cost when frames are served one by one.  Time is simulated."""
+
+    def __init__(self, launch_s=2e-4, per_pixel_s=1.5e-9, per_gauss_s=1.0e-9,
+                 bytes_per_gauss=400, ws_per_gauss=60):
+        self.launch_s = launch_s
+        self.a = per_pixel_s
+        self.b = per_gauss_s
+        self.bpg = bytes_per_gauss
+        self.wpg = ws_per_gauss
+        self.now = 0.0
+        self.opened = set()
+        self.log = []
+
+    def clock(self):
+        return self.now
+
+    def start_clock(self):
+        pass
+
+    def session_bytes(self, spec):
+        return spec.n * self.bpg + 16 * spec.pixels * 8
+
+    def step_bytes(self, spec, frame):
+        return spec.n * self.wpg + 12 * spec.pixels
+
+    def open_session(self, s, spec):
+        self.opened.add(s)
+
+    def close_session(self, s):
+        self.opened.discard(s)
+
+    def start_frame(self, f, spec):
+        pass
+
+    def finish_frame(self, f, spec):
+        pass
+
+    def run_iteration(self, phase, frames, specs):
+        cost = self.launch_s
+        for f, sp in zip(frames, specs):
+            frac = 1.0 / (2 ** f.log2_ratio) if phase == "track" else 1.0
+            cost += self.a * sp.pixels * frac + self.b * sp.n * (2.0 if phase == "map" else 1.0)
+        self.now += cost
+        self.log.append((phase, tuple(f.session for f in frames)))
+        return self.now
+
+    def idle(self, dt):
+        self.now += dt
+
+    def sync(self):
+        pass
+
+    def event_time(self, ev):
+        return ev
+
+
+# --------------------------------------------------------------------------- GPU executor
+
+
+class GpuExecutor:
+    """Runs sessions on the HIP library with batched launches."""
+
+    def __init__(self, device=0, lr_pose=(1e-3, 3e-3), track_noise_seed=0, n_targets=4,
+                 capacity_factor=2.0):
+        import torch
+
+        from . import rtgs
+        self.torch = torch
+        self.rtgs = rtgs
+        self.dev = torch.device("cuda", device)
+        self.handle = rtgs.Handle(device)
+        self.sessions = {}
+        self.lr_rho, self.lr_phi = lr_pose
+        self.n_targets = n_targets
+        self.capacity_factor = capacity_factor
+        self.base_event = None
+        self.base_wall = None
+        self.overflows = 0
+
+    # ---- footprint -----------------------------------------------------------
+    def session_bytes(self, spec):
+        # parameters, their gradients and two Adam moments (56 B each), target
+        # frames (16 B per pixel each), per-frame outputs
+        return spec.n * 56 * 4 + self.n_targets * 16 * spec.pixels + 40 * spec.pixels
+
+    def _cap(self, spec):
+        return int(self.capacity_factor * (12 * spec.n + 4 * _tiles(spec.width, spec.height)))
+
+    def step_bytes(self, spec, frame):
+        return self.rtgs.rtgs_workspace_size(spec.n, spec.width, spec.height, self._cap(spec))
+
+    # ---- sessions ------------------------------------------------------------
+    def open_session(self, s, spec):
+        if s in self.sessions:
+            self._restore(s)
+            return
+        torch = self.torch
+        cfg = synth.CONFIGS[spec.kind]
+        sspec = synth.SceneSpec(f"s{s}", spec.width, spec.height, spec.n, spec.seed,
+                                cfg.log_scale_mean, cfg.log_scale_std, cfg.z_near, cfg.z_far,
+                                cfg.transparent_frac)
+        cam = synth.make_camera(spec.width, spec.height)
+        sc = synth.make_scene(sspec, cam)
+        params = [torch.from_numpy(a).to(self.dev) for a in sc.arrays()]
+        rc = self.rtgs.Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+        # targets: the scene seen from small pose offsets (the frames of a slow
+        # trajectory), plus sensor noise; rendered once at session open
+        r = self.rtgs.Renderer(self.dev.index, check="every")
+        targets = []
+        for k in range(self.n_targets):
+            xi = torch.tensor(synth.pose_offset(spec.seed * 31 + k, 0.01, 0.5),
+                              dtype=torch.float64, device=self.dev)
+            from .pose import apply_left
+            vm = apply_left(xi, torch.eye(3, 4, dtype=torch.float32, device=self.dev))
+            st = r.forward(tuple(params), vm.contiguous(), rc)
+            g = torch.Generator(device=self.dev).manual_seed(spec.seed + k)
+            targets.append((st.color + 0.01 * torch.randn(st.color.shape, generator=g,
+                                                          device=self.dev),
+                            st.depth + 0.01 * torch.randn(st.depth.shape, generator=g,
+                                                          device=self.dev)))
+        maps = [p.clone().requires_grad_(True) for p in params]
+        opt = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in
+                                zip(maps, (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3))],
+                               eps=1e-15, foreach=True)
+        self.sessions[s] = dict(
+            spec=spec, cam=rc, params=maps, opt=opt, targets=targets,
+            viewmat=torch.eye(3, 4, dtype=torch.float32, device=self.dev).contiguous(),
+            m=torch.zeros(6, device=self.dev), v=torch.zeros(6, device=self.dev), t=0,
+            last_T=None,
+            out=dict(color=torch.empty(3, spec.height, spec.width, device=self.dev),
+                     depth=torch.empty(spec.height, spec.width, device=self.dev),
+                     alpha=torch.empty(spec.height, spec.width, device=self.dev),
+                     final_T=torch.empty(spec.height, spec.width, device=self.dev),
+                     last_idx=torch.empty(spec.height, spec.width, dtype=torch.int32,
+                                          device=self.dev)),
+            gpose=torch.zeros(6, device=self.dev),
+            pmask=torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev))
+        torch.cuda.synchronize(self.dev)
+
+    def close_session(self, s):
+        """Evict: the session's tensors and optimiser state move to host memory."""
+        S = self.sessions.get(s)
+        if S is None or S.get("offloaded"):
+            return
+        S["opt_state"] = S["opt"].state_dict()
+        S["params"] = [p.detach().cpu() for p in S["params"]]
+        S["opt"] = None
+        for k in ("viewmat", "m", "v", "gpose", "pmask"):
+            S[k] = S[k].cpu()
+        S["targets"] = [(c.cpu(), d.cpu()) for c, d in S["targets"]]
+        S["out"] = {k: v.cpu() for k, v in S["out"].items()}
+        S["last_T"] = None
+        S["offloaded"] = True
+
+    def _restore(self, s):
+        torch = self.torch
+        S = self.sessions[s]
+        S["params"] = [p.to(self.dev).requires_grad_(True) for p in S["params"]]
+        S["opt"] = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in
+                                     zip(S["params"], (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3))],
+                                    eps=1e-15, foreach=True)
+        S["opt"].load_state_dict(S.pop("opt_state"))
+        for k in ("viewmat", "m", "v", "gpose", "pmask"):
+            S[k] = S[k].to(self.dev)
+        S["targets"] = [(c.to(self.dev), d.to(self.dev)) for c, d in S["targets"]]
+        S["out"] = {k: v.to(self.dev) for k, v in S["out"].items()}
+        S["offloaded"] = False
+
+    # ---- frames ----------------------------------------------------------------
+    def start_frame(self, f, spec):
+        S = self.sessions[f.session]
+        f.target = S["targets"][f.index % self.n_targets]
+        f.mask = None
+        if f.log2_ratio > 0 and S["last_T"] is not None:
+            self.rtgs.downsample_mask(S["last_T"], f.log2_ratio, S["pmask"])
+            f.mask = S["pmask"]
+
+    def finish_frame(self, f, spec):
+        S = self.sessions[f.session]
+        S["last_T"] = S["out"]["final_T"]
+
+    # ---- one iteration for a group of frames -----------------------------------
+    def run_iteration(self, phase, frames, specs):
+        torch, rtgs = self.torch, self.rtgs
+        items = []
+        cap = 0
+        for f in frames:
+            S = self.sessions[f.session]
+            o = S["out"]
+            items.append(dict(scene=tuple(p.detach() for p in S["params"]),
+                              viewmat=S["viewmat"], cam=S["cam"], pixel_mask=f.mask,
+                              color=o["color"], depth=o["depth"], alpha=o["alpha"],
+                              final_T=o["final_T"], last_idx=o["last_idx"]))
+            cap += self._cap(S["spec"])
+        ns = [S_["spec"].n for S_ in (self.sessions[f.session] for f in frames)]
+        ws_ = [self.sessions[f.session]["spec"].width for f in frames]
+        hs_ = [self.sessions[f.session]["spec"].height for f in frames]
+        ws = torch.empty(rtgs.rtgs_workspace_size_batched(ns, ws_, hs_, cap),
+                         dtype=torch.uint8, device=self.dev)
+        rtgs.render_fwd_batched(self.handle, items, ws, cap)
+        # L1 colour + 0.5 L1 depth over the active pixels of each frame
+        cs = [it["color"] for it in items]
+        ds = [it["depth"] for it in items]
+        tcs = [f.target[0] for f in frames]
+        tds = [f.target[1] for f in frames]
+        gcs = torch._foreach_sign(torch._foreach_sub(cs, tcs))
+        gds = torch._foreach_sign(torch._foreach_sub(ds, tds))
+        for f, gc, gd, it in zip(frames, gcs, gds, items):
+            npx = float(it["cam"].width * it["cam"].height) / (2 ** f.log2_ratio)
+            gc.mul_(1.0 / (3 * npx))
+            gd.mul_(0.5 / npx)
+            if f.mask is not None:
+                gc.mul_(f.mask)
+                gd.mul_(f.mask)
+            it["dL_dcolor"] = gc
+            it["dL_ddepth"] = gd
+        if phase == "track":
+            for f, it in zip(frames, items):
+                it["g_pose6"] = self.sessions[f.session]["gpose"]
+            rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=rtgs.RTGS_GRAD_POSE)
+            self._pose_step(frames)
+        else:
+            grads = []
+            for f, it in zip(frames, items):
+                S = self.sessions[f.session]
+                g = [torch.empty_like(p) for p in S["params"]]
+                it.update(g_means=g[0], g_log_scales=g[1], g_quats=g[2], g_opacity_logits=g[3],
+                          g_colors=g[4])
+                grads.append(g)
+            rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=rtgs.RTGS_GRAD_MAP)
+            for f, g in zip(frames, grads):
+                S = self.sessions[f.session]
+                for p, gg in zip(S["params"], g):
+                    p.grad = gg
+                S["opt"].step()
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        return ev
+
+    def _pose_step(self, frames, b1=0.9, b2=0.999, eps=1e-8):
+        """Adam on xi = (rho, phi) for every session of the group, vectorised,
+        then re-linearisation T <- Exp(-step) T (xi back to zero)."""
+        torch = self.torch
+        from .pose import apply_left
+        ss = [self.sessions[f.session] for f in frames]
+        g = torch.stack([S["gpose"] for S in ss])
+        m = torch.stack([S["m"] for S in ss])
+        v = torch.stack([S["v"] for S in ss])
+        t = torch.tensor([S["t"] + 1 for S in ss], dtype=torch.float32, device=self.dev)[:, None]
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        lr = torch.tensor([self.lr_rho] * 3 + [self.lr_phi] * 3, device=self.dev)
+        upd = lr * (m / (1 - b1 ** t)) / (torch.sqrt(v / (1 - b2 ** t)) + eps)
+        vm = torch.stack([S["viewmat"] for S in ss])
+        new = apply_left(-upd.double(), vm)
+        for k, S in enumerate(ss):
+            S["m"], S["v"] = m[k], v[k]
+            S["t"] += 1
+            S["viewmat"].copy_(new[k])
+
+    # ---- clock ----------------------------------------------------------------
+    def clock(self):
+        return time.perf_counter()
+
+    def warmup(self, specs, iters=2):
+        """One untimed tracking and mapping iteration per open session (first
+        launches, allocator growth)."""
+        for s in list(self.sessions):
+            spec = self.sessions[s]["spec"]
+            for phase in ("track", "map"):
+                f = Frame(s, 0, 0.0, True, 1, 1)
+                self.start_frame(f, spec)
+                for _ in range(iters):
+                    self.run_iteration(phase, [f], [spec])
+        self.sync()
+
+    def start_clock(self):
+        torch = self.torch
+        torch.cuda.synchronize(self.dev)
+        self.base_event = torch.cuda.Event(enable_timing=True)
+        self.base_event.record()
+        torch.cuda.synchronize(self.dev)
+        self.base_wall = 0.0
+
+    def idle(self, dt):
+        time.sleep(min(dt, 0.002))
+
+    def sync(self):
+        self.torch.cuda.synchronize(self.dev)
+
+    def event_time(self, ev):
+        return self.base_event.elapsed_time(ev) / 1e3
+
+    def verify(self):
+        code, pairs, _ = self.rtgs.rtgs_query(self.handle, True)
+        if code != self.rtgs.RTGS_OK:
+            self.overflows += 1
+        return pairs
+
+
+def _tiles(w, h):
+    return ((w + 15) // 16) * ((h + 15) // 16)
