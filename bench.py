@@ -74,7 +74,7 @@ def make_optimizer(params):
     import torch
     lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)
     return torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in zip(params, lrs)],
-                            eps=1e-15, foreach=True)
+                            eps=1e-15, fused=True)
 
 
 def l1_grads(color, depth, tc, td, pixel_mask=None):
@@ -209,6 +209,25 @@ def cpu_baseline(sc, cam, sample=192, seed=5):
             "seconds": dt}
 
 
+def serving_run(seconds, warmup_s, downsample, mode, seed=4242, rate=30.0):
+    """The 16-session serving mix on a Poisson trace (30 Hz per session)."""
+    from paper_2510_06644_amd import serving
+    specs = serving.serving_mix()
+    ex = serving.GpuExecutor(0)
+    cfg = serving.ServeConfig(mode=mode, downsample=downsample)
+    eng = serving.Engine(specs, ex, cfg)
+    eng.preopen()
+    ex.warmup(specs, iters=1)
+    trace = serving.poisson_trace(len(specs), rate, seconds, seed)
+    rep = eng.run(trace, warmup_s=warmup_s)
+    ex.verify()
+    rep["mode"] = mode
+    rep["downsample"] = downsample
+    rep["trace_s"] = seconds
+    rep["overflows"] = ex.overflows
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +236,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of the serving trace (0 disables the serving runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this path has no multi-GPU mode "
@@ -277,6 +298,14 @@ def main():
             mapping_step(R2, params2, view2, rc2, opt2, tc2, td2)
         R2.cap = R.cap
         variant = as_written_variant(R2, params2, view2, rc2, opt2, tc2, td2)
+    serve = None
+    if args.serve_seconds > 0:
+        serve = {}
+        for mode, ds in (("batched", True), ("serial", True), ("batched", False)):
+            log(f"serving {mode} downsample={ds}")
+            key = f"{mode}{'_downsampled' if ds else '_full_res'}"
+            serve[key] = serving_run(args.serve_seconds, min(0.5, args.serve_seconds / 4), ds,
+                                     mode)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -305,6 +334,7 @@ def main():
         "work": cnt,
         "host_wall_ms_per_step": 1000.0 * wall_ms,
         "as_written": variant,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

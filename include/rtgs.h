@@ -244,9 +244,10 @@ int32_t rtgs_downsample_log2_ratio(int32_t is_keyframe, int32_t n, int32_t k,
 
 /* Status (Sec. 5.5, the check-status call): with blocking != 0 waits for the
  * work enqueued through h, then reports in *pairs_needed (HOST, may be NULL)
- * the largest pair count any render_fwd needed since the previous query and
- * resets it; returns RTGS_ERR_CAPACITY if that exceeded the capacity it was
- * given.  With blocking == 0 and work pending, *state = RTGS_STATE_EXECUTING
+ * the largest pair count any render_fwd needed since the previous query, and
+ * resets.  Returns RTGS_ERR_CAPACITY if any of those calls needed more pairs
+ * than the capacity it was given (then *pairs_needed is the largest such
+ * need).  With blocking == 0 and work pending, *state = RTGS_STATE_EXECUTING
  * and nothing is reset. */
 int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed,
                    int32_t* state);

@@ -102,13 +102,13 @@ struct EventTimer : StageTimer {
 struct rtgs_context {
   int device = 0;
   EventTimer timer;
-  unsigned long long* d_scalars = nullptr;   // [0] largest pair count since last query
+  unsigned long long* d_scalars = nullptr;   // [0] largest pair count since last query,
+                                             // [1] largest count that overflowed (or 0)
   uint32_t* d_prune = nullptr;               // prune scratch
   SessionDev* h_ring = nullptr;              // pinned [kRing][RTGS_MAX_SESSIONS]
   hipEvent_t ring_ev[kRing] = {};
   int ring_pos = 0;
   hipStream_t last_stream = nullptr;
-  int64_t min_cap = INT64_MAX;               // smallest capacity since last query
   bool used = false;
 };
 
@@ -458,7 +458,6 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   if (e != hipSuccess) return hip_fail(e, "render_fwd launch");
   h->last_stream = st;
   h->used = true;
-  if (cap < h->min_cap) h->min_cap = cap;
   return RTGS_OK;
 }
 
@@ -586,18 +585,18 @@ int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed, int
     }
     if (q != hipSuccess) return hip_fail(q, "hipStreamQuery");
   }
-  unsigned long long got = 0, zero = 0;
-  hipError_t e = hipMemcpyAsync(&got, h->d_scalars, sizeof(got), hipMemcpyDeviceToHost, st);
+  unsigned long long got[2] = {0, 0}, zero[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(got, h->d_scalars, sizeof(got), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess) e = hipMemcpyAsync(h->d_scalars, &zero, sizeof(zero), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->d_scalars, zero, sizeof(zero), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "rtgs_query");
-  if (pairs_needed) *pairs_needed = (int64_t)got;
-  const int64_t cap = h->min_cap;
-  h->min_cap = INT64_MAX;
-  if ((int64_t)got > cap)
-    return fail(RTGS_ERR_CAPACITY, "a render needed %llu pairs, capacity %lld",
-                (unsigned long long)got, (long long)cap);
+  if (got[1] > 0) {
+    if (pairs_needed) *pairs_needed = (int64_t)got[1];
+    return fail(RTGS_ERR_CAPACITY, "a render needed %llu pairs, more than its capacity",
+                (unsigned long long)got[1]);
+  }
+  if (pairs_needed) *pairs_needed = (int64_t)got[0];
   return RTGS_OK;
 }
 

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
     const double t = 2.0 * log(255.0 * o);
     const float ex = (float)sqrt(t * P.sxx);
     const float ey = (float)sqrt(t * P.syy);
-    W.ext[gid] = make_float4(ex, ey, 0.f, 0.f);
+    W.ext[gid] = make_float4(ex, ey, (float)t, 0.f);
     // padded pixel range in float32, fixed operation order (see the replay)
     const float lox = floorf((uh - ex) - 1.5f), hix = ceilf((uh + ex) + 0.5f);
     const float loy = floorf((vh - ey) - 1.5f), hiy = ceilf((vh + ey) + 0.5f);
@@ -277,7 +277,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_tot
   block_scan_1024(W.chunk_total, W.chunk_off, c_total, part);
   if (threadIdx.x == 0) {
     W.counters[0] = (long long)total;
-    atomicMax(max_pairs, (unsigned long long)total);
+    // [0]: largest pair count of any call; [1]: largest count of a call whose
+    // capacity it exceeded (0 if none)
+    atomicMax(&max_pairs[0], (unsigned long long)total);
+    if ((int64_t)total > W.cap) atomicMax(&max_pairs[1], (unsigned long long)total);
   }
 }
 

@@ -64,19 +64,50 @@ __device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile) {
   return c;
 }
 
-// Bit w set when the padded bounding box of the alpha >= 1/255 ellipse meets
-// the 8x8 quadrant of wave w.
-__device__ __forceinline__ unsigned quad_mask(float4 r0, float4 ex, int tx0, int ty0) {
-  const float lox = floorf((r0.x - ex.x) - 1.5f), hix = ceilf((r0.x + ex.x) + 0.5f);
-  const float loy = floorf((r0.y - ex.y) - 1.5f), hiy = ceilf((r0.y + ex.y) + 0.5f);
+// Smallest value of the quadratic form q(d) = a dx^2 + 2 b dx dy + c dy^2
+// over the box [x0, x1] x [y0, y1] of offsets d (a convex quadratic: zero if
+// the box holds the centre, otherwise reached on an edge, where it is a 1D
+// quadratic minimised in closed form and clamped to the edge).
+__device__ __forceinline__ float box_min_quad(float a, float b, float c, float x0, float x1,
+                                              float y0, float y1) {
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
+  float m = 3.0e38f;
+  const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float X = xs[e];                           // edge dx = X
+    const float dy = fminf(y1, fmaxf(y0, c > 0.f ? -b * X / c : 0.f));
+    m = fminf(m, a * X * X + 2.f * b * X * dy + c * dy * dy);
+    const float Y = ys[e];                           // edge dy = Y
+    const float dx = fminf(x1, fmaxf(x0, a > 0.f ? -b * Y / a : 0.f));
+    m = fminf(m, a * dx * dx + 2.f * b * dx * Y + c * Y * Y);
+  }
+  return m;
+}
+
+// Bit w set when the alpha >= 1/255 ellipse (q <= t) of the Gaussian can
+// reach a pixel centre of the 8x8 quadrant of wave w.  The margin keeps the
+// test conservative against the float32 evaluation of alpha.
+__device__ __forceinline__ unsigned quad_mask(float4 r0, float4 r1, float4 ex, int tx0, int ty0) {
+  const float u = r0.x + r0.z, v = r0.y + r0.w;
+  const float t = ex.z * (1.f + 1e-3f) + 1e-3f;
   unsigned m = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    const float qx = (float)(tx0 + (w & 1) * 8), qy = (float)(ty0 + (w >> 1) * 8);
-    const bool hit = hix >= qx && lox <= qx + 7.f && hiy >= qy && loy <= qy + 7.f;
-    m |= hit ? (1u << w) : 0u;
+    const float qx = (float)(tx0 + (w & 1) * 8) + 0.5f - u;
+    const float qy = (float)(ty0 + (w >> 1) * 8) + 0.5f - v;
+    const float q = box_min_quad(r1.x, r1.y, r1.z, qx, qx + 7.f, qy, qy + 7.f);
+    m |= (q <= t) ? (1u << w) : 0u;
   }
   return m;
+}
+
+// 64-bit ballot of "entry (base + lane) is in this wave's quadrant".
+__device__ __forceinline__ unsigned long long wave_entries(const unsigned* s_m, int base, int cnt,
+                                                           unsigned wbit) {
+  const int k = base + (int)(threadIdx.x & 63);
+  const bool hit = k < cnt && (s_m[k] & wbit) != 0;
+  return __ballot(hit);
 }
 
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
@@ -101,24 +132,28 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     const int64_t e = b0 + tid;
     if (e < end) {
       const uint32_t g = W.ids[e];
-      const float4 r0 = W.rec0[g];
+      const float4 r0 = W.rec0[g], r1 = W.rec1[g];
       s_r0[tid] = r0;
-      s_r1[tid] = W.rec1[g];
+      s_r1[tid] = r1;
       s_r2[tid] = W.rec2[g];
-      s_m[tid] = quad_mask(r0, W.ext[g], c.tile_x0, c.tile_y0);
+      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0);
     }
     __syncthreads();
     const int cnt = (int)min((int64_t)kBlock, end - b0);
-    if (!done) {
-      for (int k = 0; k < cnt; ++k) {
-        if (!(s_m[k] & c.wbit)) continue;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
+      while (m) {
+        if (__ballot(!done) == 0) break;               // the whole wave has stopped
+        const int k = 64 * q + __builtin_ctzll(m);
+        m &= m - 1;
+        if (done) continue;
         const Frag f = frag_alpha(s_r0[k], s_r1[k], pxf, pyf);
         if (f.alpha < kAlphaMin) continue;
-        const float tn = T * (1.f - f.alpha);
+        const float tn = T * f.om;
         if (tn < kTMin) {
           done = true;
           stop = b0 + k;
-          break;
+          continue;
         }
         const float w = f.alpha * T;
         const float4 col = s_r2[k];
@@ -154,7 +189,6 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
 }
 
 constexpr int kBwdBatch = 128;           // list entries staged per batch
-constexpr int kPartStride = kBwdBatch + 1;  // odd row stride: conflict-free LDS writes
 
 // Gaussian-major slot of the pair (Gaussian g, tile (tx, ty)): g's first slot
 // plus the tile's row-major index inside g's tile rectangle.
@@ -170,9 +204,10 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 // bitwise reproducible and no float atomics are used.
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
+  constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
   __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch];
   __shared__ unsigned s_m[kBwdBatch];
-  __shared__ float s_part[4][NV][kPartStride];
+  __shared__ float s_part[4][kBwdBatch * kStride];
   __shared__ int s_hi;
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
@@ -205,22 +240,28 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   const int64_t hi = min((int64_t)s_hi, end - 1);
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
   float S0 = 0.f, S1 = 0.f, S2 = 0.f, Sz = 0.f;   // suffix sums normalised by T
+  float* part = s_part[wave];
   for (int64_t bend = hi + 1; bend > start; bend -= kBwdBatch) {
     const int64_t b0 = bend - kBwdBatch > start ? bend - kBwdBatch : start;
     const int cnt = (int)(bend - b0);
     __syncthreads();
     if (tid < cnt) {
       const uint32_t g = W.ids[b0 + tid];
-      const float4 r0 = W.rec0[g];
+      const float4 r0 = W.rec0[g], r1 = W.rec1[g];
       s_r0[tid] = r0;
-      s_r1[tid] = W.rec1[g];
+      s_r1[tid] = r1;
       s_r2[tid] = W.rec2[g];
-      s_m[tid] = quad_mask(r0, W.ext[g], c.tile_x0, c.tile_y0);
+      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0);
     }
+    // zero this batch's partial sums (each wave its own)
+    for (int i = lane; i < kBwdBatch * kStride; i += 64) part[i] = 0.f;
     __syncthreads();
-    for (int k = cnt - 1; k >= 0; --k) {
-      float mine = 0.f;
-      if (s_m[k] & c.wbit) {
+    for (int q = kBwdBatch / 64 - 1; q >= 0; --q) {
+      unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
+      while (m) {
+        const int bit = 63 - __builtin_clzll(m);       // descending list order
+        m &= ~(1ull << bit);
+        const int k = 64 * q + bit;
         float v[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) v[i] = 0.f;
@@ -231,14 +272,15 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
           if (f.alpha >= kAlphaMin) {
             contrib = true;
             const float4 col = s_r2[k];
-            const float om = 1.f - f.alpha;
-            const float Tj = Tc / om;                     // T before this fragment
+            const float om = f.om;
+            const float rom = __builtin_amdgcn_rcpf(om);
+            const float Tj = Tc * rom;                    // T before this fragment
             const float w = f.alpha * Tj;
             float dla = (col.x - S0) * g0;
             dla = __builtin_fmaf(col.y - S1, g1, dla);
             dla = __builtin_fmaf(col.z - S2, g2, dla);
             dla = __builtin_fmaf(col.w - Sz, gD, dla);
-            dla = __builtin_fmaf(Tj, dla, gAT / om);      // dL/dalpha
+            dla = __builtin_fmaf(Tj, dla, gAT * rom);     // dL/dalpha
             S0 = __builtin_fmaf(f.alpha, col.x, om * S0);
             S1 = __builtin_fmaf(f.alpha, col.y, om * S1);
             S2 = __builtin_fmaf(f.alpha, col.z, om * S2);
@@ -262,14 +304,14 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
           }
         }
         if (__ballot(contrib)) {
-          float tot[NV];
 #pragma unroll
-          for (int i = 0; i < NV; ++i) tot[i] = read_lane63(wave_sum_to_lane63(v[i]));
+          for (int i = 0; i < NV; ++i) v[i] = wave_sum_to_lane63(v[i]);
+          if (lane == 63) {
 #pragma unroll
-          for (int i = 0; i < NV; ++i) mine = lane == i ? tot[i] : mine;
+            for (int i = 0; i < NV; ++i) part[k * kStride + i] = v[i];
+          }
         }
       }
-      if (lane < NV) s_part[wave][lane][k] = mine;
     }
     __syncthreads();
     if (tid < cnt) {
@@ -278,8 +320,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
       if (slot < W.cap) {
         float* dst = W.partial + slot * NV;
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-          dst[i] = ((s_part[0][i][tid] + s_part[1][i][tid]) + s_part[2][i][tid]) + s_part[3][i][tid];
+        for (int i = 0; i < NV; ++i) {
+          const int o = tid * kStride + i;
+          dst[i] = ((s_part[0][o] + s_part[1][o]) + s_part[2][o]) + s_part[3][o];
+        }
       }
     }
   }

@@ -218,14 +218,17 @@ __device__ __forceinline__ float dpp_f(float v) {
 
 // Sum over the 64 lanes of a wavefront; the total lands in lane 63 (other
 // lanes hold partial sums).  Inclusive row scans by shifted adds within each
-// 16-lane row, then the row totals are carried across rows by broadcasts.
+// 16-lane row (out-of-row sources read 0), then the row totals are carried
+// across rows by the two broadcasts (lane 15 of each row to the next row,
+// lane 31 to rows 2 and 3; rows without a source read 0).  Each step is one
+// v_add_f32 with a DPP source operand.
 __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   v += dpp_f<kDppRowShr1, 0xf, true>(v);
   v += dpp_f<kDppRowShr2, 0xf, true>(v);
   v += dpp_f<kDppRowShr4, 0xf, true>(v);
   v += dpp_f<kDppRowShr8, 0xf, true>(v);
-  v += dpp_f<kDppRowBcast15, 0xa, false>(v);
-  v += dpp_f<kDppRowBcast31, 0xc, false>(v);
+  v += dpp_f<kDppRowBcast15, 0xf, true>(v);
+  v += dpp_f<kDppRowBcast31, 0xf, true>(v);
   return v;
 }
 
@@ -238,6 +241,7 @@ __device__ __forceinline__ float read_lane63(float v) {
 // r0 = (u_hi, v_hi, u_lo, v_lo), r1 = (a, b, c, opacity).
 struct Frag {
   float dx, dy, e, alpha;   // e = exp(power), alpha = min(0.99, o e)
+  float om;                 // 1 - alpha, from one fused rounding of 1 - o e
 };
 
 __device__ __forceinline__ Frag frag_alpha(float4 r0, float4 r1, float px, float py) {
@@ -250,7 +254,11 @@ __device__ __forceinline__ Frag frag_alpha(float4 r0, float4 r1, float px, float
   const float quad = __builtin_fmaf(qa, f.dx, qc * f.dy);
   const float power = __builtin_fmaf(-0.5f, quad, -(r1.y * f.dx) * f.dy);
   f.e = __expf(power);
-  f.alpha = fminf(kAlphaMax, r1.w * f.e);
+  const float raw = r1.w * f.e;
+  f.alpha = fminf(kAlphaMax, raw);
+  // 1 - alpha without rounding o e first: near-opaque fragments (alpha close
+  // to 0.99) would otherwise lose digits of the transmittance they leave
+  f.om = raw > kAlphaMax ? 1.f - kAlphaMax : __builtin_fmaf(-r1.w, f.e, 1.f);
   return f;
 }
 

@@ -430,7 +430,7 @@ class GpuExecutor:
         maps = [p.clone().requires_grad_(True) for p in params]
         opt = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in
                                 zip(maps, (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3))],
-                               eps=1e-15, foreach=True)
+                               eps=1e-15, fused=True)
         self.sessions[s] = dict(
             spec=spec, cam=rc, params=maps, opt=opt, targets=targets,
             viewmat=torch.eye(3, 4, dtype=torch.float32, device=self.dev).contiguous(),
@@ -467,7 +467,7 @@ class GpuExecutor:
         S["params"] = [p.to(self.dev).requires_grad_(True) for p in S["params"]]
         S["opt"] = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in
                                      zip(S["params"], (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3))],
-                                    eps=1e-15, foreach=True)
+                                    eps=1e-15, fused=True)
         S["opt"].load_state_dict(S.pop("opt_state"))
         for k in ("viewmat", "m", "v", "gpose", "pmask"):
             S[k] = S[k].to(self.dev)
