@@ -66,6 +66,21 @@ extern "C" {
 #define RTGS_GRAD_RECOMPUTE_STATE 8 /* final_T/last_idx were not saved: the
                                        backward recomputes them first          */
 
+/* ---- downsampled rendering (Sec. 4.2) ----
+ * A frame downsampled to one pixel in 2^j (j = 2, 3, 4; 1 also accepted) is
+ * rendered with one sample per block of 2^ceil(j/2) x 2^floor(j/2) pixels:
+ * tiles of 16x16 samples, so the work scales with the samples, not the
+ * pixels.  The sample of each block is the first pixel (raster order) the
+ * pixel mask keeps in it; downsample_mask with the same j keeps exactly one.
+ * All other pixels render as background (0, final_T = 1, last_idx = -1).
+ * Per pixel the result equals rendering with that pixel mask at j = 0.
+ * Single-session calls pass j in bits 8..11 of flags / grad_flags
+ * (RTGS_SAMPLE_LOG2(j)); batched calls use rtgs_session.sample_log2.  The
+ * forward and its backward must use the same j.  Workspace sizes computed
+ * with j = 0 suffice for any j. */
+#define RTGS_SAMPLE_SHIFT     8
+#define RTGS_SAMPLE_LOG2(j)   ((j) << RTGS_SAMPLE_SHIFT)
+
 /* ---- query states (Sec. 5.5: IDLE / EXECUTING) ---- */
 #define RTGS_STATE_IDLE       0
 #define RTGS_STATE_EXECUTING  1
@@ -103,6 +118,7 @@ typedef struct {
   rtgs_gaussians g;
   rtgs_camera cam;
   const uint8_t* pixel_mask;   /* [H][W] or NULL (all pixels active) */
+  int32_t sample_log2;         /* 0, or j of a downsampled frame (see above) */
   /* forward outputs */
   float* color;                /* [3][H][W] */
   float* depth;                /* [H][W] expected depth sum w z */
@@ -253,8 +269,8 @@ int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed,
                    int32_t* state);
 
 /* Test access to forward intermediates kept in a workspace after render_fwd.
- * n, width, height (HOST arrays of n_sessions) and pair_capacity must be those
- * of that call.  All outputs are device arrays and any may be NULL: per
+ * n, width, height, sample_log2 (HOST arrays of n_sessions; sample_log2 may
+ * be NULL for all zero) and pair_capacity must be those of that call.  All outputs are device arrays and any may be NULL: per
  * Gaussian of the batch (global index over sessions)
  *   stage [n][12] = u, v, conic a, b, c, opacity, depth z, e_x, e_y,
  *                   r, g, b   (u, v: float32 part of the centre; e_x, e_y:
@@ -264,7 +280,8 @@ int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed,
  * per tile of the batch: ranges [T][2] = [start, end) into ids; ids [P] =
  * Gaussian ids in tile-then-depth order (at most ids_capacity written). */
 int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width,
-                         const int32_t* height, int32_t n_sessions,
+                         const int32_t* height, const int32_t* sample_log2,
+                         int32_t n_sessions,
                          int64_t pair_capacity, const void* ws,
                          uint64_t ws_bytes, float* stage, int32_t* rect,
                          int32_t* ranges, int32_t* ids, int64_t ids_capacity,

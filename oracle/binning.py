@@ -30,9 +30,10 @@ import numpy as np
 TILE = 16
 
 
-def tile_rects(u, v, ex, ey, valid, width, height):
+def tile_rects(u, v, ex, ey, valid, width, height, tile_w=TILE, tile_h=TILE):
     """Per-Gaussian inclusive tile rectangle (tx0, ty0, tx1, ty1); empty rows
-    get tx1 < tx0."""
+    get tx1 < tx0.  Tiles are tile_w x tile_h pixels (16 x 16, or larger for a
+    frame rendered with one sample per block of pixels)."""
     f = np.float32
     u, v, ex, ey = (np.asarray(t, dtype=np.float32) for t in (u, v, ex, ey))
     lo_x = np.floor((u - ex) - f(1.5))
@@ -47,17 +48,17 @@ def tile_rects(u, v, ex, ey, valid, width, height):
         j0 = np.clip(lo_y, 0, height - 1)
         j1 = np.clip(hi_y, 0, height - 1)
     i0, i1, j0, j1 = (np.nan_to_num(t).astype(np.int64) for t in (i0, i1, j0, j1))
-    tx0, tx1, ty0, ty1 = i0 // TILE, i1 // TILE, j0 // TILE, j1 // TILE
+    tx0, tx1, ty0, ty1 = i0 // tile_w, i1 // tile_w, j0 // tile_h, j1 // tile_h
     tx1 = np.where(empty, tx0 - 1, tx1)
     return tx0, ty0, tx1, ty1
 
 
-def tile_lists(u, v, ex, ey, z, valid, width, height):
+def tile_lists(u, v, ex, ey, z, valid, width, height, tile_w=TILE, tile_h=TILE):
     """Sorted tile lists: (ranges [T,2] int64, ids [P] int64), tiles in
     row-major order."""
-    tiles_x = (width + TILE - 1) // TILE
-    tiles_y = (height + TILE - 1) // TILE
-    tx0, ty0, tx1, ty1 = tile_rects(u, v, ex, ey, valid, width, height)
+    tiles_x = (width + tile_w - 1) // tile_w
+    tiles_y = (height + tile_h - 1) // tile_h
+    tx0, ty0, tx1, ty1 = tile_rects(u, v, ex, ey, valid, width, height, tile_w, tile_h)
     nx = np.maximum(tx1 - tx0 + 1, 0)
     ny = np.where(nx > 0, np.maximum(ty1 - ty0 + 1, 0), 0)
     cnt = nx * ny

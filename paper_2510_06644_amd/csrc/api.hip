@@ -36,8 +36,13 @@ constexpr uint64_t kAlign = 256;
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int64_t tiles_of(int w, int h) {
-  return (int64_t)((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+// Sample block of a downsampled frame: 2^ceil(j/2) x 2^floor(j/2) pixels.
+int sub_sx(int j) { return (j + 1) / 2; }
+int sub_sy(int j) { return j / 2; }
+
+int64_t tiles_of(int w, int h, int j = 0) {
+  const int tw = kTile << sub_sx(j), th = kTile << sub_sy(j);
+  return (int64_t)((w + tw - 1) / tw) * ((h + th - 1) / th);
 }
 
 int64_t blocks_of(int n) { return (n + kGaussPerBlock - 1) / kGaussPerBlock; }
@@ -137,6 +142,7 @@ WsLayout make_layout(const Counts& c, int64_t cap) {
   L.chunk_total = take(4 * (uint64_t)(c.c_total + 1));
   L.chunk_off = take(4 * (uint64_t)(c.c_total + 1));
   L.hist = take(4 * (uint64_t)c.h_total);
+  L.gsum = take(4 * 16 * t);
   L.tile_count = take(4 * (t + 1));
   L.tile_start = take(4 * (t + 1));
   L.keys = take(8 * (uint64_t)cap);
@@ -169,6 +175,7 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.chunk_total = reinterpret_cast<uint32_t*>(base + L.chunk_total);
   w.chunk_off = reinterpret_cast<uint32_t*>(base + L.chunk_off);
   w.hist = reinterpret_cast<uint32_t*>(base + L.hist);
+  w.gsum = reinterpret_cast<uint32_t*>(base + L.gsum);
   w.tile_count = reinterpret_cast<uint32_t*>(base + L.tile_count);
   w.tile_start = reinterpret_cast<uint32_t*>(base + L.tile_start);
   w.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
@@ -184,14 +191,18 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
 
 namespace {
 
-int32_t geometry(const int32_t* n, const int32_t* w, const int32_t* h, int32_t ns, Counts& g) {
+int32_t geometry(const int32_t* n, const int32_t* w, const int32_t* h, int32_t ns, Counts& g,
+                 const int32_t* js = nullptr) {
   if (ns < 1 || ns > RTGS_MAX_SESSIONS)
     return fail(RTGS_ERR_INVALID_ARG, "n_sessions %d outside [1, %d]", ns, RTGS_MAX_SESSIONS);
   for (int s = 0; s < ns; ++s) {
     if (n[s] < 0) return fail(RTGS_ERR_INVALID_ARG, "session %d: n = %d < 0", s, n[s]);
     if (w[s] <= 0 || h[s] <= 0)
       return fail(RTGS_ERR_INVALID_ARG, "session %d: image %d x %d", s, w[s], h[s]);
-    const int64_t t = tiles_of(w[s], h[s]);
+    const int j = js ? js[s] : 0;
+    if (j < 0 || j > 4)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: sample_log2 %d outside [0, 4]", s, j);
+    const int64_t t = tiles_of(w[s], h[s], j);
     if (t > kMaxTilesPerSession)
       return fail(RTGS_ERR_INVALID_ARG, "session %d: %lld tiles > %d (image too large)", s,
                   (long long)t, kMaxTilesPerSession);
@@ -269,8 +280,10 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
     d.n = s.g.n;
     d.width = s.cam.width;
     d.height = s.cam.height;
-    d.tiles_x = (s.cam.width + kTile - 1) / kTile;
-    d.tiles_y = (s.cam.height + kTile - 1) / kTile;
+    d.sub_sx = sub_sx(s.sample_log2);
+    d.sub_sy = sub_sy(s.sample_log2);
+    d.tiles_x = (s.cam.width + (kTile << d.sub_sx) - 1) / (kTile << d.sub_sx);
+    d.tiles_y = (s.cam.height + (kTile << d.sub_sy) - 1) / (kTile << d.sub_sy);
     d.fx = s.cam.fx;
     d.fy = s.cam.fy;
     d.cx = s.cam.cx;
@@ -313,7 +326,7 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
     t[i] = d;
     gbase += s.g.n;
     bbase += (int32_t)blocks_of(s.g.n);
-    const int32_t ts = (int32_t)tiles_of(s.cam.width, s.cam.height);
+    const int32_t ts = (int32_t)tiles_of(s.cam.width, s.cam.height, s.sample_log2);
     tbase += ts;
     cbase += (int32_t)chunks_of(s.g.n);
     hbase += chunks_of(s.g.n) * ts;
@@ -342,14 +355,17 @@ int32_t prepare(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws, u
     return fail(RTGS_ERR_INVALID_ARG, "n_sessions %d outside [1, %d]", ns, RTGS_MAX_SESSIONS);
   int32_t r = check_cap(cap);
   if (r) return r;
-  std::vector<int32_t> n(ns), wd(ns), ht(ns);
+  std::vector<int32_t> n(ns), wd(ns), ht(ns), js(ns);
   for (int i = 0; i < ns; ++i) {
     n[i] = ss[i].g.n;
     wd[i] = ss[i].cam.width;
     ht[i] = ss[i].cam.height;
+    js[i] = ss[i].sample_log2;
+    if (js[i] > 0 && !ss[i].pixel_mask)
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: sample_log2 > 0 needs a pixel mask", i);
   }
   Counts g;
-  r = geometry(n.data(), wd.data(), ht.data(), ns, g);
+  r = geometry(n.data(), wd.data(), ht.data(), ns, g, js.data());
   if (r) return r;
   if (!ws) return fail(RTGS_ERR_INVALID_ARG, "null workspace");
   L = make_layout(g, cap);
@@ -432,13 +448,22 @@ int32_t rtgs_workspace_size_batched(const int32_t* n, const int32_t* width, cons
 
 int32_t rtgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t pair_capacity,
                             int32_t flags, uint64_t* bytes) {
-  return rtgs_workspace_size_batched(&n, &width, &height, 1, pair_capacity, flags, bytes);
+  if (!bytes) return fail(RTGS_ERR_INVALID_ARG, "null argument");
+  int32_t r = check_cap(pair_capacity);
+  if (r) return r;
+  const int32_t j = (flags >> RTGS_SAMPLE_SHIFT) & 0xf;
+  Counts g;
+  r = geometry(&n, &width, &height, 1, g, &j);
+  if (r) return r;
+  *bytes = make_layout(g, pair_capacity).total;
+  return RTGS_OK;
 }
 
 int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
   if (flags & ~(RTGS_FWD_SAVE_STATE | RTGS_FWD_STATS))
-    return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
+    return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d (sample_log2 goes in the sessions)",
+                flags);
   WsLayout L;
   WsPtrs w;
   int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w);
@@ -494,6 +519,8 @@ int32_t render_fwd(rtgs_handle_t h, const rtgs_gaussians* g, const rtgs_camera* 
                    int32_t* last_idx, uint8_t* visible_out, int32_t flags, void* stream) {
   if (!g || !cam) return fail(RTGS_ERR_INVALID_ARG, "null gaussians or camera");
   rtgs_session s = single(g, cam, pixel_mask);
+  s.sample_log2 = (flags >> RTGS_SAMPLE_SHIFT) & 0xf;
+  flags &= ~(0xf << RTGS_SAMPLE_SHIFT);
   s.color = out_color;
   s.depth = out_depth;
   s.alpha = out_alpha;
@@ -512,6 +539,8 @@ int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g, const rtgs_camera* 
                    void* stream) {
   if (!g || !cam) return fail(RTGS_ERR_INVALID_ARG, "null gaussians or camera");
   rtgs_session s = single(g, cam, pixel_mask);
+  s.sample_log2 = (grad_flags >> RTGS_SAMPLE_SHIFT) & 0xf;
+  grad_flags &= ~(0xf << RTGS_SAMPLE_SHIFT);
   s.final_T = const_cast<float*>(final_T);
   s.last_idx = const_cast<int32_t*>(last_idx);
   s.dL_dcolor = dL_dcolor;
@@ -601,14 +630,14 @@ int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed, int
 }
 
 int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width, const int32_t* height,
-                         int32_t n_sessions, int64_t pair_capacity, const void* ws,
-                         uint64_t ws_bytes, float* stage, int32_t* rect, int32_t* ranges,
-                         int32_t* ids, int64_t ids_capacity, void* stream) {
+                         const int32_t* sample_log2, int32_t n_sessions, int64_t pair_capacity,
+                         const void* ws, uint64_t ws_bytes, float* stage, int32_t* rect,
+                         int32_t* ranges, int32_t* ids, int64_t ids_capacity, void* stream) {
   if (!n || !width || !height || !ws) return fail(RTGS_ERR_INVALID_ARG, "null argument");
   int32_t r = check_cap(pair_capacity);
   if (r) return r;
   Counts g;
-  r = geometry(n, width, height, n_sessions, g);
+  r = geometry(n, width, height, n_sessions, g, sample_log2);
   if (r) return r;
   const WsLayout L = make_layout(g, pair_capacity);
   if (ws_bytes < L.total) return fail(RTGS_ERR_WORKSPACE, "workspace too small");

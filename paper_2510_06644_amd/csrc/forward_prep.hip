@@ -9,7 +9,7 @@
 //    compositing matches the float64 definition far below 1e-4;
 //  * binning is a counting sort by tile without global atomics (device-scope
 //    atomics cross the XCDs and serialise): each workgroup takes a chunk of
-//    2048 Gaussians and counts its (tile, Gaussian) pairs per tile in an LDS
+//    1024 Gaussians and counts its (tile, Gaussian) pairs per tile in an LDS
 //    histogram; a column scan over chunks turns the counts into per
 //    (chunk, tile) offsets; a second pass over the chunk scatters
 //    (depth bits, id) keys through LDS-atomic cursors.  The same pass writes
@@ -136,7 +136,8 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
     if (!(hix < 0.f || lox > (float)(S.width - 1) || hiy < 0.f || loy > (float)(S.height - 1))) {
       const int i0 = (int)fmaxf(lox, 0.f), i1 = (int)fminf(hix, (float)(S.width - 1));
       const int j0 = (int)fmaxf(loy, 0.f), j1 = (int)fminf(hiy, (float)(S.height - 1));
-      rect = make_int4(i0 / kTile, j0 / kTile, i1 / kTile, j1 / kTile);
+      const int shx = 4 + S.sub_sx, shy = 4 + S.sub_sy;   // tile = (16 bw) x (16 bh)
+      rect = make_int4(i0 >> shx, j0 >> shy, i1 >> shx, j1 >> shy);
     }
   } else {
     W.rec0[gid] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -151,8 +152,8 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
 }
 
 // In-chunk exclusive offsets of the Gaussians' tile counts, in local index
-// order, into s_off[0..kChunk); returns the chunk's pair total.  Local index
-// i = j * 256 + thread for round j.
+// order, into s_off[0..kChunk]; s_off[kChunk] = the chunk's pair total, which
+// is returned.  Local index i = j * 256 + thread for round j.
 __device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, uint32_t* s_off,
                                   uint32_t* s_wave) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -177,30 +178,57 @@ __device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, u
     carry += tot;
     __syncthreads();
   }
+  if (threadIdx.x == 0) s_off[kChunk] = carry;
+  __syncthreads();
   return carry;
 }
 
-// Pair m of the chunk -> (local Gaussian index, tile index within the session).
-__device__ __forceinline__ int chunk_pair(const SessionDev& S, const WsPtrs& W, int c,
-                                          const uint32_t* s_off, uint32_t m, int& tile) {
-  int lo = 0, hi = kChunk - 1;          // last i with s_off[i] <= m
+// Walk this thread's share of the chunk's pairs: pairs [m0, m1) in
+// Gaussian-major order, m0 = thread * ceil(total / 256).  One binary search
+// finds the first Gaussian; after that the walk steps through tiles of the
+// Gaussian's rectangle row by row and on to the next Gaussian, so pairs are
+// spread evenly however many tiles a Gaussian touches.  f(local index, tile)
+// is called for every pair.
+template <typename F>
+__device__ __forceinline__ void chunk_pairs(const SessionDev& S, const WsPtrs& W, int c,
+                                            const uint32_t* s_off, uint32_t total, F f) {
+  const uint32_t per = (total + kBlock - 1) / kBlock;
+  const uint32_t m0 = threadIdx.x * per;
+  const uint32_t m1 = min(total, m0 + per);
+  if (m0 >= m1) return;
+  int lo = 0, hi = kChunk - 1;          // last i with s_off[i] <= m0
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (s_off[mid] <= m) lo = mid; else hi = mid - 1;
+    if (s_off[mid] <= m0) lo = mid; else hi = mid - 1;
   }
-  const int gid = S.gauss_base + c * kChunk + lo;
-  const int4 r = W.rect[gid];
-  const int w = r.z - r.x + 1;
-  const int k = (int)(m - s_off[lo]);
-  tile = (r.y + k / w) * S.tiles_x + (r.x + k % w);
-  return lo;
+  int i = lo;
+  int4 r = W.rect[S.gauss_base + c * kChunk + i];
+  int w = r.z - r.x + 1;
+  const int k0 = (int)(m0 - s_off[i]);
+  int tx = r.x + k0 % w, ty = r.y + k0 / w;
+  for (uint32_t m = m0; m < m1; ++m) {
+    while (m >= s_off[i + 1]) {           // next Gaussian with pairs
+      ++i;
+      if (m < s_off[i + 1]) {
+        r = W.rect[S.gauss_base + c * kChunk + i];
+        w = r.z - r.x + 1;
+        tx = r.x;
+        ty = r.y;
+      }
+    }
+    f(i, ty * S.tiles_x + tx);
+    if (++tx > r.z) {
+      tx = r.x;
+      ++ty;
+    }
+  }
 }
 
-// Per chunk of 2048 Gaussians: pair counts per tile of the session (LDS
+// Per chunk of kChunk Gaussians: pair counts per tile of the session (LDS
 // histogram), and the chunk's pair total.
 __global__ __launch_bounds__(kBlock) void k_chunk_hist(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_hist[];
-  __shared__ uint32_t s_off[kChunk];
+  __shared__ uint32_t s_off[kChunk + 1];
   __shared__ uint32_t s_wave[kBlock / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
@@ -210,35 +238,63 @@ __global__ __launch_bounds__(kBlock) void k_chunk_hist(Batch B, WsPtrs W) {
   for (int t = threadIdx.x; t < ts; t += kBlock) s_hist[t] = 0u;
   const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
   // pairs are dealt evenly over the threads, whatever the Gaussians' sizes
-  for (uint32_t m = threadIdx.x; m < total; m += kBlock) {
-    int tile;
-    chunk_pair(S, W, c, s_off, m, tile);
-    atomicAdd(&s_hist[tile], 1u);
-  }
+  chunk_pairs(S, W, c, s_off, total, [&](int, int tile) { atomicAdd(&s_hist[tile], 1u); });
   __syncthreads();
   uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
   for (int t = threadIdx.x; t < ts; t += kBlock) h[t] = s_hist[t];
   if (threadIdx.x == 0) W.chunk_total[blockIdx.x] = total;
 }
 
-// One thread per tile: exclusive scan of its counts over the session's
-// chunks (in place), and the tile's pair count.
-__global__ __launch_bounds__(kBlock) void k_tile_scan(Batch B, WsPtrs W) {
+// Column scan of the per-(chunk, tile) counts, in two passes with one thread
+// per (tile, group of chunks): group sums, then each group's exclusive prefix
+// written back in place.  The group of the last chunks also writes the tile's
+// pair count.
+constexpr int kScanGroups = 16;
+
+__device__ __forceinline__ void tile_groups(const SessionDev& S, int g, int& c0, int& c1) {
+  const int nc = (S.n + kChunk - 1) / kChunk;
+  const int per = (nc + kScanGroups - 1) / kScanGroups;
+  c0 = min(nc, g * per);
+  c1 = min(nc, c0 + per);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_group_sums(Batch B, WsPtrs W) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int g = blockIdx.y;
   if (t >= B.t_total) return;
   const int s = find_session(B.sess, B.n_sessions, t,
                              [](const SessionDev& x) { return x.tile_base; });
   const SessionDev& S = B.sess[s];
   const int ts = S.tiles_x * S.tiles_y;
-  const int nc = (S.n + kChunk - 1) / kChunk;
-  uint32_t* h = W.hist + S.hist_base + (t - S.tile_base);
+  int c0, c1;
+  tile_groups(S, g, c0, c1);
+  const uint32_t* h = W.hist + S.hist_base + (t - S.tile_base);
+  uint32_t sum = 0;
+#pragma unroll 4
+  for (int c = c0; c < c1; ++c) sum += h[(int64_t)c * ts];
+  W.gsum[(int64_t)g * B.t_total + t] = sum;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_group_scan(Batch B, WsPtrs W) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int g = blockIdx.y;
+  if (t >= B.t_total) return;
+  const int s = find_session(B.sess, B.n_sessions, t,
+                             [](const SessionDev& x) { return x.tile_base; });
+  const SessionDev& S = B.sess[s];
+  const int ts = S.tiles_x * S.tiles_y;
   uint32_t run = 0;
-  for (int c = 0; c < nc; ++c) {
+  for (int q = 0; q < g; ++q) run += W.gsum[(int64_t)q * B.t_total + t];
+  if (g == kScanGroups - 1) W.tile_count[t] = run + W.gsum[(int64_t)g * B.t_total + t];
+  int c0, c1;
+  tile_groups(S, g, c0, c1);
+  uint32_t* h = W.hist + S.hist_base + (t - S.tile_base);
+#pragma unroll 4
+  for (int c = c0; c < c1; ++c) {
     const uint32_t v = h[(int64_t)c * ts];
     h[(int64_t)c * ts] = run;
     run += v;
   }
-  W.tile_count[t] = run;
 }
 
 // Exclusive scan of n values in[0..n) into out[0..n]; out[n] = total.
@@ -289,7 +345,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_tot
 // cursors, pairs dealt evenly over the threads.
 __global__ __launch_bounds__(kBlock) void k_emit(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_cur[];
-  __shared__ uint32_t s_off[kChunk];
+  __shared__ uint32_t s_off[kChunk + 1];
   __shared__ uint32_t s_wave[kBlock / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
@@ -305,15 +361,17 @@ __global__ __launch_bounds__(kBlock) void k_emit(Batch B, WsPtrs W) {
     const int li = c * kChunk + i;
     if (li < S.n) W.goff[S.gauss_base + li] = base + s_off[i];
   }
-  for (uint32_t m = threadIdx.x; m < total; m += kBlock) {
-    int tile;
-    const int i = chunk_pair(S, W, c, s_off, m, tile);
-    const int gid = S.gauss_base + c * kChunk + i;
-    const unsigned long long key =
-        ((unsigned long long)__float_as_uint(W.rec2[gid].w) << 32) | (unsigned)gid;
+  int cur_i = -1;
+  unsigned long long key = 0;
+  chunk_pairs(S, W, c, s_off, total, [&](int i, int tile) {
+    if (i != cur_i) {
+      const int gid = S.gauss_base + c * kChunk + i;
+      key = ((unsigned long long)__float_as_uint(W.rec2[gid].w) << 32) | (unsigned)gid;
+      cur_i = i;
+    }
     const uint32_t pos = atomicAdd(&s_cur[tile], 1u);
     if ((int64_t)pos < W.cap) W.keys[pos] = key;
-  }
+  });
 }
 
 // Bitonic sorting network on a[0..n) (ascending), all merges in the "flip"
@@ -425,7 +483,9 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
   }
   {
     Scope sc(tm, kStScan, st);
-    k_tile_scan<<<(b.t_total + kBlock - 1) / kBlock, kBlock, 0, st>>>(b, w);
+    const dim3 grid((b.t_total + kBlock - 1) / kBlock, kScanGroups);
+    k_tile_group_sums<<<grid, kBlock, 0, st>>>(b, w);
+    k_tile_group_scan<<<grid, kBlock, 0, st>>>(b, w);
     k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, b.c_total, max_pairs);
   }
   if (b.c_total > 0) {

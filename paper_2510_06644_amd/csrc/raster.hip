@@ -36,29 +36,50 @@ __device__ __forceinline__ int tile_of_block(int t_total) {
   return ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
 }
 
+// A tile holds 16x16 samples: one per pixel normally, or one per block of
+// 2^sub_sx x 2^sub_sy pixels for a downsampled frame (the pixel the mask keeps
+// in that block).  Wave w owns the 8x8 samples of quadrant w.
 struct TileCtx {
   int s;
-  int tile_x0, tile_y0;
-  int px, py;
-  bool inside;
+  int lt;                       // tile index within the session
+  int tile_x0, tile_y0;         // first pixel of the tile
+  int bx0, by0;                 // first pixel of this lane's sample block
+  int px, py;                   // the lane's sample pixel
+  bool inside;                  // the block lies (partly) in the image
+  bool has;                     // a sample pixel exists (mask) in the block
   int pix;
   unsigned wbit;
-  int qx0, qy0;
 };
 
 __device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile) {
   TileCtx c;
   c.s = find_session(B.sess, B.n_sessions, tile, [](const SessionDev& x) { return x.tile_base; });
   const SessionDev& S = B.sess[c.s];
-  const int lt = tile - S.tile_base;
-  c.tile_x0 = (lt % S.tiles_x) * kTile;
-  c.tile_y0 = (lt / S.tiles_x) * kTile;
+  c.lt = tile - S.tile_base;
+  c.tile_x0 = (c.lt % S.tiles_x) << (4 + S.sub_sx);
+  c.tile_y0 = (c.lt / S.tiles_x) << (4 + S.sub_sy);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  c.qx0 = c.tile_x0 + (wave & 1) * 8;
-  c.qy0 = c.tile_y0 + (wave >> 1) * 8;
-  c.px = c.qx0 + (lane & 7);
-  c.py = c.qy0 + (lane >> 3);
-  c.inside = c.px < S.width && c.py < S.height;
+  const int sx = (wave & 1) * 8 + (lane & 7), sy = (wave >> 1) * 8 + (lane >> 3);
+  c.bx0 = c.tile_x0 + (sx << S.sub_sx);
+  c.by0 = c.tile_y0 + (sy << S.sub_sy);
+  c.inside = c.bx0 < S.width && c.by0 < S.height;
+  c.px = c.bx0;
+  c.py = c.by0;
+  c.has = c.inside;
+  if (c.inside && (S.sub_sx | S.sub_sy)) {
+    // the block's sample: its first masked-in pixel in raster order
+    c.has = false;
+    const int x1 = min(S.width, c.bx0 + (1 << S.sub_sx));
+    const int y1 = min(S.height, c.by0 + (1 << S.sub_sy));
+    for (int y = c.by0; y < y1 && !c.has; ++y)
+      for (int x = c.bx0; x < x1; ++x)
+        if (S.pmask[y * S.width + x]) {
+          c.px = x;
+          c.py = y;
+          c.has = true;
+          break;
+        }
+  }
   c.pix = c.py * S.width + c.px;
   c.wbit = 1u << wave;
   return c;
@@ -86,17 +107,20 @@ __device__ __forceinline__ float box_min_quad(float a, float b, float c, float x
 }
 
 // Bit w set when the alpha >= 1/255 ellipse (q <= t) of the Gaussian can
-// reach a pixel centre of the 8x8 quadrant of wave w.  The margin keeps the
-// test conservative against the float32 evaluation of alpha.
-__device__ __forceinline__ unsigned quad_mask(float4 r0, float4 r1, float4 ex, int tx0, int ty0) {
+// reach a pixel centre of the quadrant of wave w (8x8 sample blocks of
+// 2^sx x 2^sy pixels).  The margin keeps the test conservative against the
+// float32 evaluation of alpha.
+__device__ __forceinline__ unsigned quad_mask(float4 r0, float4 r1, float4 ex, int tx0, int ty0,
+                                              int sx, int sy) {
   const float u = r0.x + r0.z, v = r0.y + r0.w;
   const float t = ex.z * (1.f + 1e-3f) + 1e-3f;
+  const float wx = (float)((8 << sx) - 1), wy = (float)((8 << sy) - 1);
   unsigned m = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    const float qx = (float)(tx0 + (w & 1) * 8) + 0.5f - u;
-    const float qy = (float)(ty0 + (w >> 1) * 8) + 0.5f - v;
-    const float q = box_min_quad(r1.x, r1.y, r1.z, qx, qx + 7.f, qy, qy + 7.f);
+    const float qx = (float)(tx0 + ((w & 1) * 8 << sx)) + 0.5f - u;
+    const float qy = (float)(ty0 + ((w >> 1) * 8 << sy)) + 0.5f - v;
+    const float q = box_min_quad(r1.x, r1.y, r1.z, qx, qx + wx, qy, qy + wy);
     m |= (q <= t) ? (1u << w) : 0u;
   }
   return m;
@@ -118,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   const TileCtx c = tile_ctx(B, tile);
   const SessionDev& S = B.sess[c.s];
   const int tid = threadIdx.x;
-  const bool active = c.inside && (S.pmask == nullptr || S.pmask[c.pix] != 0);
+  const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
   const int64_t start = min((int64_t)W.tile_start[tile], W.cap);
   const int64_t end = min((int64_t)W.tile_start[tile + 1], W.cap);
@@ -136,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
       s_r0[tid] = r0;
       s_r1[tid] = r1;
       s_r2[tid] = W.rec2[g];
-      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0);
+      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
     }
     __syncthreads();
     const int cnt = (int)min((int64_t)kBlock, end - b0);
@@ -170,22 +194,31 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   }
   if (!c.inside) return;
   const int64_t hw = (int64_t)S.width * S.height;
-  if (S.color) {
-    S.color[c.pix] = C0;
-    S.color[hw + c.pix] = C1;
-    S.color[2 * hw + c.pix] = C2;
-  }
-  if (S.depth) S.depth[c.pix] = D;
-  if (S.alpha) S.alpha[c.pix] = 1.f - T;
-  if (S.final_T) S.final_T[c.pix] = T;
-  if (S.last_idx) S.last_idx[c.pix] = last;
-  if (S.stats) {
-    // work counts: fragments blended, list entries up to the stop (or the end
-    // of the list), list entries up to the last blended one
-    S.stats[c.pix] = nblend;
-    S.stats[hw + c.pix] = active ? (int)(min(stop + 1, end) - start) : 0;
-    S.stats[2 * hw + c.pix] = last >= 0 ? (int)(last - start + 1) : 0;
-  }
+  // every pixel of the lane's block: the sample gets its result, the others
+  // (masked out) render as background
+  const int x1 = min(S.width, c.bx0 + (1 << S.sub_sx));
+  const int y1 = min(S.height, c.by0 + (1 << S.sub_sy));
+  for (int y = c.by0; y < y1; ++y)
+    for (int x = c.bx0; x < x1; ++x) {
+      const int p = y * S.width + x;
+      const bool me = p == c.pix;
+      if (S.color) {
+        S.color[p] = me ? C0 : 0.f;
+        S.color[hw + p] = me ? C1 : 0.f;
+        S.color[2 * hw + p] = me ? C2 : 0.f;
+      }
+      if (S.depth) S.depth[p] = me ? D : 0.f;
+      if (S.alpha) S.alpha[p] = me ? 1.f - T : 0.f;
+      if (S.final_T) S.final_T[p] = me ? T : 1.f;
+      if (S.last_idx) S.last_idx[p] = me ? last : -1;
+      if (S.stats) {
+        // work counts: fragments blended, list entries up to the stop (or
+        // the end of the list), list entries up to the last blended one
+        S.stats[p] = me ? nblend : 0;
+        S.stats[hw + p] = me && active ? (int)(min(stop + 1, end) - start) : 0;
+        S.stats[2 * hw + p] = me && last >= 0 ? (int)(last - start + 1) : 0;
+      }
+    }
 }
 
 constexpr int kBwdBatch = 128;           // list entries staged per batch
@@ -214,8 +247,8 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   const TileCtx c = tile_ctx(B, tile);
   const SessionDev& S = B.sess[c.s];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ltx = c.tile_x0 / kTile, lty = c.tile_y0 / kTile;
-  const bool active = c.inside && (S.pmask == nullptr || S.pmask[c.pix] != 0);
+  const int ltx = c.lt % S.tiles_x, lty = c.lt / S.tiles_x;
+  const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);
   const int64_t hw = (int64_t)S.width * S.height;
   int last = -1;
   float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gD = 0.f, gA = 0.f;
@@ -251,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
       s_r0[tid] = r0;
       s_r1[tid] = r1;
       s_r2[tid] = W.rec2[g];
-      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0);
+      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
     }
     // zero this batch's partial sums (each wave its own)
     for (int i = lane; i < kBwdBatch * kStride; i += 64) part[i] = 0.f;

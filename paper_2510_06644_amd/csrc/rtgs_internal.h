@@ -18,7 +18,7 @@ constexpr float kTMin = 1e-4f;              // early-termination transmittance
 constexpr double kNearZ = 0.2;
 constexpr double kDilation = 0.3;
 constexpr double kFovClamp = 1.3;
-constexpr int kChunk = 2048;              // Gaussians per binning chunk (8 per thread)
+constexpr int kChunk = 1024;              // Gaussians per binning chunk (4 per thread)
 constexpr int kMaxTilesPerSession = 12288; // LDS tile histogram of one session (48 KB)
 
 // Device copy of one session (built on the host from rtgs_session).
@@ -58,6 +58,8 @@ struct SessionDev {
   int32_t height;
   int32_t tiles_x;
   int32_t tiles_y;
+  int32_t sub_sx;       // log2 of the sample block width (0: one sample per pixel)
+  int32_t sub_sy;       // log2 of the sample block height
   float fx, fy, cx, cy;
   // offsets into the batch-global index spaces
   int32_t gauss_base;   // first global Gaussian index
@@ -83,6 +85,7 @@ struct WsLayout {
   uint64_t chunk_total; // uint32[C + 1]: pairs per chunk
   uint64_t chunk_off;   // uint32[C + 1]: exclusive scan of chunk_total
   uint64_t hist;        // uint32[sum_s C_s T_s]: per (chunk, tile) counts, then offsets
+  uint64_t gsum;        // uint32[16][T]: per (group of chunks, tile) sums
   uint64_t tile_count;  // uint32[T + 1]
   uint64_t tile_start;  // uint32[T + 1]
   uint64_t keys;        // uint64[cap]
@@ -120,6 +123,7 @@ struct WsPtrs {
   uint32_t* chunk_total;
   uint32_t* chunk_off;
   uint32_t* hist;
+  uint32_t* gsum;
   uint32_t* tile_count;
   uint32_t* tile_start;
   unsigned long long* keys;

@@ -39,6 +39,7 @@ RTGS_GRAD_RECOMPUTE_STATE = 8
 RTGS_STATE_IDLE = 0
 RTGS_STATE_EXECUTING = 1
 RTGS_MAX_SESSIONS = 64
+RTGS_SAMPLE_SHIFT = 8
 
 EXPORTS = (
     "rtgs_last_error", "rtgs_create", "rtgs_destroy", "rtgs_workspace_size",
@@ -66,7 +67,7 @@ class CCamera(ctypes.Structure):
 
 
 class CSession(ctypes.Structure):
-    _fields_ = [("g", CGaussians), ("cam", CCamera), ("pixel_mask", vp),
+    _fields_ = [("g", CGaussians), ("cam", CCamera), ("pixel_mask", vp), ("sample_log2", i32),
                 ("color", vp), ("depth", vp), ("alpha", vp), ("final_T", vp), ("last_idx", vp),
                 ("visible", vp), ("stats", vp), ("dL_dcolor", vp), ("dL_ddepth", vp), ("dL_dalpha", vp),
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
@@ -112,8 +113,8 @@ def lib():
             L.downsample_mask.argtypes = [vp, i32, i32, i32, vp, vp, vp]
             L.rtgs_downsample_log2_ratio.argtypes = [i32, i32, i32, i32]
             L.rtgs_query.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
-            L.rtgs_debug_stage.argtypes = [vp, vp, vp, i32, i64, vp, u64, vp, vp, vp, vp, i64,
-                                           vp]
+            L.rtgs_debug_stage.argtypes = [vp, vp, vp, vp, i32, i64, vp, u64, vp, vp, vp, vp,
+                                           i64, vp]
             L.rtgs_selftest_wave_sum.argtypes = [vp, vp, i32, vp]
             L.rtgs_profile_enable.argtypes = [vp, i32]
             L.rtgs_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -265,6 +266,7 @@ def make_sessions(items):
         s = arr[i]
         s.g = _gauss(*sc, it.get("gauss_mask"))
         s.cam = _cam(it["cam"], it["viewmat"])
+        s.sample_log2 = int(it.get("sample_log2", 0))
         for name in ("pixel_mask", "color", "depth", "alpha", "final_T", "last_idx", "visible",
                      "stats",
                      "dL_dcolor", "dL_ddepth", "dL_dalpha", "g_means", "g_log_scales", "g_quats",
@@ -324,12 +326,13 @@ def rtgs_query(handle, blocking=True):
 
 
 def rtgs_debug_stage(ns, widths, heights, pair_capacity, ws, stage=None, rect=None,
-                     ranges=None, ids=None, stream=None):
+                     ranges=None, ids=None, stream=None, sample_log2=None):
     k = len(ns)
     a = (i32 * k)(*ns)
     w = (i32 * k)(*widths)
     h = (i32 * k)(*heights)
-    _check(lib().rtgs_debug_stage(a, w, h, k, int(pair_capacity), _p(ws),
+    j = None if sample_log2 is None else (i32 * k)(*sample_log2)
+    _check(lib().rtgs_debug_stage(a, w, h, j, k, int(pair_capacity), _p(ws),
                                   ws.numel() * ws.element_size(), _p(stage), _p(rect),
                                   _p(ranges), _p(ids), 0 if ids is None else ids.numel(),
                                   _stream(stream)))
@@ -403,7 +406,7 @@ class Renderer:
 
     # ------------------------------------------------------------------ managed calls
     def forward(self, scene, viewmat, cam: Cam, gauss_mask=None, pixel_mask=None,
-                save_state=True, stream=None):
+                save_state=True, stream=None, sample_log2=0):
         """Render one frame; returns a FwdState (outputs + the workspace the
         matching backward needs).  Each forward gets its own workspace from
         torch's caching allocator, so several forwards may await backward."""
@@ -415,7 +418,7 @@ class Renderer:
         while True:
             need = rtgs_workspace_size(n, w, h, cap)
             ws = torch.empty(need, dtype=torch.uint8, device=dev)
-            out = FwdState(ws=ws, cap=cap, cam=cam, n=n,
+            out = FwdState(ws=ws, cap=cap, cam=cam, n=n, sample_log2=sample_log2,
                            color=torch.empty(3, h, w, device=dev),
                            depth=torch.empty(h, w, device=dev),
                            alpha=torch.empty(h, w, device=dev),
@@ -426,7 +429,8 @@ class Renderer:
             render_fwd(self.handle, *scene, viewmat, cam, ws, cap, out.color, out.depth,
                        out.alpha, out.final_T, out.last_idx, out.visible, gauss_mask=gauss_mask,
                        pixel_mask=pixel_mask,
-                       flags=RTGS_FWD_SAVE_STATE if save_state else 0, stream=stream)
+                       flags=(RTGS_FWD_SAVE_STATE if save_state else 0)
+                       | (int(sample_log2) << RTGS_SAMPLE_SHIFT), stream=stream)
             self.cap = max(self.cap, cap)
             if self.check != "every":
                 return out
@@ -446,6 +450,7 @@ class Renderer:
         flags |= RTGS_GRAD_COV3D if cov3d else 0
         if st.final_T is None:
             flags |= RTGS_GRAD_RECOMPUTE_STATE
+        flags |= int(st.sample_log2) << RTGS_SAMPLE_SHIFT
         g = {}
         if map_grads:
             g["means"] = torch.empty(n, 3, device=dev)
@@ -479,18 +484,22 @@ class FwdState:
     final_T: torch.Tensor | None
     last_idx: torch.Tensor | None
     visible: torch.Tensor
+    sample_log2: int = 0
     pairs: int = -1
 
     def stage(self):
         """Forward intermediates for tests: dict of numpy arrays."""
         n, w, h = self.n, self.cam.width, self.cam.height
         dev = self.ws.device
-        t = _tiles(w, h)
+        j = self.sample_log2
+        tw, th = 16 << ((j + 1) // 2), 16 << (j // 2)
+        t = ((w + tw - 1) // tw) * ((h + th - 1) // th)
         stage = torch.empty(max(n, 1), 12, device=dev)
         rect = torch.empty(max(n, 1), 4, dtype=torch.int32, device=dev)
         ranges = torch.empty(t, 2, dtype=torch.int32, device=dev)
         ids = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
-        rtgs_debug_stage([n], [w], [h], self.cap, self.ws, stage, rect, ranges, ids)
+        rtgs_debug_stage([n], [w], [h], self.cap, self.ws, stage, rect, ranges, ids,
+                         sample_log2=[j])
         torch.cuda.synchronize()
         rng = ranges.cpu().numpy()
         total = int(rng[:, 1].max()) if t else 0

@@ -498,6 +498,7 @@ class GpuExecutor:
             o = S["out"]
             items.append(dict(scene=tuple(p.detach() for p in S["params"]),
                               viewmat=S["viewmat"], cam=S["cam"], pixel_mask=f.mask,
+                              sample_log2=f.log2_ratio if f.mask is not None else 0,
                               color=o["color"], depth=o["depth"], alpha=o["alpha"],
                               final_T=o["final_T"], last_idx=o["last_idx"]))
             cap += self._cap(S["spec"])
