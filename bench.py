@@ -38,8 +38,39 @@ FLOP_BWD_PER_ENTRY = 18
 FLOP_BWD_PER_BLEND = 65
 FLOP_FWD_PER_ENTRY = 18
 FLOP_FWD_PER_BLEND = 12
-PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (published)
+# Vector FP32 peak from unit counts and clock, without packed FP32 (the
+# kernels are built with packed FP32 disabled): 256 CUs x 4 SIMDs x 16 lanes
+# x 2 flop (FMA) x 2.4 GHz.  The published 157.3 TFLOP/s counts packed FMAs.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_FP32_PUBLISHED = 157.3
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raster_bwd_mapping_1200x680_300k_traffic.md")
+KERNEL_SOURCES = ("paper_2510_06644_amd/csrc/raster.hip", "paper_2510_06644_amd/csrc/rtgs_internal.h")
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per raster_bwd launch from the committed PMC summary, if it
+    was taken on the current kernel sources (else None)."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    start = text.find("```json")
+    if start < 0:
+        return None
+    rec = json.loads(text[start + 7:text.index("```", start + 7)])
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec
 
 
 def log(*a):
@@ -246,6 +277,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a 512 MiB device copy (scales PMC byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the serving trace (0 disables the serving runs)")
     args = ap.parse_args()
@@ -285,10 +318,13 @@ def main():
     bwd_ms = prof["raster_bwd"][0] / prof["raster_bwd"][1]
     flops = FLOP_BWD_PER_ENTRY * cnt["visited_to_last"] + FLOP_BWD_PER_BLEND * cnt["blended"]
     achieved = flops / (bwd_ms * 1e-3) / 1e12
+    trec = measured_traffic()
     roof = {"kernel": "raster_bwd", "bound": "alu", "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None, "avg_ms": bwd_ms, "launches": prof["raster_bwd"][1],
-            "flops_per_launch": flops}
+            "traffic": None if trec is None else trec["bytes_per_launch"],
+            "frac_vs_published_157": achieved / PEAK_FP32_PUBLISHED,
+            "avg_ms": bwd_ms, "launches": prof["raster_bwd"][1], "flops_per_launch": flops,
+            "kernel_hash": kernel_hash()}
     log("stage breakdown")
     _, _, stages = timed_loop(R, params, view, rc, opt, tc, td, 10,
                               profile_stages=list(rtgs.STAGES))
@@ -339,7 +375,8 @@ def main():
         "roofline": roof,
         "raster_fwd_roofline": {"bound": "alu", "avg_ms": fwd_ms,
                                 "achieved": fwd_flops / (fwd_ms * 1e-3) / 1e12,
-                                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"},
+                                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                "frac": fwd_flops / (fwd_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
         "stages_ms": stages_ms,
         "work": cnt,
         "host_wall_ms_per_step": 1000.0 * wall_ms,
@@ -348,6 +385,12 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.calib_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
