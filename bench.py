@@ -102,10 +102,8 @@ def render_target(R, target_scene, view, rc, seed):
 
 
 def make_optimizer(params):
-    import torch
-    lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)
-    return torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in zip(params, lrs)],
-                            eps=1e-15, fused=True)
+    from paper_2510_06644_amd import optim
+    return optim.MapAdam(params, eps=1e-15)
 
 
 def l1_grads(color, depth, tc, td, pixel_mask=None):
@@ -131,9 +129,8 @@ def mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=None, pixel_mask=N
     gc, gd = l1_grads(st.color, st.depth, tc, td, pixel_mask)
     g = R.backward(scene, view, rc, st, gc, gd, pose=False, map_grads=True, cov3d=cov3d,
                    gauss_mask=gauss_mask, pixel_mask=pixel_mask)
-    for p, k in zip(params, ("means", "log_scales", "quats", "opacity_logits", "colors")):
-        p.grad = g[k]
-    opt.step()
+    opt.step(R.handle, [g[k] for k in ("means", "log_scales", "quats", "opacity_logits",
+                                        "colors")])
     return st, g
 
 

@@ -224,6 +224,36 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* sessions,
                            int64_t pair_capacity, int32_t grad_flags,
                            void* stream);
 
+/* Parameter update of the mapping stage: the Gaussian gradients of Step 5
+ * update the 3D Gaussian parameters (Sec. 3.1).  The paper names no
+ * optimiser; this is Adam without weight decay.  For each group (a HOST
+ * array of n_groups entries; every pointer in an entry is a device float
+ * array of n elements, updated in place):
+ *   exp_avg    <- beta1 exp_avg + (1 - beta1) grad
+ *   exp_avg_sq <- beta2 exp_avg_sq + (1 - beta2) grad^2
+ *   param      <- param - lr / (1 - beta1^step) * exp_avg
+ *                        / (sqrt(exp_avg_sq) / sqrt(1 - beta2^step) + eps)
+ * where step (>= 1) is the group's update count including this one; the
+ * arithmetic is float32, with 1 - beta and the two bias factors formed in
+ * double on the host.  Groups
+ * may be tensors of different sessions; all of them are updated by one
+ * kernel launch per 64 groups.  Groups must not overlap.  Errors:
+ * INVALID_ARG (null array with n > 0, n < 0, step < 1, beta outside [0, 1),
+ * eps < 0 or not finite, lr not finite), HIP. */
+typedef struct rtgs_adam_group {
+  float* param;
+  const float* grad;
+  float* exp_avg;
+  float* exp_avg_sq;
+  int64_t n;
+  float lr;
+  int32_t step;
+} rtgs_adam_group;
+
+int32_t adam_step(rtgs_handle_t h, const rtgs_adam_group* groups,
+                  int32_t n_groups, double beta1, double beta2, double eps,
+                  void* stream);
+
 /* Adaptive Gaussian pruning, the mask step (Sec. 4.1, Eq. 7):
  * score_k = ||dL/dmu_k||_2 + lambda * ||dL/dSigma_k||_F (Frobenius over the
  * nine entries of the symmetric gradient); among the V Gaussians with
@@ -289,7 +319,7 @@ int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width,
 
 /* Stage profiler (HIP events on the stream each kernel is launched on).
  * Stages: 0 init, 1 preprocess, 2 scan, 3 emit, 4 sort, 5 raster_fwd,
- * 6 (unused), 7 raster_bwd, 8 preprocess_bwd, 9 pose_reduce, 10 bin_count,
+ * 6 adam, 7 raster_bwd, 8 preprocess_bwd, 9 pose_reduce, 10 bin_count,
  * 11 merge.  After
  * rtgs_profile_enable(h, mask) every launch of a stage whose bit is set is
  * bracketed by two events; rtgs_profile_read waits for them and returns per
@@ -299,8 +329,10 @@ int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width,
 int32_t rtgs_profile_enable(rtgs_handle_t h, int32_t stage_mask);
 int32_t rtgs_profile_read(rtgs_handle_t h, double* total_ms, int64_t* launches);
 
-/* Test hook for the wavefront reduction used by the backward merge: out[w] =
- * sum of in[64 w .. 64 w + 63] for each wave w of n_waves. */
+/* Test hook for the wavefront reduce-scatter of the backward merge (ten
+ * values per lane, as in the full-gradient backward): for each wave w of
+ * n_waves and value i < 10, out[10 w + i] = sum over lanes l < 64 of
+ * in[(10 w + i) * 64 + l].  in and out are device arrays. */
 int32_t rtgs_selftest_wave_sum(const float* in, float* out, int32_t n_waves,
                                void* stream);
 

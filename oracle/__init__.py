@@ -19,6 +19,8 @@ Everything is plain PyTorch on the CPU in float64:
 * ``selection``  - the importance score and mask selection (Eq. 7, Sec. 4.1)
                    and the downsampling schedule and pixel choice (Sec. 4.2).
 * ``loss``       - the L1 colour + depth loss (Eq. 6, reading in DESIGN).
+* ``optim``      - the map update (Adam, a reading: the paper names no
+                   optimiser).
 
 Parity status: every function here is pinned by tests under ``tests/`` against
 closed forms, invariants, finite differences or brute force (see each module).
@@ -31,3 +33,4 @@ from .render import render, render_with_grads, RenderOut, Grads  # noqa: F401
 from .binning import tile_lists  # noqa: F401
 from .selection import importance_score, prune_select, downsample_log2_ratio, downsample_select  # noqa: F401
 from .loss import l1_loss_grads  # noqa: F401
+from .optim import adam_step  # noqa: F401

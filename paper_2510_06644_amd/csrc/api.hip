@@ -130,10 +130,7 @@ WsLayout make_layout(const Counts& c, int64_t cap) {
   const uint64_t n = (uint64_t)c.n_total, t = (uint64_t)c.t_total;
   L.table = take(sizeof(SessionDev) * RTGS_MAX_SESSIONS);
   L.counters = take(64);
-  L.rec0 = take(16 * n);
-  L.rec1 = take(16 * n);
-  L.rec2 = take(16 * n);
-  L.ext = take(16 * n);
+  L.rec = take(64 * n);
   L.rect = take(16 * n);
   L.cnt = take(4 * n);
   L.goff = take(4 * n);
@@ -163,10 +160,7 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   WsPtrs w{};
   w.table = reinterpret_cast<SessionDev*>(base + L.table);
   w.counters = reinterpret_cast<long long*>(base + L.counters);
-  w.rec0 = reinterpret_cast<float4*>(base + L.rec0);
-  w.rec1 = reinterpret_cast<float4*>(base + L.rec1);
-  w.rec2 = reinterpret_cast<float4*>(base + L.rec2);
-  w.ext = reinterpret_cast<float4*>(base + L.ext);
+  w.rec = reinterpret_cast<GaussRec*>(base + L.rec);
   w.rect = reinterpret_cast<int4*>(base + L.rect);
   w.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
   w.goff = reinterpret_cast<uint32_t*>(base + L.goff);
@@ -586,6 +580,62 @@ int32_t downsample_mask(const float* final_T, int32_t width, int32_t height, int
   hipError_t e = launch_downsample(final_T, width, height, log2_ratio, mask_out, n_active_dev,
                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "downsample_mask launch");
+  return RTGS_OK;
+}
+
+int32_t adam_step(rtgs_handle_t h, const rtgs_adam_group* groups, int32_t n_groups, double beta1,
+                  double beta2, double eps, void* stream) {
+  if (!h) return fail(RTGS_ERR_INVALID_ARG, "null handle");
+  if (n_groups < 0 || (n_groups > 0 && !groups))
+    return fail(RTGS_ERR_INVALID_ARG, "bad group list (n_groups = %d)", n_groups);
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
+    return fail(RTGS_ERR_INVALID_ARG, "betas (%g, %g) outside [0, 1)", beta1, beta2);
+  if (!(eps >= 0.0) || !std::isfinite(eps))
+    return fail(RTGS_ERR_INVALID_ARG, "eps %g must be finite and >= 0", eps);
+  for (int i = 0; i < n_groups; ++i) {
+    const rtgs_adam_group& g = groups[i];
+    if (g.n < 0) return fail(RTGS_ERR_INVALID_ARG, "group %d: n = %lld < 0", i, (long long)g.n);
+    if (g.n > 0 && (!g.param || !g.grad || !g.exp_avg || !g.exp_avg_sq))
+      return fail(RTGS_ERR_INVALID_ARG, "group %d: null array", i);
+    if (g.step < 1) return fail(RTGS_ERR_INVALID_ARG, "group %d: step %d < 1", i, g.step);
+    if (!std::isfinite(g.lr)) return fail(RTGS_ERR_INVALID_ARG, "group %d: lr not finite", i);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
+  const int64_t per_block = 256 * kAdamPerThread;
+  for (int first = 0; first < n_groups; first += kAdamMaxGroups) {
+    AdamArgs a{};
+    // 1 - beta is formed in double: float32(beta2 = 0.999) alone would
+    // carry a 1e-5 relative error into 1 - beta2
+    a.beta1 = (float)beta1;
+    a.beta2 = (float)beta2;
+    a.omb1 = (float)(1.0 - beta1);
+    a.omb2 = (float)(1.0 - beta2);
+    a.eps = (float)eps;
+    int64_t blocks = 0;
+    for (int i = first; i < n_groups && i < first + kAdamMaxGroups; ++i) {
+      const rtgs_adam_group& g = groups[i];
+      if (g.n == 0) continue;
+      AdamGroupDev& d = a.grp[a.n_groups++];
+      d.p = g.param;
+      d.g = g.grad;
+      d.m = g.exp_avg;
+      d.v = g.exp_avg_sq;
+      d.n = g.n;
+      const double bc1 = 1.0 - std::pow(beta1, (double)g.step);
+      const double bc2 = 1.0 - std::pow(beta2, (double)g.step);
+      d.step_size = (float)((double)g.lr / bc1);
+      d.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
+      auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+      d.vec = al(g.param) && al(g.grad) && al(g.exp_avg) && al(g.exp_avg_sq);
+      d.block0 = (int32_t)blocks;
+      blocks += (g.n + per_block - 1) / per_block;
+      if (blocks > (int64_t)INT32_MAX) return fail(RTGS_ERR_INVALID_ARG, "too many elements");
+    }
+    a.n_blocks = (int32_t)blocks;
+    hipError_t e = launch_adam(a, st, tm);
+    if (e != hipSuccess) return hip_fail(e, "adam_step launch");
+  }
   return RTGS_OK;
 }
 

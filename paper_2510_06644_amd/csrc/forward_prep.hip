@@ -121,15 +121,17 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
     split(P.u, uh, ul);
     split(P.v, vh, vl);
     const float zf = (float)P.z;
-    W.rec0[gid] = make_float4(uh, vh, ul, vl);
-    W.rec1[gid] = make_float4((float)(P.syy * inv), (float)(-P.sxy * inv), (float)(P.sxx * inv),
-                              (float)o);
-    W.rec2[gid] = make_float4(S.colors[3 * li + 0], S.colors[3 * li + 1], S.colors[3 * li + 2], zf);
     // bounding box of the alpha = 1/255 ellipse: d^T M d <= 2 ln(255 o)
     const double t = 2.0 * log(255.0 * o);
     const float ex = (float)sqrt(t * P.sxx);
     const float ey = (float)sqrt(t * P.syy);
-    W.ext[gid] = make_float4(ex, ey, (float)t, 0.f);
+    GaussRec r;
+    r.pos = make_float4(uh, vh, ul, vl);
+    r.conic = make_float4((float)(P.syy * inv), (float)(-P.sxy * inv), (float)(P.sxx * inv),
+                          (float)o);
+    r.col = make_float4(S.colors[3 * li + 0], S.colors[3 * li + 1], S.colors[3 * li + 2], zf);
+    r.ext = make_float4(ex, ey, (float)t, 0.f);
+    W.rec[gid] = r;
     // padded pixel range in float32, fixed operation order (see the replay)
     const float lox = floorf((uh - ex) - 1.5f), hix = ceilf((uh + ex) + 0.5f);
     const float loy = floorf((vh - ey) - 1.5f), hiy = ceilf((vh + ey) + 0.5f);
@@ -140,10 +142,12 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
       rect = make_int4(i0 >> shx, j0 >> shy, i1 >> shx, j1 >> shy);
     }
   } else {
-    W.rec0[gid] = make_float4(0.f, 0.f, 0.f, 0.f);
-    W.rec1[gid] = make_float4(0.f, 0.f, 0.f, 0.f);
-    W.rec2[gid] = make_float4(0.f, 0.f, 0.f, (float)P.z);
-    W.ext[gid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    GaussRec r;
+    r.pos = make_float4(0.f, 0.f, 0.f, 0.f);
+    r.conic = make_float4(0.f, 0.f, 0.f, 0.f);
+    r.col = make_float4(0.f, 0.f, 0.f, (float)P.z);
+    r.ext = make_float4(0.f, 0.f, 0.f, 0.f);
+    W.rec[gid] = r;
   }
   W.rect[gid] = rect;
   const bool vis = rect.z >= rect.x;
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(Batch B, WsPtrs W) {
   chunk_pairs(S, W, c, s_off, total, [&](int i, int tile) {
     if (i != cur_i) {
       const int gid = S.gauss_base + c * kChunk + i;
-      key = ((unsigned long long)__float_as_uint(W.rec2[gid].w) << 32) | (unsigned)gid;
+      key = ((unsigned long long)__float_as_uint(W.rec[gid].col.w) << 32) | (unsigned)gid;
       cur_i = i;
     }
     const uint32_t pos = atomicAdd(&s_cur[tile], 1u);
@@ -437,7 +441,8 @@ __global__ void k_debug_stage(Batch B, WsPtrs W, float* stage, int* rect, int* r
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < B.n_total) {
     if (stage) {
-      const float4 r0 = W.rec0[i], r1 = W.rec1[i], r2 = W.rec2[i], e = W.ext[i];
+      const GaussRec R = W.rec[i];
+      const float4 r0 = R.pos, r1 = R.conic, r2 = R.col, e = R.ext;
       float* o = stage + 12 * (int64_t)i;
       o[0] = r0.x; o[1] = r0.y; o[2] = r1.x; o[3] = r1.y; o[4] = r1.z; o[5] = r1.w;
       o[6] = r2.w; o[7] = e.x; o[8] = e.y; o[9] = r2.x; o[10] = r2.y; o[11] = r2.z;
@@ -458,10 +463,20 @@ __global__ void k_debug_stage(Batch B, WsPtrs W, float* stage, int* rect, int* r
 }
 
 __global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
+  constexpr int NV = kWaveSumValues;
   const int w = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (w >= n_waves) return;     // whole waves exit together
-  const float v = wave_sum_to_lane63(in[64 * w + (threadIdx.x & 63)]);
-  if ((threadIdx.x & 63) == 63) out[w] = v;
+  const int lane = threadIdx.x & 63;
+  float v[NV], x[3];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = in[((int64_t)w * NV + i) * 64 + lane];
+  wave_reduce_scatter<NV>(v, x);
+  if ((lane & 15) == 15) {
+    const int row = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if ((row & 1) + 2 * j < NV / 2) out[(int64_t)w * NV + wave_scatter_index(NV, row, j)] = x[j];
+  }
 }
 
 }  // namespace

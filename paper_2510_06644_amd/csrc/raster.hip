@@ -16,9 +16,9 @@
 // Backward: walks the list from the block's largest saved position down,
 // recovering T before each blended fragment as T / (1 - alpha) (Eq. 5 read
 // as the reverse recurrence) and the normalised suffix colour/depth; the
-// per-fragment 2D gradients of one list entry are summed over the wave with
-// DPP row shifts and broadcasts, the four waves' sums are added in LDS in a
-// fixed order, and the tile's total for that Gaussian is stored in the
+// per-fragment 2D gradients of one list entry are summed over the wave by a
+// reduce-scatter (lane swaps across halves and rows, then DPP row sums), the
+// four waves' sums are added in LDS in a fixed order, and the tile's total for that Gaussian is stored in the
 // pair's own slot: the pixel -> tile merge of the paper's Gradient Merging
 // Unit (Sec. 5.3) done with cross-lane operations.  The tile -> Gaussian
 // merge (its Stage Buffer) is a segmented sum over the Gaussian's slots in
@@ -155,12 +155,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     if (__syncthreads_and(done)) break;
     const int64_t e = b0 + tid;
     if (e < end) {
-      const uint32_t g = W.ids[e];
-      const float4 r0 = W.rec0[g], r1 = W.rec1[g];
-      s_r0[tid] = r0;
-      s_r1[tid] = r1;
-      s_r2[tid] = W.rec2[g];
-      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
+      const GaussRec r = W.rec[W.ids[e]];
+      s_r0[tid] = r.pos;
+      s_r1[tid] = r.conic;
+      s_r2[tid] = r.col;
+      s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
     }
     __syncthreads();
     const int cnt = (int)min((int64_t)kBlock, end - b0);
@@ -232,8 +231,8 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 
 // NV = 10 (all parameters: u, v, a, b, c, o, r, g, b, z) or 6 (pose only:
 // u, v, a, b, c, z).  Each (tile, Gaussian) pair gets the sum of its pixels'
-// gradients in slot pair_slot(); the sum is formed in a fixed order (DPP
-// tree inside each wave, then the four waves in order), so the result is
+// gradients in slot pair_slot(); the sum is formed in a fixed order (lane
+// swaps and DPP row sums inside each wave, then the four waves in order), so the result is
 // bitwise reproducible and no float atomics are used.
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
@@ -279,12 +278,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
     const int cnt = (int)(bend - b0);
     __syncthreads();
     if (tid < cnt) {
-      const uint32_t g = W.ids[b0 + tid];
-      const float4 r0 = W.rec0[g], r1 = W.rec1[g];
-      s_r0[tid] = r0;
-      s_r1[tid] = r1;
-      s_r2[tid] = W.rec2[g];
-      s_m[tid] = quad_mask(r0, r1, W.ext[g], c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
+      const GaussRec r = W.rec[W.ids[b0 + tid]];
+      s_r0[tid] = r.pos;
+      s_r1[tid] = r.conic;
+      s_r2[tid] = r.col;
+      s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
     }
     // zero this batch's partial sums (each wave its own)
     for (int i = lane; i < kBwdBatch * kStride; i += 64) part[i] = 0.f;
@@ -337,11 +335,14 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
           }
         }
         if (__ballot(contrib)) {
+          float x[3];
+          wave_reduce_scatter<NV>(v, x);
+          if ((lane & 15) == 15) {
+            const int row = lane >> 4;
 #pragma unroll
-          for (int i = 0; i < NV; ++i) v[i] = wave_sum_to_lane63(v[i]);
-          if (lane == 63) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) part[k * kStride + i] = v[i];
+            for (int j = 0; j < 3; ++j)
+              if ((row & 1) + 2 * j < NV / 2)
+                part[k * kStride + wave_scatter_index(NV, row, j)] = x[j];
           }
         }
       }

@@ -73,10 +73,7 @@ struct SessionDev {
 struct WsLayout {
   uint64_t table;       // SessionDev[RTGS_MAX_SESSIONS]
   uint64_t counters;    // int64[8]: 0 pairs of this call
-  uint64_t rec0;        // float4[N]: u_hi, v_hi, u_lo, v_lo
-  uint64_t rec1;        // float4[N]: a, b, c, opacity
-  uint64_t rec2;        // float4[N]: r, g, b, z
-  uint64_t ext;         // float4[N]: e_x, e_y, -, -
+  uint64_t rec;         // GaussRec[N]: the 64-byte raster record of each Gaussian
   uint64_t rect;        // int4[N]: tile rectangle
   uint64_t cnt;         // uint32[N]: tiles touched
   uint64_t goff;        // uint32[N]: first slot of the Gaussian's pairs, Gaussian-major
@@ -107,14 +104,21 @@ struct Counts {
 
 WsLayout make_layout(const Counts& c, int64_t cap);
 
+// What the raster kernels read of one Gaussian, packed into one 64-byte
+// line so that staging a list entry touches a single cache line.
+struct alignas(64) GaussRec {
+  float4 pos;     // u_hi, v_hi, u_lo, v_lo (centre as a float32 pair)
+  float4 conic;   // a, b, c (inverse 2D covariance), opacity
+  float4 col;     // r, g, b, depth z
+  float4 ext;     // e_x, e_y (half-widths of the alpha = 1/255 box), t = 2 ln(255 o), 0
+};
+static_assert(sizeof(GaussRec) == 64, "one line per record");
+
 // Pointers derived from a workspace.
 struct WsPtrs {
   SessionDev* table;
   long long* counters;
-  float4* rec0;
-  float4* rec1;
-  float4* rec2;
-  float4* ext;
+  GaussRec* rec;
   int4* rect;
   uint32_t* cnt;
   uint32_t* goff;
@@ -149,7 +153,7 @@ struct Batch {
 
 // Stages that the handle's profiler can bracket with HIP events.
 enum Stage {
-  kStInit = 0, kStPreprocess, kStScan, kStEmit, kStSort, kStRasterFwd, kStZero, kStRasterBwd,
+  kStInit = 0, kStPreprocess, kStScan, kStEmit, kStSort, kStRasterFwd, kStAdam, kStRasterBwd,
   kStPreprocessBwd, kStPoseReduce, kStBinCount, kStMerge, kStCount
 };
 
@@ -189,6 +193,29 @@ hipError_t launch_downsample(const float* final_T, int w, int h, int j, uint8_t*
 hipError_t launch_debug_stage(const Batch& b, const WsPtrs& w, float* stage, int* rect,
                               int* ranges, int* ids, int64_t ids_cap, hipStream_t st);
 hipError_t launch_wave_sum_test(const float* in, float* out, int n_waves, hipStream_t st);
+constexpr int kWaveSumValues = 10;    // values per lane in the reduction self-test
+
+// One Adam update over up to kAdamMaxGroups parameter tensors in one launch.
+constexpr int kAdamMaxGroups = 64;
+struct AdamGroupDev {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  float step_size;      // lr / (1 - beta1^t)
+  float inv_sqrt_bc2;   // 1 / sqrt(1 - beta2^t)
+  int32_t vec;          // all four arrays 16-byte aligned
+  int32_t block0;       // first block of the group
+};
+struct AdamArgs {
+  AdamGroupDev grp[kAdamMaxGroups];
+  int32_t n_groups;
+  int32_t n_blocks;
+  float beta1, beta2, omb1, omb2, eps;   // omb = 1 - beta, rounded once from double
+};
+hipError_t launch_adam(const AdamArgs& a, hipStream_t st, StageTimer* tm);
+constexpr int kAdamPerThread = 4;
 
 constexpr int kPruneScratchWords = 4096;
 
@@ -220,24 +247,64 @@ __device__ __forceinline__ float dpp_f(float v) {
       0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, BOUND_ZERO));
 }
 
-// Sum over the 64 lanes of a wavefront; the total lands in lane 63 (other
-// lanes hold partial sums).  Inclusive row scans by shifted adds within each
-// 16-lane row (out-of-row sources read 0), then the row totals are carried
-// across rows by the two broadcasts (lane 15 of each row to the next row,
-// lane 31 to rows 2 and 3; rows without a source read 0).  Each step is one
-// v_add_f32 with a DPP source operand.
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+// Sum of a 16-lane row, inclusive scan by shifted adds (out-of-row sources
+// read 0): lane 15 of each row ends with the row total.
+__device__ __forceinline__ float row_sum_to_lane15(float v) {
   v += dpp_f<kDppRowShr1, 0xf, true>(v);
   v += dpp_f<kDppRowShr2, 0xf, true>(v);
   v += dpp_f<kDppRowShr4, 0xf, true>(v);
   v += dpp_f<kDppRowShr8, 0xf, true>(v);
-  v += dpp_f<kDppRowBcast15, 0xf, true>(v);
-  v += dpp_f<kDppRowBcast31, 0xf, true>(v);
   return v;
 }
 
-__device__ __forceinline__ float read_lane63(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+// a + b for a pair of registers after v_permlane32_swap: lanes 0-31 get
+// a(l) + a(l + 32), lanes 32-63 get b(l - 32) + b(l).
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  // (the two results are copied out as integers first: a bit cast applied
+  // to an element of the returned pair reads the first element for both)
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  const unsigned x = r[0], y = r[1];
+  return __uint_as_float(x) + __uint_as_float(y);
+}
+
+// The same with v_permlane16_swap between rows 2i and 2i + 1 (16 lanes each):
+// row 2i gets a summed over both rows, row 2i + 1 gets b summed over both.
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  const unsigned x = r[0], y = r[1];
+  return __uint_as_float(x) + __uint_as_float(y);
+}
+
+// Wavefront reduce-scatter of NV (even, <= 12) per-lane values.  Two
+// lane-swap steps each halve the number of values a lane carries while
+// adding pairs of lanes; the (at most 3) values left are then summed along
+// each 16-lane row.  Lane 16 r + 15 (row r) ends with, in x[s], the
+// wavefront total of value
+//   wave_scatter_index(NV, r, s) = (r >> 1) * NV / 2 + (r & 1) + 2 s
+// for every s with (r & 1) + 2 s < NV / 2.  About 3 NV instructions
+// instead of the 6 NV of a full tree per value.
+template <int NV>
+__device__ __forceinline__ void wave_reduce_scatter(const float (&v)[NV], float (&x)[3]) {
+  constexpr int H = NV / 2;
+  static_assert(NV % 2 == 0 && H <= 6, "even value count up to 12");
+  float w[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) w[i] = swap32_add(v[i], v[i + H]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (2 * j < H) {
+      x[j] = swap16_add(w[2 * j], 2 * j + 1 < H ? w[2 * j + 1] : 0.f);
+      x[j] = row_sum_to_lane15(x[j]);
+    } else {
+      x[j] = 0.f;
+    }
+  }
+}
+
+__device__ __forceinline__ int wave_scatter_index(int nv, int row, int s) {
+  return (row >> 1) * (nv / 2) + (row & 1) + 2 * s;
 }
 
 // Raster-side alpha of one (pixel, Gaussian) pair: the same instructions in

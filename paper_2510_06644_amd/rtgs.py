@@ -30,7 +30,7 @@ RTGS_ERR_WORKSPACE = -4
 RTGS_FWD_SAVE_STATE = 1
 RTGS_FWD_STATS = 2
 RTGS_PROFILE_STAGES = 16
-STAGES = ("init", "preprocess", "scan", "emit", "sort", "raster_fwd", "zero", "raster_bwd",
+STAGES = ("init", "preprocess", "scan", "emit", "sort", "raster_fwd", "adam", "raster_bwd",
           "preprocess_bwd", "pose_reduce", "bin_count", "merge")
 RTGS_GRAD_POSE = 1
 RTGS_GRAD_MAP = 2
@@ -46,7 +46,7 @@ EXPORTS = (
     "rtgs_workspace_size_batched", "render_fwd", "render_bwd", "render_fwd_batched",
     "render_bwd_batched", "prune_by_grad", "downsample_mask", "rtgs_downsample_log2_ratio",
     "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum", "rtgs_profile_enable",
-    "rtgs_profile_read",
+    "rtgs_profile_read", "adam_step",
 )
 
 vp = ctypes.c_void_p
@@ -73,6 +73,11 @@ class CSession(ctypes.Structure):
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
                 ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_viewmat", vp),
                 ("g_cov3d", vp)]
+
+
+class CAdamGroup(ctypes.Structure):
+    _fields_ = [("param", vp), ("grad", vp), ("exp_avg", vp), ("exp_avg_sq", vp), ("n", i64),
+                ("lr", f32), ("step", i32)]
 
 
 _lib = None
@@ -111,6 +116,8 @@ def lib():
                                              i32, vp]
             L.prune_by_grad.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp]
             L.downsample_mask.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+            L.adam_step.argtypes = [vp, ctypes.POINTER(CAdamGroup), i32, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, vp]
             L.rtgs_downsample_log2_ratio.argtypes = [i32, i32, i32, i32]
             L.rtgs_query.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
             L.rtgs_debug_stage.argtypes = [vp, vp, vp, vp, i32, i64, vp, u64, vp, vp, vp, vp,
@@ -301,6 +308,21 @@ def prune_by_grad(handle, g_means, g_cov3d, visible, mask_in, lam, max_ratio, ma
                                _p(score_out), _stream(stream)))
 
 
+def adam_step(handle, groups, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """groups: iterable of (param, grad, exp_avg, exp_avg_sq, lr, step); the
+    four tensors are contiguous float32 device tensors of one size, updated in
+    place."""
+    groups = list(groups)
+    arr = (CAdamGroup * max(len(groups), 1))()
+    for k, (p, g, m, v, lr, step) in enumerate(groups):
+        for t in (p, g, m, v):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != p.numel():
+                raise ValueError("adam_step: contiguous float32 tensors of one size expected")
+        arr[k] = CAdamGroup(_p(p), _p(g), _p(m), _p(v), p.numel(), float(lr), int(step))
+    _check(lib().adam_step(handle.ptr, arr, len(groups), float(beta1), float(beta2), float(eps),
+                           _stream(stream)))
+
+
 def downsample_mask(final_T, log2_ratio, mask_out, n_active=None, stream=None):
     h, w = final_T.shape
     _check(lib().downsample_mask(_p(final_T), w, h, int(log2_ratio), _p(mask_out),
@@ -355,7 +377,10 @@ def rtgs_profile_read(handle):
 
 
 def rtgs_selftest_wave_sum(inp, out, stream=None):
-    _check(lib().rtgs_selftest_wave_sum(_p(inp), _p(out), out.numel(), _stream(stream)))
+    """inp: [n_waves * 10 * 64], out: [n_waves * 10] device float tensors."""
+    if out.numel() % 10 or inp.numel() != out.numel() * 64:
+        raise ValueError("rtgs_selftest_wave_sum: 640 inputs and 10 outputs per wave")
+    _check(lib().rtgs_selftest_wave_sum(_p(inp), _p(out), out.numel() // 10, _stream(stream)))
 
 
 # --------------------------------------------------------------------------- managed renderer

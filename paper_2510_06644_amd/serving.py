@@ -427,10 +427,9 @@ class GpuExecutor:
                                                           device=self.dev),
                             st.depth + 0.01 * torch.randn(st.depth.shape, generator=g,
                                                           device=self.dev)))
-        maps = [p.clone().requires_grad_(True) for p in params]
-        opt = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in
-                                zip(maps, (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3))],
-                               eps=1e-15, fused=True)
+        from .optim import MapAdam
+        maps = [p.clone() for p in params]
+        opt = MapAdam(maps, eps=1e-15)
         self.sessions[s] = dict(
             spec=spec, cam=rc, params=maps, opt=opt, targets=targets,
             viewmat=torch.eye(3, 4, dtype=torch.float32, device=self.dev).contiguous(),
@@ -451,9 +450,8 @@ class GpuExecutor:
         S = self.sessions.get(s)
         if S is None or S.get("offloaded"):
             return
-        S["opt_state"] = S["opt"].state_dict()
-        S["params"] = [p.detach().cpu() for p in S["params"]]
-        S["opt"] = None
+        S["params"] = [p.cpu() for p in S["params"]]
+        S["opt"].to("cpu").rebind(S["params"])
         for k in ("viewmat", "m", "v", "gpose", "pmask"):
             S[k] = S[k].cpu()
         S["targets"] = [(c.cpu(), d.cpu()) for c, d in S["targets"]]
@@ -464,11 +462,8 @@ class GpuExecutor:
     def _restore(self, s):
         torch = self.torch
         S = self.sessions[s]
-        S["params"] = [p.to(self.dev).requires_grad_(True) for p in S["params"]]
-        S["opt"] = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in
-                                     zip(S["params"], (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3))],
-                                    eps=1e-15, fused=True)
-        S["opt"].load_state_dict(S.pop("opt_state"))
+        S["params"] = [p.to(self.dev) for p in S["params"]]
+        S["opt"].to(self.dev).rebind(S["params"])
         for k in ("viewmat", "m", "v", "gpose", "pmask"):
             S[k] = S[k].to(self.dev)
         S["targets"] = [(c.to(self.dev), d.to(self.dev)) for c, d in S["targets"]]
@@ -538,11 +533,10 @@ class GpuExecutor:
                           g_colors=g[4])
                 grads.append(g)
             rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=rtgs.RTGS_GRAD_MAP)
-            for f, g in zip(frames, grads):
-                S = self.sessions[f.session]
-                for p, gg in zip(S["params"], g):
-                    p.grad = gg
-                S["opt"].step()
+            # one update launch for the maps of every session of the group
+            from .optim import step_many
+            step_many(self.handle, [(self.sessions[f.session]["opt"], g)
+                                    for f, g in zip(frames, grads)])
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         return ev

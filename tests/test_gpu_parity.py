@@ -36,12 +36,15 @@ def _case(name="c0", xi=None, n=None, cam=None, seed=None):
 def test_wave_sum_selftest():
     say("test_wave_sum_selftest")
     g = torch.Generator().manual_seed(0)
-    x = torch.randn(64 * 37, generator=g).cuda()
-    out = torch.empty(37).cuda()
-    rtgs.rtgs_selftest_wave_sum(x, out)
+    # distinct magnitudes per value so that a value landing in another
+    # value's slot cannot pass
+    scale = 10.0 ** torch.arange(10, dtype=torch.float32)[None, :, None] / 1e5
+    x = (torch.randn(37, 10, 64, generator=g) + 3.0) * scale
+    out = torch.full((37 * 10,), float("nan")).cuda()
+    rtgs.rtgs_selftest_wave_sum(x.reshape(-1).cuda(), out)
     torch.cuda.synchronize()
-    want = x.double().view(37, 64).sum(1)
-    assert torch.allclose(out.double(), want, rtol=1e-5, atol=1e-5)
+    want = x.double().sum(2).reshape(-1)
+    assert torch.allclose(out.double().cpu(), want, rtol=1e-5, atol=0)
 
 
 @pytest.mark.parametrize("posed", [False, True])

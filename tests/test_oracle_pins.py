@@ -418,3 +418,35 @@ def test_pose_gradient_is_the_left_perturbation_of_the_viewmat_gradient():
     assert np.allclose(g.pose[:3].numpy(), gv[:, 3], rtol=1e-12, atol=1e-10)
     assert np.allclose(g.pose[3:].numpy(), [a[2, 1] - a[1, 2], a[0, 2] - a[2, 0], a[1, 0] - a[0, 1]],
                        rtol=1e-10, atol=1e-8)
+
+
+# ------------------------------------------------- map update (Sec. 3.1)
+def test_adam_first_step_of_constant_gradient_closed_form():
+    # m1 / (1 - b1) = g and v1 / (1 - b2) = g^2, so the first update is
+    # p - lr g / (|g| + eps) whatever the betas
+    rng = np.random.default_rng(3)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50) * 10.0 ** rng.integers(-4, 3, size=50)
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.9)):
+        p1, m1, v1 = oracle.adam_step(p, g, np.zeros(50), np.zeros(50), 1, 0.01, b1, b2, 1e-8)
+        np.testing.assert_allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(m1, (1 - b1) * g, rtol=1e-15)
+        np.testing.assert_allclose(v1, (1 - b2) * g * g, rtol=1e-15)
+
+
+def test_adam_matches_torch_adam_over_several_steps():
+    rng = np.random.default_rng(4)
+    p0 = rng.normal(size=(40, 3))
+    grads = [rng.normal(size=(40, 3)) for _ in range(6)]
+    pt = torch.tensor(p0, dtype=F64, requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=3e-3, betas=(0.8, 0.99), eps=1e-10)
+    p, m, v = p0, np.zeros_like(p0), np.zeros_like(p0)
+    for t, g in enumerate(grads, 1):
+        pt.grad = torch.tensor(g, dtype=F64)
+        opt.step()
+        p, m, v = oracle.adam_step(p, g, m, v, t, 3e-3, 0.8, 0.99, 1e-10)
+        np.testing.assert_allclose(p, pt.detach().numpy(), rtol=1e-13, atol=1e-15)
+    st = opt.state[pt]
+    # torch forms m by lerp: equal up to rounding of a near-cancelling sum
+    np.testing.assert_allclose(m, st["exp_avg"].numpy(), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-13, atol=1e-15)
