@@ -15,8 +15,9 @@
 //    (depth bits, id) keys through LDS-atomic cursors.  The same pass writes
 //    each Gaussian's first slot in Gaussian-major pair order, which the
 //    backward uses to merge gradients without atomics.  Then one workgroup
-//    per tile sorts its range in LDS (bitonic network on 64-bit keys; ranges
-//    beyond the LDS capacity sort in place in global memory).  No host sync:
+//    per tile sorts its range in LDS (merge sort of 64-bit keys; long ranges
+//    go to a second kernel with 1024 threads, and ranges beyond its LDS
+//    capacity sort in place in global memory).  No host sync:
 //    the pair total stays on the device and a capacity overflow only drops
 //    pairs.
 #include "rtgs_internal.h"
@@ -24,7 +25,6 @@
 namespace rtgs {
 namespace {
 
-constexpr int kSortLds = 4096;    // 64-bit keys sorted in LDS per tile (32 KB)
 constexpr int kScanThreads = 1024;
 
 __global__ void k_init(long long* counters) {
@@ -415,24 +415,114 @@ __device__ void bitonic_sort(P a, int n) {
   }
 }
 
-// One workgroup per tile: sort its keys, write the Gaussian ids in order.
+// Merge sort of one tile's 64-bit keys with NT threads holding 4 keys each
+// (lists up to 4 NT keys; the tail is padded with all-ones keys, which no
+// real key equals since depth bits of a finite float are below 0x7f800000).
+// Each thread sorts its 4 keys in registers, then log2(NT) merge levels run
+// through two LDS buffers: a thread finds where its 4 outputs start on the
+// merge path of its pair of runs by binary search and merges 4 keys.  One
+// barrier per level, instead of one per bitonic stage.
+constexpr unsigned long long kKeyPad = ~0ull;
+constexpr int kSortPerThread = 4;
+
+__device__ __forceinline__ void cas(unsigned long long& a, unsigned long long& b) {
+  const unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+
+template <int NT>
+__device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, int n,
+                                unsigned long long* buf0, unsigned long long* buf1) {
+  constexpr int K = kSortPerThread, N = K * NT;
+  const int t = threadIdx.x;
+  unsigned long long k[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) k[s] = K * t + s < n ? keys[K * t + s] : kKeyPad;
+  cas(k[0], k[1]);
+  cas(k[2], k[3]);
+  cas(k[0], k[2]);
+  cas(k[1], k[3]);
+  cas(k[1], k[2]);
+#pragma unroll
+  for (int s = 0; s < K; ++s) buf0[K * t + s] = k[s];
+  __syncthreads();
+  unsigned long long* src = buf0;
+  unsigned long long* dst = buf1;
+  for (int L = K; L < N; L <<= 1) {
+    const int pos = K * t;
+    const int base = pos & ~(2 * L - 1);
+    const int r = pos - base;
+    const unsigned long long* A = src + base;
+    const unsigned long long* Bv = src + base + L;
+    // number of A keys among the first r outputs (ties: A first)
+    int lo = r > L ? r - L : 0, hi = r < L ? r : L;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (A[mid] <= Bv[r - 1 - mid]) lo = mid + 1;
+      else hi = mid;
+    }
+    int i = lo, j = r - lo;
+    unsigned long long x = i < L ? A[i] : kKeyPad, y = j < L ? Bv[j] : kKeyPad;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const bool take_a = j >= L || (i < L && x <= y);
+      dst[pos + s] = take_a ? x : y;
+      if (take_a) {
+        ++i;
+        x = i < L ? A[i] : kKeyPad;
+      } else {
+        ++j;
+        y = j < L ? Bv[j] : kKeyPad;
+      }
+    }
+    __syncthreads();
+    unsigned long long* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  for (int i = t; i < n; i += NT) ids[i] = (uint32_t)src[i];
+}
+
+// One workgroup per tile: lists of up to 1024 keys are sorted here; longer
+// ones are queued for k_sort_big_tiles.
 __global__ __launch_bounds__(kBlock) void k_sort_tiles(WsPtrs W) {
-  __shared__ unsigned long long sk[kSortLds];
+  __shared__ unsigned long long b0[kSortPerThread * kBlock], b1[kSortPerThread * kBlock];
   const int t = blockIdx.x;
   const int64_t cap = W.cap;
   const int64_t st = min((int64_t)W.tile_start[t], cap);
   const int64_t en = min((int64_t)W.tile_start[t + 1], cap);
   const int n = (int)(en - st);
   if (n <= 0) return;
-  if (n <= kSortLds) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) sk[i] = W.keys[st + i];
+  if (n > kSortPerThread * kBlock) {
+    if (threadIdx.x == 0) {
+      const unsigned long long q = atomicAdd((unsigned long long*)&W.counters[2], 1ull);
+      W.big_tiles[q] = (uint32_t)t;
+    }
+    return;
+  }
+  merge_sort_tile<kBlock>(W.keys + st, W.ids + st, n, b0, b1);
+}
+
+// Queued long lists: up to 4096 keys by the LDS merge sort with 1024
+// threads, longer ones by the bitonic network in place in global memory.
+constexpr int kBigThreads = 1024;
+__global__ __launch_bounds__(kBigThreads) void k_sort_big_tiles(WsPtrs W) {
+  __shared__ unsigned long long b0[kSortPerThread * kBigThreads], b1[kSortPerThread * kBigThreads];
+  const long long count = W.counters[2];
+  for (long long q = blockIdx.x; q < count; q += gridDim.x) {
+    const int t = (int)W.big_tiles[q];
+    const int64_t st = min((int64_t)W.tile_start[t], W.cap);
+    const int64_t en = min((int64_t)W.tile_start[t + 1], W.cap);
+    const int n = (int)(en - st);
+    if (n <= kSortPerThread * kBigThreads) {
+      merge_sort_tile<kBigThreads>(W.keys + st, W.ids + st, n, b0, b1);
+    } else {
+      unsigned long long* g = W.keys + st;
+      bitonic_sort(g, n);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) W.ids[st + i] = (uint32_t)g[i];
+    }
     __syncthreads();
-    bitonic_sort(sk, n);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) W.ids[st + i] = (uint32_t)sk[i];
-  } else {
-    unsigned long long* g = W.keys + st;
-    bitonic_sort(g, n);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) W.ids[st + i] = (uint32_t)g[i];
   }
 }
 
@@ -510,6 +600,7 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
   if (b.t_total > 0) {
     Scope sc(tm, kStSort, st);
     k_sort_tiles<<<b.t_total, kBlock, 0, st>>>(w);
+    k_sort_big_tiles<<<b.t_total < 512 ? b.t_total : 512, kBigThreads, 0, st>>>(w);
   }
   return hipGetLastError();
 }

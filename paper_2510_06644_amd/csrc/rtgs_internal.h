@@ -72,7 +72,7 @@ struct SessionDev {
 // Offsets of the workspace regions (bytes from ws).
 struct WsLayout {
   uint64_t table;       // SessionDev[RTGS_MAX_SESSIONS]
-  uint64_t counters;    // int64[8]: 0 pairs of this call
+  uint64_t counters;    // int64[8]: 0 pairs of this call, 2 entries of big_tiles
   uint64_t rec;         // GaussRec[N]: the 64-byte raster record of each Gaussian
   uint64_t rect;        // int4[N]: tile rectangle
   uint64_t cnt;         // uint32[N]: tiles touched
@@ -85,6 +85,7 @@ struct WsLayout {
   uint64_t gsum;        // uint32[16][T]: per (group of chunks, tile) sums
   uint64_t tile_count;  // uint32[T + 1]
   uint64_t tile_start;  // uint32[T + 1]
+  uint64_t big_tiles;   // uint32[T]: tiles whose list is too long for the one-pass sort
   uint64_t keys;        // uint64[cap]
   uint64_t ids;         // uint32[cap]
   uint64_t partial;     // float[cap][10]: per (tile, Gaussian) merged 2D gradient
@@ -130,6 +131,7 @@ struct WsPtrs {
   uint32_t* gsum;
   uint32_t* tile_count;
   uint32_t* tile_start;
+  uint32_t* big_tiles;
   unsigned long long* keys;
   uint32_t* ids;
   float* partial;

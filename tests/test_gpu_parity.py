@@ -226,15 +226,19 @@ def test_capacity_overflow_is_reported_then_recovers():
     assert rel_err(st2.color.cpu().numpy(), ref.color.numpy(), keep) < IMG_TOL
 
 
-def test_long_tile_list_takes_the_global_sort_path(renderer):
-    say("test_long_tile_list")
-    # 6,000 small Gaussians inside one 16x16 tile: longer than the LDS sort
+@pytest.mark.parametrize("n,span,lo,hi", [(900, 8, 700, 1024), (2500, 8, 1025, 4096),
+                                          (6000, 8, 4097, 10 ** 9), (9000, 24, 1025, 4096)])
+def test_long_tile_lists_take_each_sort_path(renderer, n, span, lo, hi):
+    # n small Gaussians over a span x span pixel square from (4, 4): one tile
+    # (span 8) or four (span 24); the longest list selects the path: the
+    # one-workgroup merge sort (<= 1024 keys), the queued 1024-thread merge
+    # sort (<= 4096) or the in-place global sort
+    say(f"test_long_tile_lists n={n} span={span}")
     cam = synth.Camera(32, 32, 25.6, 25.6, 16.0, 16.0)
     rng = np.random.default_rng(8)
-    n = 6000
     z = rng.uniform(1, 3, n)
-    u = rng.uniform(4, 12, n)
-    v = rng.uniform(4, 12, n)
+    u = rng.uniform(4, 4 + span, n)
+    v = rng.uniform(4, 4 + span, n)
     means = np.stack([(u - 16) * z / 25.6, (v - 16) * z / 25.6, z], 1)
     sc = synth.Scene(means.astype(np.float32), np.full((n, 3), -5.5, np.float32),
                      np.tile(np.float32([1, 0, 0, 0]), (n, 1)),
@@ -245,7 +249,10 @@ def test_long_tile_list_takes_the_global_sort_path(renderer):
     valid = np.ones(n, bool)
     ranges, ids = binning.tile_lists(stg[:, 0], stg[:, 1], stg[:, 7], stg[:, 8], stg[:, 6],
                                      valid, 32, 32)
-    assert (ranges[:, 1] - ranges[:, 0]).max() > 4096
+    longest = (ranges[:, 1] - ranges[:, 0]).max()
+    say(f"  longest list {longest}")
+    assert lo <= longest <= hi
+    assert np.array_equal(dbg["ranges"], ranges)
     assert np.array_equal(dbg["ids"], ids)
     ref = oracle.render(sc.arrays(), eye_view(), cam_tuple(cam))
     keep = ~ref.flags.numpy()
