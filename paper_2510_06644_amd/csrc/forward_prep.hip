@@ -155,15 +155,20 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
   W.cnt[gid] = vis ? (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1)) : 0u;
 }
 
+// Threads per workgroup of the binning passes over a chunk: one Gaussian per
+// thread, so the few hundred chunks of a frame still fill the chip.
+constexpr int kBinThreads = 1024;
+static_assert(kChunk % kBinThreads == 0, "whole rounds per chunk");
+
 // In-chunk exclusive offsets of the Gaussians' tile counts, in local index
 // order, into s_off[0..kChunk]; s_off[kChunk] = the chunk's pair total, which
-// is returned.  Local index i = j * 256 + thread for round j.
+// is returned.  Local index i = j * kBinThreads + thread for round j.
 __device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, uint32_t* s_off,
                                   uint32_t* s_wave) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t carry = 0;
-  for (int j = 0; j < kChunk / kBlock; ++j) {
-    const int i = j * kBlock + (int)threadIdx.x;
+  for (int j = 0; j < kChunk / kBinThreads; ++j) {
+    const int i = j * kBinThreads + (int)threadIdx.x;
     const int li = c * kChunk + i;
     const uint32_t n = li < S.n ? W.cnt[S.gauss_base + li] : 0u;
     uint32_t x = n;
@@ -174,7 +179,7 @@ __device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, u
     if (lane == 63) s_wave[wave] = x;
     __syncthreads();
     uint32_t before = 0, tot = 0;
-    for (int q = 0; q < kBlock / 64; ++q) {
+    for (int q = 0; q < kBinThreads / 64; ++q) {
       before += q < wave ? s_wave[q] : 0u;
       tot += s_wave[q];
     }
@@ -188,7 +193,7 @@ __device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, u
 }
 
 // Walk this thread's share of the chunk's pairs: pairs [m0, m1) in
-// Gaussian-major order, m0 = thread * ceil(total / 256).  One binary search
+// Gaussian-major order, m0 = thread * ceil(total / kBinThreads).  One binary search
 // finds the first Gaussian; after that the walk steps through tiles of the
 // Gaussian's rectangle row by row and on to the next Gaussian, so pairs are
 // spread evenly however many tiles a Gaussian touches.  f(local index, tile)
@@ -196,7 +201,7 @@ __device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, u
 template <typename F>
 __device__ __forceinline__ void chunk_pairs(const SessionDev& S, const WsPtrs& W, int c,
                                             const uint32_t* s_off, uint32_t total, F f) {
-  const uint32_t per = (total + kBlock - 1) / kBlock;
+  const uint32_t per = (total + kBinThreads - 1) / kBinThreads;
   const uint32_t m0 = threadIdx.x * per;
   const uint32_t m1 = min(total, m0 + per);
   if (m0 >= m1) return;
@@ -230,22 +235,22 @@ __device__ __forceinline__ void chunk_pairs(const SessionDev& S, const WsPtrs& W
 
 // Per chunk of kChunk Gaussians: pair counts per tile of the session (LDS
 // histogram), and the chunk's pair total.
-__global__ __launch_bounds__(kBlock) void k_chunk_hist(Batch B, WsPtrs W) {
+__global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_hist[];
   __shared__ uint32_t s_off[kChunk + 1];
-  __shared__ uint32_t s_wave[kBlock / 64];
+  __shared__ uint32_t s_wave[kBinThreads / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
   const SessionDev& S = B.sess[s];
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
-  for (int t = threadIdx.x; t < ts; t += kBlock) s_hist[t] = 0u;
+  for (int t = threadIdx.x; t < ts; t += kBinThreads) s_hist[t] = 0u;
   const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
   // pairs are dealt evenly over the threads, whatever the Gaussians' sizes
   chunk_pairs(S, W, c, s_off, total, [&](int, int tile) { atomicAdd(&s_hist[tile], 1u); });
   __syncthreads();
   uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
-  for (int t = threadIdx.x; t < ts; t += kBlock) h[t] = s_hist[t];
+  for (int t = threadIdx.x; t < ts; t += kBinThreads) h[t] = s_hist[t];
   if (threadIdx.x == 0) W.chunk_total[blockIdx.x] = total;
 }
 
@@ -347,21 +352,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_tot
 // Per chunk: each Gaussian's first Gaussian-major slot, then
 // (depth bits << 32 | id) keys scattered into the tile ranges through LDS
 // cursors, pairs dealt evenly over the threads.
-__global__ __launch_bounds__(kBlock) void k_emit(Batch B, WsPtrs W) {
+__global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_cur[];
   __shared__ uint32_t s_off[kChunk + 1];
-  __shared__ uint32_t s_wave[kBlock / 64];
+  __shared__ uint32_t s_wave[kBinThreads / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
   const SessionDev& S = B.sess[s];
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
   const uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
-  for (int t = threadIdx.x; t < ts; t += kBlock) s_cur[t] = W.tile_start[S.tile_base + t] + h[t];
+  for (int t = threadIdx.x; t < ts; t += kBinThreads) s_cur[t] = W.tile_start[S.tile_base + t] + h[t];
   const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
   const uint32_t base = W.chunk_off[blockIdx.x];
-  for (int j = 0; j < kChunk / kBlock; ++j) {
-    const int i = j * kBlock + (int)threadIdx.x;
+  for (int j = 0; j < kChunk / kBinThreads; ++j) {
+    const int i = j * kBinThreads + (int)threadIdx.x;
     const int li = c * kChunk + i;
     if (li < S.n) W.goff[S.gauss_base + li] = base + s_off[i];
   }
@@ -584,7 +589,7 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
   }
   if (b.c_total > 0) {
     Scope sc(tm, kStBinCount, st);
-    k_chunk_hist<<<b.c_total, kBlock, lds, st>>>(b, w);
+    k_chunk_hist<<<b.c_total, kBinThreads, lds, st>>>(b, w);
   }
   {
     Scope sc(tm, kStScan, st);
@@ -595,7 +600,7 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
   }
   if (b.c_total > 0) {
     Scope sc(tm, kStEmit, st);
-    k_emit<<<b.c_total, kBlock, lds, st>>>(b, w);
+    k_emit<<<b.c_total, kBinThreads, lds, st>>>(b, w);
   }
   if (b.t_total > 0) {
     Scope sc(tm, kStSort, st);
