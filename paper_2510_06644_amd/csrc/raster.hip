@@ -144,49 +144,51 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   const int tid = threadIdx.x;
   const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
-  const int64_t start = min((int64_t)W.tile_start[tile], W.cap);
-  const int64_t end = min((int64_t)W.tile_start[tile + 1], W.cap);
+  // list positions fit in int32: the pair capacity is below 2^31
+  const int start = (int)min((int64_t)W.tile_start[tile], W.cap);
+  const int end = (int)min((int64_t)W.tile_start[tile + 1], W.cap);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   int last = -1;
-  int64_t stop = end;           // list position where the pixel stopped
+  int stop = end;               // list position where the pixel stopped
   int nblend = 0;
   bool done = !active;
-  for (int64_t b0 = start; b0 < end; b0 += kBlock) {
+  for (int b0 = start; b0 < end; b0 += kBlock) {
     if (__syncthreads_and(done)) break;
-    const int64_t e = b0 + tid;
+    const int e = b0 + tid;
     if (e < end) {
       const GaussRec r = W.rec[W.ids[e]];
       s_r0[tid] = r.pos;
-      s_r1[tid] = r.conic;
+      s_r1[tid] = conic_log2(r.conic);
       s_r2[tid] = r.col;
       s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
     }
     __syncthreads();
-    const int cnt = (int)min((int64_t)kBlock, end - b0);
+    const int cnt = min(kBlock, end - b0);
     for (int q = 0; q < kBlock / 64; ++q) {
       unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
       while (m) {
         if (__ballot(!done) == 0) break;               // the whole wave has stopped
         const int k = 64 * q + __builtin_ctzll(m);
         m &= m - 1;
-        if (done) continue;
+        // every lane evaluates the entry; the decisions below are selects,
+        // not branches: skip (alpha < 1/255), stop (T would fall below
+        // 1e-4; the fragment is excluded) or blend
         const Frag f = frag_alpha(s_r0[k], s_r1[k], pxf, pyf);
-        if (f.alpha < kAlphaMin) continue;
         const float tn = T * f.om;
-        if (tn < kTMin) {
-          done = true;
-          stop = b0 + k;
-          continue;
-        }
-        const float w = f.alpha * T;
+        const bool hit = !done && !(f.alpha < kAlphaMin);
+        const bool stop_here = hit && tn < kTMin;
+        const bool blend = hit && !(tn < kTMin);
+        done = done || stop_here;
+        stop = stop_here ? b0 + k : stop;
+        const float w = blend ? f.alpha * T : 0.f;       // adds exactly 0 otherwise
         const float4 col = s_r2[k];
         C0 = __builtin_fmaf(w, col.x, C0);
         C1 = __builtin_fmaf(w, col.y, C1);
         C2 = __builtin_fmaf(w, col.z, C2);
         D = __builtin_fmaf(w, col.w, D);
-        T = tn;
-        last = (int)(b0 + k);
-        ++nblend;
+        T = blend ? tn : T;
+        last = blend ? b0 + k : last;
+        nblend += blend ? 1 : 0;
       }
     }
     __syncthreads();
@@ -214,8 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         // work counts: fragments blended, list entries up to the stop (or
         // the end of the list), list entries up to the last blended one
         S.stats[p] = me ? nblend : 0;
-        S.stats[hw + p] = me && active ? (int)(min(stop + 1, end) - start) : 0;
-        S.stats[2 * hw + p] = me && last >= 0 ? (int)(last - start + 1) : 0;
+        S.stats[hw + p] = me && active ? min(stop + 1, end) - start : 0;
+        S.stats[2 * hw + p] = me && last >= 0 ? last - start + 1 : 0;
       }
     }
 }
@@ -237,7 +239,7 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
-  __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch];
+  __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch], s_cn[kBwdBatch];
   __shared__ unsigned s_m[kBwdBatch];
   __shared__ float s_part[4][kBwdBatch * kStride];
   __shared__ int s_hi;
@@ -265,23 +267,27 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   __syncthreads();
   if (last >= 0) atomicMax(&s_hi, last);
   __syncthreads();
-  const int64_t start = min((int64_t)W.tile_start[tile], W.cap);
-  const int64_t end = min((int64_t)W.tile_start[tile + 1], W.cap);
+  const int start = (int)min((int64_t)W.tile_start[tile], W.cap);
+  const int end = (int)min((int64_t)W.tile_start[tile + 1], W.cap);
   // a saved position outside this tile's list (state of another forward) is
   // never followed past the list
-  const int64_t hi = min((int64_t)s_hi, end - 1);
+  const int hi = min(s_hi, end - 1);
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
-  float S0 = 0.f, S1 = 0.f, S2 = 0.f, Sz = 0.f;   // suffix sums normalised by T
+  // S_j . g: the colour and depth of the fragments behind j, normalised by
+  // the transmittance T_{j+1} they start from, dotted with the upstream gradient
+  float SG = 0.f;
   float* part = s_part[wave];
-  for (int64_t bend = hi + 1; bend > start; bend -= kBwdBatch) {
-    const int64_t b0 = bend - kBwdBatch > start ? bend - kBwdBatch : start;
-    const int cnt = (int)(bend - b0);
+  for (int bend = hi + 1; bend > start; bend -= kBwdBatch) {
+    const int b0 = max(bend - kBwdBatch, start);
+    const int cnt = bend - b0;
+    const int lrel = last - b0;     // entries k <= lrel lie before the pixel's stop
     __syncthreads();
     if (tid < cnt) {
       const GaussRec r = W.rec[W.ids[b0 + tid]];
       s_r0[tid] = r.pos;
-      s_r1[tid] = r.conic;
+      s_r1[tid] = conic_log2(r.conic);
       s_r2[tid] = r.col;
+      s_cn[tid] = r.conic;
       s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
     }
     // zero this batch's partial sums (each wave its own)
@@ -293,57 +299,55 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
         const int bit = 63 - __builtin_clzll(m);       // descending list order
         m &= ~(1ull << bit);
         const int k = 64 * q + bit;
+        const float4 k4 = s_r1[k];
+        const Frag f = frag_alpha(s_r0[k], k4, pxf, pyf);
+        const bool contrib = k <= lrel && !(f.alpha < kAlphaMin);
+        if (__ballot(contrib) == 0) continue;          // no lane blended this entry
+        // lanes that did not blend it take alpha = 0 and 1 - alpha = 1, so
+        // every update below leaves their state unchanged and their
+        // gradients exactly zero (selects, not branches)
+        const float4 col = s_r2[k];
+        const float al = contrib ? f.alpha : 0.f;
+        const float om = contrib ? f.om : 1.f;
+        const float rom = __builtin_amdgcn_rcpf(om);
+        const float Tj = contrib ? Tc * rom : Tc;       // T before this fragment
+        const float w = al * Tj;
+        // (colour, depth) of the fragment dotted with the upstream gradient
+        float cg = col.x * g0;
+        cg = __builtin_fmaf(col.y, g1, cg);
+        cg = __builtin_fmaf(col.z, g2, cg);
+        cg = __builtin_fmaf(col.w, gD, cg);
+        // dL/dalpha_j = T_j (c_j - S_j) . g + T_final gA / (1 - alpha_j)
+        const float dla = __builtin_fmaf(Tj, cg - SG, gAT * rom);
+        SG = __builtin_fmaf(al, cg, om * SG);
+        Tc = Tj;
+        // the clamp alpha = 0.99 has no gradient to o or to the power
+        const bool live = contrib && !(k4.w * f.e > kAlphaMax);
+        const float ng = live ? -(f.alpha * dla) : 0.f;  // -dL/dpower
+        const float p = ng * f.dx, q = ng * f.dy;
+        // summed over the tile's pixels, these give the 2D gradients once
+        // the Gaussian's conic is applied (epilogue)
         float v[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = 0.f;
-        bool contrib = false;
-        if ((int64_t)b0 + k <= (int64_t)last) {
-          const float4 r1 = s_r1[k];
-          const Frag f = frag_alpha(s_r0[k], r1, pxf, pyf);
-          if (f.alpha >= kAlphaMin) {
-            contrib = true;
-            const float4 col = s_r2[k];
-            const float om = f.om;
-            const float rom = __builtin_amdgcn_rcpf(om);
-            const float Tj = Tc * rom;                    // T before this fragment
-            const float w = f.alpha * Tj;
-            float dla = (col.x - S0) * g0;
-            dla = __builtin_fmaf(col.y - S1, g1, dla);
-            dla = __builtin_fmaf(col.z - S2, g2, dla);
-            dla = __builtin_fmaf(col.w - Sz, gD, dla);
-            dla = __builtin_fmaf(Tj, dla, gAT * rom);     // dL/dalpha
-            S0 = __builtin_fmaf(f.alpha, col.x, om * S0);
-            S1 = __builtin_fmaf(f.alpha, col.y, om * S1);
-            S2 = __builtin_fmaf(f.alpha, col.z, om * S2);
-            Sz = __builtin_fmaf(f.alpha, col.w, om * Sz);
-            Tc = Tj;
-            v[NV - 1] = w * gD;                           // depth slot (last)
-            if (NV == 10) {
-              v[6] = w * g0;
-              v[7] = w * g1;
-              v[8] = w * g2;
-            }
-            if (!(r1.w * f.e > kAlphaMax)) {              // not clamped
-              const float gp = f.alpha * dla;             // dL/dpower
-              if (NV == 10) v[5] = f.e * dla;              // dL/do
-              v[0] = -gp * __builtin_fmaf(r1.x, f.dx, r1.y * f.dy);
-              v[1] = -gp * __builtin_fmaf(r1.y, f.dx, r1.z * f.dy);
-              v[2] = -0.5f * gp * f.dx * f.dx;
-              v[3] = -gp * f.dx * f.dy;
-              v[4] = -0.5f * gp * f.dy * f.dy;
-            }
-          }
+        v[0] = p;
+        v[1] = q;
+        v[2] = p * f.dx;
+        v[3] = p * f.dy;
+        v[4] = q * f.dy;
+        v[NV - 1] = w * gD;                               // depth slot (last)
+        if (NV == 10) {
+          v[5] = live ? f.e * dla : 0.f;                  // dL/do
+          v[6] = w * g0;
+          v[7] = w * g1;
+          v[8] = w * g2;
         }
-        if (__ballot(contrib)) {
-          float x[3];
-          wave_reduce_scatter<NV>(v, x);
-          if ((lane & 15) == 15) {
-            const int row = lane >> 4;
+        float x[3];
+        wave_reduce_scatter<NV>(v, x);
+        if ((lane & 15) == 15) {
+          const int row = lane >> 4;
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-              if ((row & 1) + 2 * j < NV / 2)
-                part[k * kStride + wave_scatter_index(NV, row, j)] = x[j];
-          }
+          for (int j = 0; j < 3; ++j)
+            if ((row & 1) + 2 * j < NV / 2)
+              part[k * kStride + wave_scatter_index(NV, row, j)] = x[j];
         }
       }
     }
@@ -352,18 +356,31 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
       const uint32_t g = W.ids[b0 + tid];
       const int64_t slot = pair_slot(W, g, ltx, lty);
       if (slot < W.cap) {
-        float* dst = W.partial + slot * NV;
+        float t[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
           const int o = tid * kStride + i;
-          dst[i] = ((s_part[0][o] + s_part[1][o]) + s_part[2][o]) + s_part[3][o];
+          t[i] = ((s_part[0][o] + s_part[1][o]) + s_part[2][o]) + s_part[3][o];
         }
+        // d power / d(u, v) = -(a dx + b dy, b dx + c dy) and
+        // d power / d(a, b, c) = -(dx^2 / 2, dx dy, dy^2 / 2): the sums of
+        // p = -g dx and q = -g dy (g = dL/dpower) and of p dx, p dy, q dy
+        // become the 2D gradients with the conic applied once here
+        const float4 cn = s_cn[tid];
+        float* dst = W.partial + slot * NV;
+        dst[0] = __builtin_fmaf(cn.x, t[0], cn.y * t[1]);
+        dst[1] = __builtin_fmaf(cn.y, t[0], cn.z * t[1]);
+        dst[2] = 0.5f * t[2];
+        dst[3] = t[3];
+        dst[4] = 0.5f * t[4];
+#pragma unroll
+        for (int i = 5; i < NV; ++i) dst[i] = t[i];
       }
     }
   }
   // pairs after the last blended fragment of every pixel carry no gradient
-  const int64_t z0 = hi + 1 > start ? hi + 1 : start;
-  for (int64_t pos = z0 + tid; pos < end; pos += kBlock) {
+  const int z0 = max(hi + 1, start);
+  for (int pos = z0 + tid; pos < end; pos += kBlock) {
     const uint32_t g = W.ids[pos];
     const int64_t slot = pair_slot(W, g, ltx, lty);
     if (slot < W.cap) {

@@ -311,27 +311,35 @@ __device__ __forceinline__ int wave_scatter_index(int nv, int row, int s) {
 
 // Raster-side alpha of one (pixel, Gaussian) pair: the same instructions in
 // the forward and the backward so both take the same skip decisions.
-// r0 = (u_hi, v_hi, u_lo, v_lo), r1 = (a, b, c, opacity).
+// r0 = (u_hi, v_hi, u_lo, v_lo); k = (A, B, C, opacity), the conic (a, b, c)
+// pre-scaled to base-2 exponent units by conic_log2(), so that
+// exp(power) = 2^(A dx^2 + B dx dy + C dy^2) is one v_exp_f32.
 struct Frag {
   float dx, dy, e, alpha;   // e = exp(power), alpha = min(0.99, o e)
   float om;                 // 1 - alpha, from one fused rounding of 1 - o e
 };
 
-__device__ __forceinline__ Frag frag_alpha(float4 r0, float4 r1, float px, float py) {
+constexpr float kLog2e = 1.4426950408889634f;
+
+// (a, b, c, o) -> (-a log2(e) / 2, -b log2(e), -c log2(e) / 2, o):
+// power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 in natural-log units.
+__device__ __forceinline__ float4 conic_log2(float4 c) {
+  return make_float4(-0.5f * kLog2e * c.x, -kLog2e * c.y, -0.5f * kLog2e * c.z, c.w);
+}
+
+__device__ __forceinline__ Frag frag_alpha(float4 r0, float4 k, float px, float py) {
   Frag f;
   f.dx = (r0.x - px) + r0.z;
   f.dy = (r0.y - py) + r0.w;
-  const float qa = r1.x * f.dx;
-  const float qc = r1.z * f.dy;
-  // power = -0.5 (a dx^2 + c dy^2) - b dx dy
-  const float quad = __builtin_fmaf(qa, f.dx, qc * f.dy);
-  const float power = __builtin_fmaf(-0.5f, quad, -(r1.y * f.dx) * f.dy);
-  f.e = __expf(power);
-  const float raw = r1.w * f.e;
+  // log2 of exp(power) = dx (A dx + B dy) + C dy^2
+  const float t = __builtin_fmaf(k.x, f.dx, k.y * f.dy);
+  const float p2 = __builtin_fmaf(f.dx, t, (k.z * f.dy) * f.dy);
+  f.e = __builtin_amdgcn_exp2f(p2);
+  const float raw = k.w * f.e;
   f.alpha = fminf(kAlphaMax, raw);
   // 1 - alpha without rounding o e first: near-opaque fragments (alpha close
   // to 0.99) would otherwise lose digits of the transmittance they leave
-  f.om = raw > kAlphaMax ? 1.f - kAlphaMax : __builtin_fmaf(-r1.w, f.e, 1.f);
+  f.om = raw > kAlphaMax ? 1.f - kAlphaMax : __builtin_fmaf(-k.w, f.e, 1.f);
   return f;
 }
 
