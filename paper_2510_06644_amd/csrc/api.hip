@@ -475,7 +475,7 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   if (r) return r;
   StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
   hipError_t e = launch_forward_prep(B, w, h->d_scalars, st, tm);
-  if (e == hipSuccess) e = launch_raster_fwd(B, w, st, tm);
+  if (e == hipSuccess) e = launch_raster_fwd(B, w, (flags & RTGS_FWD_STATS) != 0, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_fwd launch");
   h->last_stream = st;
   h->used = true;
@@ -500,7 +500,7 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   if (r) return r;
   StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
   hipError_t e = hipSuccess;
-  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, st, tm);
+  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, false, st, tm);
   if (e == hipSuccess) e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, st, tm);
   if (e == hipSuccess) e = launch_preprocess_bwd(B, w, flags, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_bwd launch");

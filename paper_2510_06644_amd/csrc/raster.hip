@@ -134,6 +134,9 @@ __device__ __forceinline__ unsigned long long wave_entries(const unsigned* s_m, 
   return __ballot(hit);
 }
 
+// STATS: also count, per pixel, the fragments blended and the list entries
+// visited (the work counts of a frame); off in ordinary renders.
+template <bool STATS>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock];
   __shared__ unsigned s_m[kBlock];
@@ -152,16 +155,19 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   int stop = end;               // list position where the pixel stopped
   int nblend = 0;
   bool done = !active;
+  // the Gaussian id this thread stages next (loaded one batch ahead)
+  uint32_t nid = start + tid < end ? W.ids[start + tid] : 0u;
   for (int b0 = start; b0 < end; b0 += kBlock) {
     if (__syncthreads_and(done)) break;
     const int e = b0 + tid;
     if (e < end) {
-      const GaussRec r = W.rec[W.ids[e]];
+      const GaussRec r = W.rec[nid];
       s_r0[tid] = r.pos;
       s_r1[tid] = conic_log2(r.conic);
       s_r2[tid] = r.col;
       s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
     }
+    if (e + kBlock < end) nid = W.ids[e + kBlock];
     __syncthreads();
     const int cnt = min(kBlock, end - b0);
     for (int q = 0; q < kBlock / 64; ++q) {
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         const bool stop_here = hit && tn < kTMin;
         const bool blend = hit && !(tn < kTMin);
         done = done || stop_here;
-        stop = stop_here ? b0 + k : stop;
+        if (STATS) stop = stop_here ? b0 + k : stop;
         const float w = blend ? f.alpha * T : 0.f;       // adds exactly 0 otherwise
         const float4 col = s_r2[k];
         C0 = __builtin_fmaf(w, col.x, C0);
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         D = __builtin_fmaf(w, col.w, D);
         T = blend ? tn : T;
         last = blend ? b0 + k : last;
-        nblend += blend ? 1 : 0;
+        if (STATS) nblend += blend ? 1 : 0;
       }
     }
     __syncthreads();
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
       if (S.alpha) S.alpha[p] = me ? 1.f - T : 0.f;
       if (S.final_T) S.final_T[p] = me ? T : 1.f;
       if (S.last_idx) S.last_idx[p] = me ? last : -1;
-      if (S.stats) {
+      if (STATS && S.stats) {
         // work counts: fragments blended, list entries up to the stop (or
         // the end of the list), list entries up to the last blended one
         S.stats[p] = me ? nblend : 0;
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     }
 }
 
-constexpr int kBwdBatch = 128;           // list entries staged per batch
+constexpr int kBwdBatch = 64;            // list entries staged per batch
 
 // Gaussian-major slot of the pair (Gaussian g, tile (tx, ty)): g's first slot
 // plus the tile's row-major index inside g's tile rectangle.
@@ -277,18 +283,29 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   // the transmittance T_{j+1} they start from, dotted with the upstream gradient
   float SG = 0.f;
   float* part = s_part[wave];
+  // the Gaussian id this thread stages next (loaded one batch ahead)
+  uint32_t nid = 0;
+  {
+    const int b0 = max(hi + 1 - kBwdBatch, start);
+    if (tid < hi + 1 - b0) nid = W.ids[b0 + tid];
+  }
   for (int bend = hi + 1; bend > start; bend -= kBwdBatch) {
     const int b0 = max(bend - kBwdBatch, start);
     const int cnt = bend - b0;
     const int lrel = last - b0;     // entries k <= lrel lie before the pixel's stop
+    const uint32_t gid = nid;       // Gaussian of entry b0 + tid (tid < cnt)
     __syncthreads();
     if (tid < cnt) {
-      const GaussRec r = W.rec[W.ids[b0 + tid]];
+      const GaussRec r = W.rec[gid];
       s_r0[tid] = r.pos;
       s_r1[tid] = conic_log2(r.conic);
       s_r2[tid] = r.col;
       s_cn[tid] = r.conic;
       s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
+    }
+    {
+      const int nb0 = max(b0 - kBwdBatch, start);
+      if (tid < b0 - nb0) nid = W.ids[nb0 + tid];
     }
     // zero this batch's partial sums (each wave its own)
     for (int i = lane; i < kBwdBatch * kStride; i += 64) part[i] = 0.f;
@@ -353,8 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
     }
     __syncthreads();
     if (tid < cnt) {
-      const uint32_t g = W.ids[b0 + tid];
-      const int64_t slot = pair_slot(W, g, ltx, lty);
+      const int64_t slot = pair_slot(W, gid, ltx, lty);
       if (slot < W.cap) {
         float t[NV];
 #pragma unroll
@@ -393,11 +409,15 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
 
 }  // namespace
 
-hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, hipStream_t st, StageTimer* tm) {
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, hipStream_t st,
+                             StageTimer* tm) {
   if (b.t_total <= 0) return hipSuccess;
   const int grid = 8 * ((b.t_total + 7) / 8);
   Scope sc(tm, kStRasterFwd, st);
-  k_raster_fwd<<<grid, kBlock, 0, st>>>(b, w);
+  if (stats)
+    k_raster_fwd<true><<<grid, kBlock, 0, st>>>(b, w);
+  else
+    k_raster_fwd<false><<<grid, kBlock, 0, st>>>(b, w);
   return hipGetLastError();
 }
 
