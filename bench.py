@@ -106,27 +106,23 @@ def make_optimizer(params):
     return optim.MapAdam(params, eps=1e-15)
 
 
-def l1_grads(color, depth, tc, td, pixel_mask=None):
-    """dL/dC, dL/dD of L = mean|C - C^| / 3 ... over active pixels (Eq. 6 reading)."""
+def l1_grads(color, depth, tc, td, pixel_mask=None, n_active=None):
+    """dL/dC, dL/dD of L = mean|C - C^| / 3 + 0.5 mean|D - D^| over the active
+    pixels (Eq. 6 reading), by the library's loss kernel."""
     import torch
-    if pixel_mask is None:
-        n = color.shape[1] * color.shape[2]
-        gc = torch.sign(color - tc) * (1.0 / (3 * n))
-        gd = torch.sign(depth - td) * (0.5 / n)
-    else:
-        m = pixel_mask.to(color.dtype)
-        n = m.sum().clamp(min=1.0)
-        gc = torch.sign(color - tc) * m / (3 * n)
-        gd = torch.sign(depth - td) * m * (0.5 / n)
+    from paper_2510_06644_amd import rtgs
+    gc = torch.empty_like(color)
+    gd = torch.empty_like(depth)
+    rtgs.loss_l1_grad(color, depth, tc, td, gc, gd, pixel_mask=pixel_mask, n_active=n_active)
     return gc, gd
 
 
 def mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=None, pixel_mask=None,
-                 cov3d=False, sample_log2=0):
+                 cov3d=False, sample_log2=0, n_active=None):
     scene = tuple(p.detach() for p in params)
     st = R.forward(scene, view, rc, gauss_mask=gauss_mask, pixel_mask=pixel_mask,
                    sample_log2=sample_log2)
-    gc, gd = l1_grads(st.color, st.depth, tc, td, pixel_mask)
+    gc, gd = l1_grads(st.color, st.depth, tc, td, pixel_mask, n_active)
     g = R.backward(scene, view, rc, st, gc, gd, pose=False, map_grads=True, cov3d=cov3d,
                    gauss_mask=gauss_mask, pixel_mask=pixel_mask)
     opt.step(R.handle, [g[k] for k in ("means", "log_scales", "quats", "opacity_logits",
@@ -191,25 +187,28 @@ def as_written_variant(R, params, view, rc, opt, tc, td, iters=60):
     gmask = torch.zeros(n, dtype=torch.uint8, device="cuda")
     newmask = torch.empty_like(gmask)
     n_masked = torch.zeros(1, dtype=torch.int32, device="cuda")
-    # warm-up of the masked path (first use of its torch kernels)
+    n_act = torch.zeros(1, dtype=torch.int32, device="cuda")
+    # warm-up of the masked path (first use of its kernels)
     st, g = mapping_step(R, params, view, rc, opt, tc, td, cov3d=True)
-    rtgs.downsample_mask(st.final_T, 2, pmask)
-    mapping_step(R, params, view, rc, opt, tc, td, pixel_mask=pmask, sample_log2=2)
+    rtgs.downsample_mask(st.final_T, 2, pmask, n_act)
+    mapping_step(R, params, view, rc, opt, tc, td, pixel_mask=pmask, sample_log2=2,
+                 n_active=n_act)
     rtgs.prune_by_grad(R.handle, g["means"], g["cov3d"], st.visible, gmask, 0.8, 0.5, newmask,
                        n_masked)
     mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=newmask, pixel_mask=pmask,
-                 sample_log2=2)
+                 sample_log2=2, n_active=n_act)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     st, _ = mapping_step(R, params, view, rc, opt, tc, td)
-    rtgs.downsample_mask(st.final_T, 2, pmask)
+    rtgs.downsample_mask(st.final_T, 2, pmask, n_act)
     use_gmask = None
     for it in range(2, iters + 1):
         st, g = mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=use_gmask,
-                             pixel_mask=pmask, cov3d=(it == 30), sample_log2=2)
+                             pixel_mask=pmask, cov3d=(it == 30), sample_log2=2,
+                             n_active=n_act)
         if it == 30:
             rtgs.prune_by_grad(R.handle, g["means"], g["cov3d"], st.visible, gmask, 0.8, 0.5,
                                newmask, n_masked)
@@ -220,7 +219,7 @@ def as_written_variant(R, params, view, rc, opt, tc, td, iters=60):
     return {"iters": iters, "ms_per_iter": e0.elapsed_time(e1) / iters,
             "iters_per_s": 1000.0 * iters / e0.elapsed_time(e1),
             "wall_ms_per_iter": 1000 * (time.perf_counter() - t0) / iters,
-            "pruned": int(n_masked.item()), "active_pixels": int(pmask.sum().item())}
+            "pruned": int(n_masked.item()), "active_pixels": int(n_act.item())}
 
 
 def cpu_baseline(sc, cam, sample=192, seed=5):

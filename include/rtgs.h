@@ -224,6 +224,24 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* sessions,
                            int64_t pair_capacity, int32_t grad_flags,
                            void* stream);
 
+/* Gradient of the tracking / mapping loss (Eq. 6, reading: L1 colour plus
+ * w_depth times L1 depth, each a mean over the active pixels) with respect
+ * to the rendered frame:
+ *   dL/dC[c][p] = w_color * m_p * sign(C - C^) / (3 N)
+ *   dL/dD[p]    = w_depth * m_p * sign(D - D^) / N,     sign(0) = 0,
+ * m_p = pixel_mask[p] != 0 (1 when pixel_mask is NULL); N = *n_active_dev
+ * (a device int32, e.g. the count downsample_mask writes; values below 1
+ * count as 1), or W * H when n_active_dev is NULL.  All arrays are device
+ * arrays: colours [3][H][W], depths and mask [H][W]; outputs overwritten.
+ * Errors: INVALID_ARG (null array, W or H <= 0, a mask without n_active_dev,
+ * weights not finite), HIP. */
+int32_t loss_l1_grad(const float* color, const float* depth,
+                     const float* target_color, const float* target_depth,
+                     const uint8_t* pixel_mask, const int32_t* n_active_dev,
+                     int32_t width, int32_t height, float w_color,
+                     float w_depth, float* dL_dcolor, float* dL_ddepth,
+                     void* stream);
+
 /* Parameter update of the mapping stage: the Gaussian gradients of Step 5
  * update the 3D Gaussian parameters (Sec. 3.1).  The paper names no
  * optimiser; this is Adam without weight decay.  For each group (a HOST

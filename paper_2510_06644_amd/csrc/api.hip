@@ -641,6 +641,26 @@ int32_t adam_step(rtgs_handle_t h, const rtgs_adam_group* groups, int32_t n_grou
   return RTGS_OK;
 }
 
+int32_t loss_l1_grad(const float* color, const float* depth, const float* target_color,
+                     const float* target_depth, const uint8_t* pixel_mask,
+                     const int32_t* n_active_dev, int32_t width, int32_t height,
+                     float w_color, float w_depth, float* dL_dcolor, float* dL_ddepth,
+                     void* stream) {
+  if (width <= 0 || height <= 0)
+    return fail(RTGS_ERR_INVALID_ARG, "image %d x %d", width, height);
+  if (!color || !depth || !target_color || !target_depth || !dL_dcolor || !dL_ddepth)
+    return fail(RTGS_ERR_INVALID_ARG, "null image or gradient");
+  if (pixel_mask && !n_active_dev)
+    return fail(RTGS_ERR_INVALID_ARG, "a pixel mask needs its active-pixel count");
+  if (!std::isfinite(w_color) || !std::isfinite(w_depth))
+    return fail(RTGS_ERR_INVALID_ARG, "weights must be finite");
+  LossArgs a{color, depth, target_color, target_depth, pixel_mask, n_active_dev,
+             dL_dcolor, dL_ddepth, width, height, w_color, w_depth};
+  hipError_t e = launch_l1_grad(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "loss_l1_grad launch");
+  return RTGS_OK;
+}
+
 int32_t rtgs_downsample_log2_ratio(int32_t is_keyframe, int32_t n, int32_t k, int32_t m) {
   if (is_keyframe) return 0;
   if (n <= k || m < 2)

@@ -105,6 +105,8 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
                              [](const SessionDev& x) { return x.block_base; });
   const SessionDev& S = B.sess[s];
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
+  // the call's counters start at zero (the binning passes run after this kernel)
+  if (blockIdx.x == 0 && threadIdx.x < 8) W.counters[threadIdx.x] = 0;
   if (li >= S.n) return;
   const int gid = S.gauss_base + li;
   float vm[12];
@@ -579,7 +581,8 @@ __global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
                                hipStream_t st, StageTimer* tm) {
   const size_t lds = sizeof(uint32_t) * (size_t)(b.t_max > 0 ? b.t_max : 1);
-  {
+  if (b.b_total <= 0) {
+    // no Gaussians: k_preprocess (which zeroes the counters) does not run
     Scope sc(tm, kStInit, st);
     k_init<<<1, 64, 0, st>>>(w.counters);
   }

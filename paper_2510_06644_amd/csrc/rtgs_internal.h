@@ -218,6 +218,20 @@ struct AdamArgs {
   float beta1, beta2, omb1, omb2, eps;   // omb = 1 - beta, rounded once from double
 };
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st, StageTimer* tm);
+
+struct LossArgs {
+  const float* color;     // [3][H][W]
+  const float* depth;     // [H][W]
+  const float* t_color;
+  const float* t_depth;
+  const uint8_t* mask;    // [H][W] or null
+  const int32_t* n_active;  // device count of active pixels, or null (H * W)
+  float* g_color;
+  float* g_depth;
+  int32_t w, h;
+  float w_color, w_depth;
+};
+hipError_t launch_l1_grad(const LossArgs& a, hipStream_t st);
 constexpr int kAdamPerThread = 4;
 
 constexpr int kPruneScratchWords = 4096;

@@ -46,7 +46,7 @@ EXPORTS = (
     "rtgs_workspace_size_batched", "render_fwd", "render_bwd", "render_fwd_batched",
     "render_bwd_batched", "prune_by_grad", "downsample_mask", "rtgs_downsample_log2_ratio",
     "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum", "rtgs_profile_enable",
-    "rtgs_profile_read", "adam_step",
+    "rtgs_profile_read", "adam_step", "loss_l1_grad",
 )
 
 vp = ctypes.c_void_p
@@ -116,6 +116,7 @@ def lib():
                                              i32, vp]
             L.prune_by_grad.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp]
             L.downsample_mask.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+            L.loss_l1_grad.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp]
             L.adam_step.argtypes = [vp, ctypes.POINTER(CAdamGroup), i32, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, vp]
             L.rtgs_downsample_log2_ratio.argtypes = [i32, i32, i32, i32]
@@ -306,6 +307,20 @@ def prune_by_grad(handle, g_means, g_cov3d, visible, mask_in, lam, max_ratio, ma
     _check(lib().prune_by_grad(handle.ptr, _p(g_means), _p(g_cov3d), _p(visible), _p(mask_in),
                                n, float(lam), float(max_ratio), _p(mask_out), _p(n_masked),
                                _p(score_out), _stream(stream)))
+
+
+def loss_l1_grad(color, depth, target_color, target_depth, dL_dcolor, dL_ddepth,
+                 pixel_mask=None, n_active=None, w_color=1.0, w_depth=0.5, stream=None):
+    """dL/dC and dL/dD of the L1 colour + w_depth L1 depth loss (means over
+    the active pixels); n_active is a device int32 count (required with a
+    mask)."""
+    _, h, w = color.shape
+    for t, shp in ((color, (3, h, w)), (target_color, (3, h, w)), (dL_dcolor, (3, h, w)),
+                   (depth, (h, w)), (target_depth, (h, w)), (dL_ddepth, (h, w))):
+        _f32(t, shp)
+    _check(lib().loss_l1_grad(_p(color), _p(depth), _p(target_color), _p(target_depth),
+                              _p(pixel_mask), _p(n_active), w, h, float(w_color), float(w_depth),
+                              _p(dL_dcolor), _p(dL_ddepth), _stream(stream)))
 
 
 def adam_step(handle, groups, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

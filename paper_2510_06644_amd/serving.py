@@ -442,7 +442,8 @@ class GpuExecutor:
                      last_idx=torch.empty(spec.height, spec.width, dtype=torch.int32,
                                           device=self.dev)),
             gpose=torch.zeros(6, device=self.dev),
-            pmask=torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev))
+            pmask=torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev),
+            pcount=torch.zeros(1, dtype=torch.int32, device=self.dev))
         torch.cuda.synchronize(self.dev)
 
     def close_session(self, s):
@@ -452,7 +453,7 @@ class GpuExecutor:
             return
         S["params"] = [p.cpu() for p in S["params"]]
         S["opt"].to("cpu").rebind(S["params"])
-        for k in ("viewmat", "m", "v", "gpose", "pmask"):
+        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount"):
             S[k] = S[k].cpu()
         S["targets"] = [(c.cpu(), d.cpu()) for c, d in S["targets"]]
         S["out"] = {k: v.cpu() for k, v in S["out"].items()}
@@ -464,7 +465,7 @@ class GpuExecutor:
         S = self.sessions[s]
         S["params"] = [p.to(self.dev) for p in S["params"]]
         S["opt"].to(self.dev).rebind(S["params"])
-        for k in ("viewmat", "m", "v", "gpose", "pmask"):
+        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount"):
             S[k] = S[k].to(self.dev)
         S["targets"] = [(c.to(self.dev), d.to(self.dev)) for c, d in S["targets"]]
         S["out"] = {k: v.to(self.dev) for k, v in S["out"].items()}
@@ -476,7 +477,7 @@ class GpuExecutor:
         f.target = S["targets"][f.index % self.n_targets]
         f.mask = None
         if f.log2_ratio > 0 and S["last_T"] is not None:
-            self.rtgs.downsample_mask(S["last_T"], f.log2_ratio, S["pmask"])
+            self.rtgs.downsample_mask(S["last_T"], f.log2_ratio, S["pmask"], S["pcount"])
             f.mask = S["pmask"]
 
     def finish_frame(self, f, spec):
@@ -504,19 +505,13 @@ class GpuExecutor:
                          dtype=torch.uint8, device=self.dev)
         rtgs.render_fwd_batched(self.handle, items, ws, cap)
         # L1 colour + 0.5 L1 depth over the active pixels of each frame
-        cs = [it["color"] for it in items]
-        ds = [it["depth"] for it in items]
-        tcs = [f.target[0] for f in frames]
-        tds = [f.target[1] for f in frames]
-        gcs = torch._foreach_sign(torch._foreach_sub(cs, tcs))
-        gds = torch._foreach_sign(torch._foreach_sub(ds, tds))
-        for f, gc, gd, it in zip(frames, gcs, gds, items):
-            npx = float(it["cam"].width * it["cam"].height) / (2 ** f.log2_ratio)
-            gc.mul_(1.0 / (3 * npx))
-            gd.mul_(0.5 / npx)
-            if f.mask is not None:
-                gc.mul_(f.mask)
-                gd.mul_(f.mask)
+        for f, it in zip(frames, items):
+            S = self.sessions[f.session]
+            gc = torch.empty_like(it["color"])
+            gd = torch.empty_like(it["depth"])
+            rtgs.loss_l1_grad(it["color"], it["depth"], f.target[0], f.target[1], gc, gd,
+                              pixel_mask=f.mask,
+                              n_active=S["pcount"] if f.mask is not None else None)
             it["dL_dcolor"] = gc
             it["dL_ddepth"] = gd
         if phase == "track":
