@@ -39,11 +39,25 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.f;
   if (gid < B.n_total) {
-    const int64_t first = W.goff[gid], n = W.cnt[gid];
-    for (int64_t k = sub; k < n && first + k < W.cap; k += 16) {
-      const float* p = W.partial + (first + k) * NV;
+    const int64_t first = W.goff[gid];
+    // slots past the pair capacity were never written
+    const int64_t n = min((int64_t)W.cnt[gid], W.cap - first);
+    // lane sub adds slots sub, sub + 16, sub + 32, ... in that order; four
+    // slots are loaded per round so that a Gaussian touching hundreds of
+    // tiles does not serialise on one load at a time
+    for (int64_t k0 = sub; k0 < n; k0 += 64) {
+      float v[4][NV];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) acc[i] += p[i];
+      for (int j = 0; j < 4; ++j) {
+        const int64_t k = k0 + 16 * j;
+        const float* p = W.partial + (first + k) * NV;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[j][i] = k < n ? p[i] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += v[j][i];
     }
   }
 #pragma unroll

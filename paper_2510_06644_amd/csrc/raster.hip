@@ -172,18 +172,16 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     const int cnt = min(kBlock, end - b0);
     for (int q = 0; q < kBlock / 64; ++q) {
       unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
-      while (m) {
-        if (__ballot(!done) == 0) break;               // the whole wave has stopped
-        const int k = 64 * q + __builtin_ctzll(m);
-        m &= m - 1;
-        // every lane evaluates the entry; the decisions below are selects,
-        // not branches: skip (alpha < 1/255), stop (T would fall below
-        // 1e-4; the fragment is excluded) or blend
+      // every lane evaluates each entry; the decisions are selects, not
+      // branches: skip (alpha < 1/255), stop (T would fall below 1e-4; the
+      // fragment is excluded) or blend
+      auto step = [&](int k) {
         const Frag f = frag_alpha(s_r0[k], s_r1[k], pxf, pyf);
         const float tn = T * f.om;
         const bool hit = !done && !(f.alpha < kAlphaMin);
-        const bool stop_here = hit && tn < kTMin;
-        const bool blend = hit && !(tn < kTMin);
+        const bool low = tn < kTMin;
+        const bool stop_here = hit && low;
+        const bool blend = hit && !low;
         done = done || stop_here;
         if (STATS) stop = stop_here ? b0 + k : stop;
         const float w = blend ? f.alpha * T : 0.f;       // adds exactly 0 otherwise
@@ -195,6 +193,15 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         T = blend ? tn : T;
         last = blend ? b0 + k : last;
         if (STATS) nblend += blend ? 1 : 0;
+      };
+      while (m) {
+        if (__ballot(!done) == 0) break;               // the whole wave has stopped
+        step(64 * q + __builtin_ctzll(m));
+        m &= m - 1;
+        if (m) {                                       // two entries per check
+          step(64 * q + __builtin_ctzll(m));
+          m &= m - 1;
+        }
       }
     }
     __syncthreads();

@@ -354,7 +354,8 @@ __device__ __forceinline__ Frag frag_alpha(float4 r0, float4 k, float px, float 
   f.alpha = fminf(kAlphaMax, raw);
   // 1 - alpha without rounding o e first: near-opaque fragments (alpha close
   // to 0.99) would otherwise lose digits of the transmittance they leave
-  f.om = raw > kAlphaMax ? 1.f - kAlphaMax : __builtin_fmaf(-k.w, f.e, 1.f);
+  // (clamped: 1 - o e < 1 - 0.99, so the max gives 1 - 0.99 up to one rounding)
+  f.om = fmaxf(1.f - kAlphaMax, __builtin_fmaf(-k.w, f.e, 1.f));
   return f;
 }
 
