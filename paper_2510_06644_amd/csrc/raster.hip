@@ -319,14 +319,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
     __syncthreads();
     for (int q = kBwdBatch / 64 - 1; q >= 0; --q) {
       unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
-      while (m) {
-        const int bit = 63 - __builtin_clzll(m);       // descending list order
-        m &= ~(1ull << bit);
-        const int k = 64 * q + bit;
+      auto step = [&](int k) {
         const float4 k4 = s_r1[k];
         const Frag f = frag_alpha(s_r0[k], k4, pxf, pyf);
         const bool contrib = k <= lrel && !(f.alpha < kAlphaMin);
-        if (__ballot(contrib) == 0) continue;          // no lane blended this entry
+        if (__ballot(contrib) == 0) return;            // no lane blended this entry
         // lanes that did not blend it take alpha = 0 and 1 - alpha = 1, so
         // every update below leaves their state unchanged and their
         // gradients exactly zero (selects, not branches)
@@ -348,18 +345,18 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
         // the clamp alpha = 0.99 has no gradient to o or to the power
         const bool live = contrib && !(k4.w * f.e > kAlphaMax);
         const float ng = live ? -(f.alpha * dla) : 0.f;  // -dL/dpower
-        const float p = ng * f.dx, q = ng * f.dy;
+        const float pg = ng * f.dx, qg = ng * f.dy;
         // summed over the tile's pixels, these give the 2D gradients once
         // the Gaussian's conic is applied (epilogue)
         float v[NV];
-        v[0] = p;
-        v[1] = q;
-        v[2] = p * f.dx;
-        v[3] = p * f.dy;
-        v[4] = q * f.dy;
+        v[0] = pg;
+        v[1] = qg;
+        v[2] = pg * f.dx;
+        v[3] = pg * f.dy;
+        v[4] = qg * f.dy;
         v[NV - 1] = w * gD;                               // depth slot (last)
         if (NV == 10) {
-          v[5] = live ? f.e * dla : 0.f;                  // dL/do
+          v[5] = ng;                                      // o dL/do (epilogue)
           v[6] = w * g0;
           v[7] = w * g1;
           v[8] = w * g2;
@@ -372,6 +369,18 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
           for (int j = 0; j < 3; ++j)
             if ((row & 1) + 2 * j < NV / 2)
               part[k * kStride + wave_scatter_index(NV, row, j)] = x[j];
+        }
+      };
+      while (m) {
+        // descending list order, two entries per iteration (their alpha
+        // evaluations are independent and can overlap)
+        const int b1 = 63 - __builtin_clzll(m);
+        m &= ~(1ull << b1);
+        step(64 * q + b1);
+        if (m) {
+          const int b2 = 63 - __builtin_clzll(m);
+          m &= ~(1ull << b2);
+          step(64 * q + b2);
         }
       }
     }
@@ -396,8 +405,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
         dst[2] = 0.5f * t[2];
         dst[3] = t[3];
         dst[4] = 0.5f * t[4];
+        // alpha = o e below the clamp, so dalpha/do = e = alpha / o and
+        // dL/do = sum alpha dL/dalpha / o = -(sum of -dL/dpower) / o
+        if (NV == 10) dst[5] = -t[5] / cn.w;
 #pragma unroll
-        for (int i = 5; i < NV; ++i) dst[i] = t[i];
+        for (int i = NV == 10 ? 6 : 5; i < NV; ++i) dst[i] = t[i];
       }
     }
   }
