@@ -222,6 +222,54 @@ def as_written_variant(R, params, view, rc, opt, tc, td, iters=60):
             "pruned": int(n_masked.item()), "active_pixels": int(n_act.item())}
 
 
+def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3):
+    """Tracking at 640x480 with 100k Gaussians: the map frozen, the camera
+    starting 2 cm / 1 degree off the pose its target frame was rendered
+    from; each iteration is render_fwd, the loss gradient, render_bwd to the
+    pose only and pose_update (Adam on xi, then T <- Exp(-step) T)."""
+    import torch
+    from paper_2510_06644_amd import pose, rtgs, synth
+    spec = synth.CONFIGS["c1"]
+    cam = synth.make_camera(spec.width, spec.height)
+    sc = synth.make_scene(spec, cam)
+    scene = tuple(torch.from_numpy(a).cuda() for a in sc.arrays())
+    rc = rtgs.Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+    R = rtgs.Renderer(0, check="deferred")
+    eye = torch.eye(3, 4, dtype=torch.float32, device="cuda").contiguous()
+    tc, td = render_target(R, scene, eye, rc, spec.seed)
+    xi0 = torch.tensor(synth.pose_offset(51, 0.02, 1.0), dtype=torch.float64, device="cuda")
+    start = pose.apply_left(xi0, eye).contiguous()
+
+    def err(vm):
+        v = vm.double().cpu()
+        t = float(v[:, 3].norm()) * 100.0
+        c = float(((v[:, :3].trace() - 1.0) / 2.0).clamp(-1.0, 1.0))
+        return {"t_cm": t, "r_deg": float(np.degrees(np.arccos(c)))}
+
+    def run(view, n):
+        m = torch.zeros(6, device="cuda")
+        v = torch.zeros(6, device="cuda")
+        for it in range(1, n + 1):
+            st = R.forward(scene, view, rc)
+            gc, gd = l1_grads(st.color, st.depth, tc, td)
+            g = R.backward(scene, view, rc, st, gc, gd, pose=True, map_grads=False)
+            rtgs.pose_update([(view, g["pose"], m, v, lr_rho, lr_phi, it)])
+
+    run(start.clone(), 3)                      # warm-up (first launches)
+    view = start.clone()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run(view, iters)
+    e1.record()
+    torch.cuda.synchronize()
+    R.verify()
+    ms = e0.elapsed_time(e1) / iters
+    return {"workload": "640x480_100k_tracking", "iters": iters, "ms_per_iter": ms,
+            "iters_per_s": 1000.0 / ms, "pose_err_start": err(start), "pose_err_end": err(view)}
+
+
 def cpu_baseline(sc, cam, sample=192, seed=5):
     """The float64 oracle, fwd + bwd to every parameter and the pose, on a
     random sample of pixels of the same frame, scaled to a full frame."""
@@ -247,7 +295,7 @@ def cpu_baseline(sc, cam, sample=192, seed=5):
 
 
 def serving_run(seconds, warmup_s, downsample, mode, seed=4242, rate=30.0):
-    """The 16-session serving mix on a Poisson trace (30 Hz per session)."""
+    """The 16-session serving mix on a Poisson trace (rate Hz per session)."""
     from paper_2510_06644_amd import serving
     specs = serving.serving_mix()
     ex = serving.GpuExecutor(0)
@@ -257,6 +305,7 @@ def serving_run(seconds, warmup_s, downsample, mode, seed=4242, rate=30.0):
     ex.warmup(specs, iters=1)
     trace = serving.poisson_trace(len(specs), rate, seconds, seed)
     rep = eng.run(trace, warmup_s=warmup_s)
+    rep["sessions"] = len(specs)
     ex.verify()
     rep["mode"] = mode
     rep["downsample"] = downsample
@@ -340,6 +389,8 @@ def main():
             mapping_step(R2, params2, view2, rc2, opt2, tc2, td2)
         R2.cap = R.cap
         variant = as_written_variant(R2, params2, view2, rc2, opt2, tc2, td2)
+    log("tracking 640x480 / 100k")
+    tracking = tracking_run()
     serve = None
     if args.serve_seconds > 0:
         serve = {}
@@ -348,6 +399,15 @@ def main():
             key = f"{mode}{'_downsampled' if ds else '_full_res'}"
             serve[key] = serving_run(args.serve_seconds, min(0.5, args.serve_seconds / 4), ds,
                                      mode)
+        # the same mix offered at 60% of the frame rate the batched engine
+        # sustained above: latency without queue growth
+        sat = serve["batched_downsampled"]
+        rate = 0.6 * sat["frames"] / sat["span_s"] / sat["sessions"]
+        log(f"serving batched downsample=True at {rate:.1f} Hz per session")
+        rep = serving_run(args.serve_seconds, min(0.5, args.serve_seconds / 4), True, "batched",
+                          rate=rate)
+        rep["rate_hz_per_session"] = rate
+        serve["batched_downsampled_60pct_load"] = rep
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -377,6 +437,7 @@ def main():
         "work": cnt,
         "host_wall_ms_per_step": 1000.0 * wall_ms,
         "as_written": variant,
+        "tracking": tracking,
         "serving": serve,
         "cpu_baseline": cpu,
     }

@@ -272,6 +272,31 @@ int32_t adam_step(rtgs_handle_t h, const rtgs_adam_group* groups,
                   int32_t n_groups, double beta1, double beta2, double eps,
                   void* stream);
 
+/* Pose update of the tracking stage (Sec. 3.1: tracking updates the camera
+ * pose; Step 5 gives dL/dP).  For each item (a HOST array of n; every
+ * pointer is a device float array): Adam on the left-perturbation tangent
+ * xi = (rho, phi) at xi = 0 with the gradient g_pose6 (as render_bwd writes
+ * it),
+ *   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+ *   s_i = lr_i (m_i / (1 - beta1^step)) / (sqrt(v_i / (1 - beta2^step)) + eps)
+ * (lr_i = lr_rho for rho, lr_phi for phi), then the re-linearisation
+ *   viewmat <- Exp(-s) viewmat
+ * (xi returns to zero).  Arithmetic in float64; viewmat [12] row-major 3x4,
+ * exp_avg / exp_avg_sq [6] updated in place.  step (>= 1) counts this
+ * update.  One launch per 48 items.  Errors: INVALID_ARG, HIP. */
+typedef struct rtgs_pose_item {
+  float* viewmat;
+  const float* g_pose6;
+  float* exp_avg;
+  float* exp_avg_sq;
+  float lr_rho;
+  float lr_phi;
+  int32_t step;
+} rtgs_pose_item;
+
+int32_t pose_update(const rtgs_pose_item* items, int32_t n, double beta1,
+                    double beta2, double eps, void* stream);
+
 /* Adaptive Gaussian pruning, the mask step (Sec. 4.1, Eq. 7):
  * score_k = ||dL/dmu_k||_2 + lambda * ||dL/dSigma_k||_F (Frobenius over the
  * nine entries of the symmetric gradient); among the V Gaussians with

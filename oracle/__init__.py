@@ -33,4 +33,4 @@ from .render import render, render_with_grads, RenderOut, Grads  # noqa: F401
 from .binning import tile_lists  # noqa: F401
 from .selection import importance_score, prune_select, downsample_log2_ratio, downsample_select  # noqa: F401
 from .loss import l1_loss_grads  # noqa: F401
-from .optim import adam_step  # noqa: F401
+from .optim import adam_step, pose_update  # noqa: F401

@@ -661,6 +661,45 @@ int32_t loss_l1_grad(const float* color, const float* depth, const float* target
   return RTGS_OK;
 }
 
+int32_t pose_update(const rtgs_pose_item* items, int32_t n, double beta1, double beta2,
+                    double eps, void* stream) {
+  if (n < 0 || (n > 0 && !items)) return fail(RTGS_ERR_INVALID_ARG, "bad item list (n = %d)", n);
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
+    return fail(RTGS_ERR_INVALID_ARG, "betas (%g, %g) outside [0, 1)", beta1, beta2);
+  if (!(eps >= 0.0) || !std::isfinite(eps))
+    return fail(RTGS_ERR_INVALID_ARG, "eps %g must be finite and >= 0", eps);
+  for (int i = 0; i < n; ++i) {
+    const rtgs_pose_item& it = items[i];
+    if (!it.viewmat || !it.g_pose6 || !it.exp_avg || !it.exp_avg_sq)
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: null array", i);
+    if (it.step < 1) return fail(RTGS_ERR_INVALID_ARG, "item %d: step %d < 1", i, it.step);
+    if (!std::isfinite(it.lr_rho) || !std::isfinite(it.lr_phi))
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: learning rate not finite", i);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int first = 0; first < n; first += kPoseMaxItems) {
+    PoseArgs a{};
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    for (int i = first; i < n && i < first + kPoseMaxItems; ++i) {
+      const rtgs_pose_item& it = items[i];
+      PoseItemDev& d = a.item[a.n++];
+      d.viewmat = it.viewmat;
+      d.g_pose6 = it.g_pose6;
+      d.exp_avg = it.exp_avg;
+      d.exp_avg_sq = it.exp_avg_sq;
+      d.lr_rho = it.lr_rho;
+      d.lr_phi = it.lr_phi;
+      d.bc1 = 1.0 - std::pow(beta1, (double)it.step);
+      d.bc2 = 1.0 - std::pow(beta2, (double)it.step);
+    }
+    hipError_t e = launch_pose_update(a, st);
+    if (e != hipSuccess) return hip_fail(e, "pose_update launch");
+  }
+  return RTGS_OK;
+}
+
 int32_t rtgs_downsample_log2_ratio(int32_t is_keyframe, int32_t n, int32_t k, int32_t m) {
   if (is_keyframe) return 0;
   if (n <= k || m < 2)

@@ -232,6 +232,23 @@ struct LossArgs {
   float w_color, w_depth;
 };
 hipError_t launch_l1_grad(const LossArgs& a, hipStream_t st);
+
+// Pose update of up to kPoseMaxItems sessions in one launch.
+constexpr int kPoseMaxItems = 48;
+struct PoseItemDev {
+  float* viewmat;         // [12] row-major 3x4, updated in place
+  const float* g_pose6;   // [6] dL/d(rho, phi)
+  float* exp_avg;         // [6]
+  float* exp_avg_sq;      // [6]
+  double lr_rho, lr_phi;
+  double bc1, bc2;        // 1 - beta1^t, 1 - beta2^t
+};
+struct PoseArgs {
+  PoseItemDev item[kPoseMaxItems];
+  int32_t n;
+  double beta1, beta2, eps;
+};
+hipError_t launch_pose_update(const PoseArgs& a, hipStream_t st);
 constexpr int kAdamPerThread = 4;
 
 constexpr int kPruneScratchWords = 4096;

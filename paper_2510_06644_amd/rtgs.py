@@ -46,7 +46,7 @@ EXPORTS = (
     "rtgs_workspace_size_batched", "render_fwd", "render_bwd", "render_fwd_batched",
     "render_bwd_batched", "prune_by_grad", "downsample_mask", "rtgs_downsample_log2_ratio",
     "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum", "rtgs_profile_enable",
-    "rtgs_profile_read", "adam_step", "loss_l1_grad",
+    "rtgs_profile_read", "adam_step", "loss_l1_grad", "pose_update",
 )
 
 vp = ctypes.c_void_p
@@ -73,6 +73,11 @@ class CSession(ctypes.Structure):
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
                 ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_viewmat", vp),
                 ("g_cov3d", vp)]
+
+
+class CPoseItem(ctypes.Structure):
+    _fields_ = [("viewmat", vp), ("g_pose6", vp), ("exp_avg", vp), ("exp_avg_sq", vp),
+                ("lr_rho", f32), ("lr_phi", f32), ("step", i32)]
 
 
 class CAdamGroup(ctypes.Structure):
@@ -116,6 +121,8 @@ def lib():
                                              i32, vp]
             L.prune_by_grad.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp]
             L.downsample_mask.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+            L.pose_update.argtypes = [ctypes.POINTER(CPoseItem), i32, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, vp]
             L.loss_l1_grad.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp]
             L.adam_step.argtypes = [vp, ctypes.POINTER(CAdamGroup), i32, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, vp]
@@ -307,6 +314,21 @@ def prune_by_grad(handle, g_means, g_cov3d, visible, mask_in, lam, max_ratio, ma
     _check(lib().prune_by_grad(handle.ptr, _p(g_means), _p(g_cov3d), _p(visible), _p(mask_in),
                                n, float(lam), float(max_ratio), _p(mask_out), _p(n_masked),
                                _p(score_out), _stream(stream)))
+
+
+def pose_update(items, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """items: iterable of (viewmat [3,4], g_pose6 [6], exp_avg [6], exp_avg_sq [6],
+    lr_rho, lr_phi, step); Adam on xi then viewmat <- Exp(-step) viewmat, in
+    place on the device."""
+    items = list(items)
+    arr = (CPoseItem * max(len(items), 1))()
+    for k, (vm, g, m, v, lr_rho, lr_phi, step) in enumerate(items):
+        _f32(vm, (3, 4), "viewmat")
+        for t in (g, m, v):
+            _f32(t, (6,), "pose vector")
+        arr[k] = CPoseItem(_p(vm), _p(g), _p(m), _p(v), float(lr_rho), float(lr_phi), int(step))
+    _check(lib().pose_update(arr, len(items), float(beta1), float(beta2), float(eps),
+                             _stream(stream)))
 
 
 def loss_l1_grad(color, depth, target_color, target_depth, dL_dcolor, dL_ddepth,

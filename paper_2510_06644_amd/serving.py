@@ -537,25 +537,15 @@ class GpuExecutor:
         return ev
 
     def _pose_step(self, frames, b1=0.9, b2=0.999, eps=1e-8):
-        """Adam on xi = (rho, phi) for every session of the group, vectorised,
-        then re-linearisation T <- Exp(-step) T (xi back to zero)."""
-        torch = self.torch
-        from .pose import apply_left
-        ss = [self.sessions[f.session] for f in frames]
-        g = torch.stack([S["gpose"] for S in ss])
-        m = torch.stack([S["m"] for S in ss])
-        v = torch.stack([S["v"] for S in ss])
-        t = torch.tensor([S["t"] + 1 for S in ss], dtype=torch.float32, device=self.dev)[:, None]
-        m = b1 * m + (1 - b1) * g
-        v = b2 * v + (1 - b2) * g * g
-        lr = torch.tensor([self.lr_rho] * 3 + [self.lr_phi] * 3, device=self.dev)
-        upd = lr * (m / (1 - b1 ** t)) / (torch.sqrt(v / (1 - b2 ** t)) + eps)
-        vm = torch.stack([S["viewmat"] for S in ss])
-        new = apply_left(-upd.double(), vm)
-        for k, S in enumerate(ss):
-            S["m"], S["v"] = m[k], v[k]
+        """Adam on xi = (rho, phi) for every session of the group, then the
+        re-linearisation T <- Exp(-step) T: one pose_update launch."""
+        items = []
+        for f in frames:
+            S = self.sessions[f.session]
             S["t"] += 1
-            S["viewmat"].copy_(new[k])
+            items.append((S["viewmat"], S["gpose"], S["m"], S["v"], self.lr_rho, self.lr_phi,
+                          S["t"]))
+        self.rtgs.pose_update(items, b1, b2, eps)
 
     # ---- clock ----------------------------------------------------------------
     def clock(self):

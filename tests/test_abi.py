@@ -80,3 +80,8 @@ def test_null_handle_and_bad_arguments_are_rejected_before_any_gpu_work():
     st = ctypes.c_int32()
     assert L.rtgs_query(None, 1, ctypes.byref(pairs), ctypes.byref(st)) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.rtgs_selftest_wave_sum(None, None, -1, None) == rtgs.RTGS_ERR_INVALID_ARG
+    assert L.pose_update(None, -1, 0.9, 0.999, 1e-8, None) == rtgs.RTGS_ERR_INVALID_ARG
+    assert L.pose_update(None, 0, 1.5, 0.999, 1e-8, None) == rtgs.RTGS_ERR_INVALID_ARG
+    assert L.adam_step(None, None, 0, 0.9, 0.999, 1e-8, None) == rtgs.RTGS_ERR_INVALID_ARG
+    assert L.loss_l1_grad(None, None, None, None, None, None, 0, 4, 1.0, 0.5, None, None,
+                          None) == rtgs.RTGS_ERR_INVALID_ARG

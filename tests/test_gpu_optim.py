@@ -1,7 +1,8 @@
-"""Map update on the GPU (adam_step) against the float64 oracle, step by step
-from the same float32 state: tensor sizes with ragged tails, a tensor whose
-start is not 16-byte aligned (element-wise path), an empty tensor, and more
-than one launch's worth of tensors."""
+"""Map and pose updates on the GPU against the float64 oracle, step by step
+from the same float32 state.  adam_step: tensor sizes with ragged tails, a
+tensor whose start is not 16-byte aligned (element-wise path), an empty
+tensor, and more than one launch's worth of tensors.  pose_update: 53
+sessions (two launches), four steps."""
 import numpy as np
 import pytest
 import torch
@@ -96,3 +97,48 @@ def test_adam_rejects_bad_arguments():
         with pytest.raises(rtgs.RtgsError) as e:
             rtgs.adam_step(h, [(p, p.clone(), p.clone(), p.clone(), 1e-3, t)], **kw)
         assert e.value.code == rtgs.RTGS_ERR_INVALID_ARG
+
+
+def test_pose_update_matches_oracle_over_steps():
+    say("test_pose_update_matches_oracle_over_steps")
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(11)
+    n = 53                                            # more than one launch (48 per launch)
+    vms, gs, ms, vs = [], [], [], []
+    for k in range(n):
+        r = Rotation.from_rotvec(rng.normal(size=3) * 0.5).as_matrix()
+        vms.append(np.concatenate([r, rng.normal(size=(3, 1))], 1).astype(np.float32))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    vm_d = [dev(v) for v in vms]
+    m_d = [torch.zeros(6, device="cuda") for _ in range(n)]
+    v_d = [torch.zeros(6, device="cuda") for _ in range(n)]
+    ref = [(v.astype(np.float64), np.zeros(6), np.zeros(6)) for v in vms]
+    for t in range(1, 5):
+        grads = [rng.normal(size=6) * 10.0 ** rng.integers(-3, 2) for _ in range(n)]
+        g_d = [dev(g) for g in grads]
+        items = [(vm_d[k], g_d[k], m_d[k], v_d[k], 1e-3, 2e-3, t) for k in range(n)]
+        rtgs.pose_update(items)
+        torch.cuda.synchronize()
+        new_ref = []
+        for k in range(n):
+            # the oracle step starts from the kernel's float32 state
+            vm0 = vm_prev[k] if t > 1 else vms[k].astype(np.float64)
+            new_ref.append(oracle.pose_update(vm0, grads[k].astype(np.float32).astype(np.float64),
+                                              m_prev[k] if t > 1 else np.zeros(6),
+                                              v_prev[k] if t > 1 else np.zeros(6), t, 1e-3, 2e-3))
+        vm_prev = [x.cpu().numpy().astype(np.float64) for x in vm_d]
+        m_prev = [x.cpu().numpy().astype(np.float64) for x in m_d]
+        v_prev = [x.cpu().numpy().astype(np.float64) for x in v_d]
+        for k in range(n):
+            np.testing.assert_allclose(vm_prev[k], new_ref[k][0], rtol=0, atol=2e-6)
+            np.testing.assert_allclose(m_prev[k], new_ref[k][1], rtol=1e-6, atol=1e-30)
+            np.testing.assert_allclose(v_prev[k], new_ref[k][2], rtol=1e-6, atol=1e-30)
+
+
+def test_pose_update_rejects_bad_arguments():
+    say("test_pose_update_rejects_bad_arguments")
+    vm = torch.zeros(3, 4, device="cuda")
+    z = torch.zeros(6, device="cuda")
+    with pytest.raises(rtgs.RtgsError) as e:
+        rtgs.pose_update([(vm, z, z.clone(), z.clone(), 1e-3, 1e-3, 0)])
+    assert e.value.code == rtgs.RTGS_ERR_INVALID_ARG

@@ -450,3 +450,26 @@ def test_adam_matches_torch_adam_over_several_steps():
     # torch forms m by lerp: equal up to rounding of a near-cancelling sum
     np.testing.assert_allclose(m, st["exp_avg"].numpy(), rtol=1e-13, atol=1e-15)
     np.testing.assert_allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_pose_update_first_step_closed_forms():
+    # first Adam step: s_i = lr_i g_i / (|g_i| + eps) ~ lr_i sign(g_i)
+    rng = np.random.default_rng(7)
+    r0 = Rotation.from_rotvec(rng.normal(size=3) * 0.3).as_matrix()
+    vm = np.concatenate([r0, rng.normal(size=(3, 1))], 1)
+    # pure translation gradient: R unchanged, t <- t - s_rho
+    g = np.array([0.3, -2.0, 1e-3, 0.0, 0.0, 0.0])
+    new, m, v = oracle.pose_update(vm, g, np.zeros(6), np.zeros(6), 1, 0.01, 0.02, eps=1e-12)
+    s_rho = 0.01 * g[:3] / (np.abs(g[:3]) + 1e-12)
+    np.testing.assert_allclose(new[:, :3], r0, atol=1e-15)
+    np.testing.assert_allclose(new[:, 3], vm[:, 3] - s_rho, atol=1e-14)
+    # pure rotation gradient: R <- Exp(-s_phi) R, t <- Exp(-s_phi) t
+    g = np.array([0.0, 0.0, 0.0, 1.0, -0.5, 0.25])
+    new, _, _ = oracle.pose_update(vm, g, np.zeros(6), np.zeros(6), 1, 0.01, 0.02, eps=1e-12)
+    rs = Rotation.from_rotvec(-0.02 * np.sign(g[3:])).as_matrix()
+    np.testing.assert_allclose(new[:, :3], rs @ r0, atol=1e-12)
+    np.testing.assert_allclose(new[:, 3], rs @ vm[:, 3], atol=1e-12)
+    # zero gradient: nothing moves
+    new, m, v = oracle.pose_update(vm, np.zeros(6), np.zeros(6), np.zeros(6), 3, 0.01, 0.02)
+    np.testing.assert_allclose(new, vm, atol=0)
+    assert not m.any() and not v.any()
