@@ -162,6 +162,17 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
 constexpr int kBinThreads = 1024;
 static_assert(kChunk % kBinThreads == 0, "whole rounds per chunk");
 
+// The chunk's tile rectangles in LDS (one coalesced load per Gaussian), so the
+// pair walk below never waits on a dependent global load.  Visible after the
+// barrier in chunk_offsets.
+__device__ __forceinline__ void stage_rects(const SessionDev& S, const WsPtrs& W, int c,
+                                            int4* s_rect) {
+  for (int i = threadIdx.x; i < kChunk; i += kBinThreads) {
+    const int li = c * kChunk + i;
+    s_rect[i] = li < S.n ? W.rect[S.gauss_base + li] : make_int4(0, 0, -1, -1);
+  }
+}
+
 // In-chunk exclusive offsets of the Gaussians' tile counts, in local index
 // order, into s_off[0..kChunk]; s_off[kChunk] = the chunk's pair total, which
 // is returned.  Local index i = j * kBinThreads + thread for round j.
@@ -195,13 +206,14 @@ __device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, u
 }
 
 // Walk this thread's share of the chunk's pairs: pairs [m0, m1) in
-// Gaussian-major order, m0 = thread * ceil(total / kBinThreads).  One binary search
+// Gaussian-major order, m0 = thread * ceil(total / kBinThreads), with the
+// chunk's tile rectangles staged in LDS (s_rect[i] for local index i).  One binary search
 // finds the first Gaussian; after that the walk steps through tiles of the
 // Gaussian's rectangle row by row and on to the next Gaussian, so pairs are
 // spread evenly however many tiles a Gaussian touches.  f(local index, tile)
 // is called for every pair.
 template <typename F>
-__device__ __forceinline__ void chunk_pairs(const SessionDev& S, const WsPtrs& W, int c,
+__device__ __forceinline__ void chunk_pairs(const SessionDev& S, const int4* s_rect, int c,
                                             const uint32_t* s_off, uint32_t total, F f) {
   const uint32_t per = (total + kBinThreads - 1) / kBinThreads;
   const uint32_t m0 = threadIdx.x * per;
@@ -213,7 +225,7 @@ __device__ __forceinline__ void chunk_pairs(const SessionDev& S, const WsPtrs& W
     if (s_off[mid] <= m0) lo = mid; else hi = mid - 1;
   }
   int i = lo;
-  int4 r = W.rect[S.gauss_base + c * kChunk + i];
+  int4 r = s_rect[i];
   int w = r.z - r.x + 1;
   const int k0 = (int)(m0 - s_off[i]);
   int tx = r.x + k0 % w, ty = r.y + k0 / w;
@@ -221,7 +233,7 @@ __device__ __forceinline__ void chunk_pairs(const SessionDev& S, const WsPtrs& W
     while (m >= s_off[i + 1]) {           // next Gaussian with pairs
       ++i;
       if (m < s_off[i + 1]) {
-        r = W.rect[S.gauss_base + c * kChunk + i];
+        r = s_rect[i];
         w = r.z - r.x + 1;
         tx = r.x;
         ty = r.y;
@@ -240,6 +252,7 @@ __device__ __forceinline__ void chunk_pairs(const SessionDev& S, const WsPtrs& W
 __global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_hist[];
   __shared__ uint32_t s_off[kChunk + 1];
+  __shared__ int4 s_rect[kChunk];
   __shared__ uint32_t s_wave[kBinThreads / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
@@ -247,9 +260,10 @@ __global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
   for (int t = threadIdx.x; t < ts; t += kBinThreads) s_hist[t] = 0u;
+  stage_rects(S, W, c, s_rect);
   const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
   // pairs are dealt evenly over the threads, whatever the Gaussians' sizes
-  chunk_pairs(S, W, c, s_off, total, [&](int, int tile) { atomicAdd(&s_hist[tile], 1u); });
+  chunk_pairs(S, s_rect, c, s_off, total, [&](int, int tile) { atomicAdd(&s_hist[tile], 1u); });
   __syncthreads();
   uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
   for (int t = threadIdx.x; t < ts; t += kBinThreads) h[t] = s_hist[t];
@@ -357,6 +371,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_tot
 __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_cur[];
   __shared__ uint32_t s_off[kChunk + 1];
+  __shared__ int4 s_rect[kChunk];
+  __shared__ uint32_t s_zb[kChunk];
   __shared__ uint32_t s_wave[kBinThreads / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
@@ -365,6 +381,11 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   const int ts = S.tiles_x * S.tiles_y;
   const uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
   for (int t = threadIdx.x; t < ts; t += kBinThreads) s_cur[t] = W.tile_start[S.tile_base + t] + h[t];
+  stage_rects(S, W, c, s_rect);
+  for (int i = threadIdx.x; i < kChunk; i += kBinThreads) {
+    const int li = c * kChunk + i;
+    s_zb[i] = li < S.n ? __float_as_uint(W.rec[S.gauss_base + li].col.w) : 0u;
+  }
   const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
   const uint32_t base = W.chunk_off[blockIdx.x];
   for (int j = 0; j < kChunk / kBinThreads; ++j) {
@@ -374,10 +395,10 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   }
   int cur_i = -1;
   unsigned long long key = 0;
-  chunk_pairs(S, W, c, s_off, total, [&](int i, int tile) {
+  chunk_pairs(S, s_rect, c, s_off, total, [&](int i, int tile) {
     if (i != cur_i) {
       const int gid = S.gauss_base + c * kChunk + i;
-      key = ((unsigned long long)__float_as_uint(W.rec[gid].col.w) << 32) | (unsigned)gid;
+      key = ((unsigned long long)s_zb[i] << 32) | (unsigned)gid;
       cur_i = i;
     }
     const uint32_t pos = atomicAdd(&s_cur[tile], 1u);
