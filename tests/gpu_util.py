@@ -9,7 +9,7 @@ from scipy.spatial.transform import Rotation
 from paper_2510_06644_amd import rtgs, synth
 
 IMG_TOL = 1e-4       # per-element, relative to max(|r|, 1e-2 max|r|)
-GRAD_TOL = 1e-4
+GRAD_TOL = 1e-4      # per-Gaussian gradient vector, relative to max(|r_i|, 1e-2 max_j |r_j|)
 
 
 def say(*a):
@@ -59,6 +59,24 @@ def rel_err(x, r, mask=None, floor_frac=1e-2):
     scale = max(np.abs(r).max(), 1e-30)
     den = np.maximum(np.abs(r), floor_frac * scale)
     return float((np.abs(x - r) / den).max())
+
+
+def grad_err(x, r, floor_frac=1e-2):
+    """Relative error of per-Gaussian gradient vectors: row i of [N, k] is one
+    Gaussian's gradient with respect to one parameter group; its error is
+    |x_i - r_i| / max(|r_i|, floor_frac max_j |r_j|) in the Euclidean norm,
+    and the result is the largest over the rows.  [N] arrays (one scalar per
+    Gaussian) reduce to `rel_err`."""
+    x = np.asarray(x, np.float64)
+    r = np.asarray(r, np.float64)
+    if r.ndim == 1:
+        return rel_err(x, r, floor_frac=floor_frac)
+    x, r = x.reshape(len(r), -1), r.reshape(len(r), -1)
+    if r.size == 0:
+        return 0.0
+    rn = np.linalg.norm(r, axis=1)
+    den = np.maximum(rn, floor_frac * max(rn.max(), 1e-30))
+    return float((np.linalg.norm(x - r, axis=1) / den).max())
 
 
 def norm_err(x, r):

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from paper_2510_06644_amd import autograd, pose, rtgs, synth
-from tests.gpu_util import GRAD_TOL, cam_tuple, eye_view, rcam, rel_err, say
+from tests.gpu_util import GRAD_TOL, cam_tuple, grad_err, eye_view, rcam, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_autograd_matches_oracle_with_pose_off_zero():
     torch.cuda.synchronize()
     _, ref = oracle.render_with_grads(sc.arrays(), vm32, cam_tuple(cam), gc, gd, ga)
     for p, name in zip(params, ("means", "log_scales", "quats", "opacity_logits", "colors")):
-        e = rel_err(p.grad.cpu().numpy(), getattr(ref, name).numpy())
+        e = grad_err(p.grad.cpu().numpy(), getattr(ref, name).numpy())
         say(f"  {name}: {e:.2e}")
         assert e < GRAD_TOL, name
     # dL/dxi through the oracle's own exponential, in float64 on the CPU
