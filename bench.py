@@ -222,11 +222,13 @@ def as_written_variant(R, params, view, rc, opt, tc, td, iters=60):
             "pruned": int(n_masked.item()), "active_pixels": int(n_act.item())}
 
 
-def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3):
+def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False):
     """Tracking at 640x480 with 100k Gaussians: the map frozen, the camera
     starting 2 cm / 1 degree off the pose its target frame was rendered
     from; each iteration is render_fwd, the loss gradient, render_bwd to the
-    pose only and pose_update (Adam on xi, then T <- Exp(-step) T)."""
+    pose only and pose_update (Adam on xi, then T <- Exp(-step) T).
+    reuse_lists: iterations after the first reuse its tile lists and depth
+    order (projection only; Sec. 3, Observation 6)."""
     import torch
     from paper_2510_06644_amd import pose, rtgs, synth
     spec = synth.CONFIGS["c1"]
@@ -249,8 +251,11 @@ def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3):
     def run(view, n):
         m = torch.zeros(6, device="cuda")
         v = torch.zeros(6, device="cuda")
+        first = None
         for it in range(1, n + 1):
-            st = R.forward(scene, view, rc)
+            st = R.forward(scene, view, rc, reuse_lists_of=first)
+            if reuse_lists and first is None:
+                first = st
             gc, gd = l1_grads(st.color, st.depth, tc, td)
             g = R.backward(scene, view, rc, st, gc, gd, pose=True, map_grads=False)
             rtgs.pose_update([(view, g["pose"], m, v, lr_rho, lr_phi, it)])
@@ -266,8 +271,9 @@ def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3):
     torch.cuda.synchronize()
     R.verify()
     ms = e0.elapsed_time(e1) / iters
-    return {"workload": "640x480_100k_tracking", "iters": iters, "ms_per_iter": ms,
-            "iters_per_s": 1000.0 / ms, "pose_err_start": err(start), "pose_err_end": err(view)}
+    return {"workload": "640x480_100k_tracking", "reuse_lists": reuse_lists, "iters": iters,
+            "ms_per_iter": ms, "iters_per_s": 1000.0 / ms, "pose_err_start": err(start),
+            "pose_err_end": err(view)}
 
 
 def cpu_baseline(sc, cam, sample=192, seed=5):
@@ -391,6 +397,7 @@ def main():
         variant = as_written_variant(R2, params2, view2, rc2, opt2, tc2, td2)
     log("tracking 640x480 / 100k")
     tracking = tracking_run()
+    tracking_reuse = tracking_run(reuse_lists=True)
     serve = None
     if args.serve_seconds > 0:
         serve = {}
@@ -438,6 +445,7 @@ def main():
         "host_wall_ms_per_step": 1000.0 * wall_ms,
         "as_written": variant,
         "tracking": tracking,
+        "tracking_reuse_lists": tracking_reuse,
         "serving": serve,
         "cpu_baseline": cpu,
     }

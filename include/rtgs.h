@@ -56,6 +56,8 @@ extern "C" {
 
 /* ---- render_fwd flags ---- */
 #define RTGS_FWD_SAVE_STATE   1   /* write final_T and last_idx (saved state)  */
+#define RTGS_FWD_REUSE_LISTS  4   /* keep the tile lists of this workspace's
+                                     last forward (see render_fwd)            */
 #define RTGS_FWD_STATS        2   /* write per-pixel work counts (sessions'
                                      `stats`; render_fwd_batched only)         */
 
@@ -177,6 +179,15 @@ int32_t rtgs_workspace_size_batched(const int32_t* n, const int32_t* width,
  * pixel_mask may be NULL; masked pixels render 0 with final_T = 1.
  * final_T and last_idx are written when RTGS_FWD_SAVE_STATE is set (they may
  * be NULL otherwise); visible may be NULL.
+ * RTGS_FWD_REUSE_LISTS (the reuse of tile intersection and sorting across the
+ * iterations of a frame, Sec. 3, Observation 6): Step 1-1 runs for the
+ * current pose and parameters, Steps 1-2 and 2 are skipped and the tile
+ * lists, depth order, tile rectangles and pair slots of the last forward
+ * without this flag on the same workspace are used (a Gaussian that has
+ * moved into a tile it was not listed for does not reach it; the lists keep
+ * their reference depth order).  The caller guarantees that forward used the
+ * same sessions, Gaussian counts, image sizes, sample_log2 and
+ * pair_capacity; visible then reports the reference visibility.
  * Errors: INVALID_ARG (null required pointer, n < 0, W or H <= 0,
  * pair_capacity < 0, bad flags), WORKSPACE (ws_bytes too small), HIP. */
 int32_t render_fwd(rtgs_handle_t h, const rtgs_gaussians* g,

@@ -78,6 +78,27 @@ def _stage(params, viewmat, cam, gauss_mask, xi):
     return cov3d, opac, proj
 
 
+def _groups(idx, w, order, chunk, tile_lists):
+    """Pixel groups and the fragment order each is composited in: chunks of
+    `chunk` pixels in the global depth order, or, with tile_lists =
+    (tile_w, tile_h, ranges [T, 2], ids), the pixels of each tile in that
+    tile's list order (lists frozen at an earlier pose: the reuse of tile
+    intersection and sorting across the iterations of a frame, Sec. 3,
+    Observation 6)."""
+    if tile_lists is None:
+        for s in range(0, idx.numel(), chunk):
+            yield torch.arange(s, min(s + chunk, idx.numel())), order
+        return
+    tw, th, ranges, ids = tile_lists
+    ranges = torch.as_tensor(ranges, dtype=torch.long)
+    ids = torch.as_tensor(ids, dtype=torch.long)
+    tiles_x = (w + tw - 1) // tw
+    tile = (idx // w) // th * tiles_x + (idx % w) // tw
+    for t in torch.unique(tile).tolist():
+        sel = torch.nonzero(tile == t).flatten()
+        yield sel, ids[ranges[t, 0]:ranges[t, 1]]
+
+
 def _active_pixels(idx, pixel_mask):
     if pixel_mask is None:
         return torch.ones_like(idx, dtype=torch.bool)
@@ -85,11 +106,11 @@ def _active_pixels(idx, pixel_mask):
 
 
 def render(scene, viewmat, cam, gauss_mask=None, pixel_mask=None, pixels=None,
-           chunk=2048, **band) -> RenderOut:
+           chunk=2048, tile_lists=None, **band) -> RenderOut:
     """Forward only, in float64.  `scene` holds the five parameter arrays
     (float32 values are promoted exactly).  `pixels` optionally restricts the
     evaluation to a list of raster indices (j*W + i); masked pixels render as
-    background with T_final = 1."""
+    background with T_final = 1.  tile_lists: see _groups."""
     params = tuple(_t(x) for x in scene)
     vm = _t(viewmat)
     w, h = cam[0], cam[1]
@@ -101,16 +122,14 @@ def render(scene, viewmat, cam, gauss_mask=None, pixel_mask=None, pixels=None,
         order = keep[order_local]
         idx, pxs, pys = _pixel_grid(w, h, pixels)
         act = _active_pixels(idx, pixel_mask)
-        outs = []
-        for s in range(0, idx.numel(), chunk):
-            sl = slice(s, s + chunk)
-            cp = composite_pixels(pxs[sl], pys[sl], proj.u, proj.v, proj.a, proj.b,
+        outs, sels = [], []
+        for sel, order_g in _groups(idx, w, order, chunk, tile_lists):
+            cp = composite_pixels(pxs[sel], pys[sel], proj.u, proj.v, proj.a, proj.b,
                                   proj.c, opac, proj.z, params[4], proj.valid,
-                                  order, **band)
+                                  order_g, **band)
             outs.append(cp)
-    cat = lambda f: torch.cat([getattr(o, f) for o in outs]) if outs else torch.zeros(0)
-    color, depth, final_t = cat("color"), cat("depth"), cat("final_t")
-    last_id, n_bl, flags = cat("last_id"), cat("n_blended"), cat("flags")
+            sels.append(sel)
+    color, depth, final_t, last_id, n_bl, flags = _scatter(outs, sels, idx.numel())
     a = act
     color = torch.where(a[:, None], color, torch.zeros_like(color))
     depth = torch.where(a, depth, torch.zeros_like(depth))
@@ -127,7 +146,7 @@ def render(scene, viewmat, cam, gauss_mask=None, pixel_mask=None, pixels=None,
 
 def render_with_grads(scene, viewmat, cam, g_color, g_depth, g_alpha=None,
                       gauss_mask=None, pixel_mask=None, pixels=None, chunk=1024,
-                      **band):
+                      tile_lists=None, **band):
     """Forward plus the gradient of  L = sum(g_color C) + sum(g_depth D)
     + sum(g_alpha A)  with respect to every parameter and the pose.
 
@@ -152,12 +171,11 @@ def render_with_grads(scene, viewmat, cam, g_color, g_depth, g_alpha=None,
     gc = _t(g_color).reshape(3, -1).T
     gd = _t(g_depth).reshape(-1)
     ga = None if g_alpha is None else _t(g_alpha).reshape(-1)
-    outs = []
-    for s in range(0, idx.numel(), chunk):
-        sl = slice(s, s + chunk)
+    outs, sels = [], []
+    for sl, order_g in _groups(idx, w, order, chunk, tile_lists):
         cp = composite_pixels(pxs[sl], pys[sl], leaves["u"], leaves["v"], leaves["a"],
                               leaves["b"], leaves["c"], leaves["o"], leaves["z"],
-                              leaves["rgb"], proj.valid, order, **band)
+                              leaves["rgb"], proj.valid, order_g, **band)
         m = act[sl].to(F64)
         loss = ((cp.color * gc[sl]).sum(1) * m).sum() + (cp.depth * gd[sl] * m).sum()
         if ga is not None:
@@ -165,15 +183,14 @@ def render_with_grads(scene, viewmat, cam, g_color, g_depth, g_alpha=None,
         if loss.requires_grad:
             loss.backward()
         outs.append(Composite_detached(cp))
+        sels.append(sl)
     stage_grads = {k: (t.grad if t.grad is not None else torch.zeros_like(t))
                    for k, t in leaves.items()}
     # Preprocessing BP: push the 2D gradients back through the stage
     tensors = [proj.u, proj.v, proj.a, proj.b, proj.c, proj.z, opac, params[4]]
     grads = [stage_grads[k] for k in ("u", "v", "a", "b", "c", "z", "o", "rgb")]
     torch.autograd.backward(tensors, grads)
-    cat = lambda f: torch.cat([getattr(o, f) for o in outs])
-    color, depth, final_t = cat("color"), cat("depth"), cat("final_t")
-    last_id, n_bl, flags = cat("last_id"), cat("n_blended"), cat("flags")
+    color, depth, final_t, last_id, n_bl, flags = _scatter(outs, sels, idx.numel())
     color = torch.where(act[:, None], color, torch.zeros_like(color))
     depth = torch.where(act, depth, torch.zeros_like(depth))
     final_t = torch.where(act, final_t, torch.ones_like(final_t))
@@ -206,3 +223,21 @@ class Composite_detached:
         self.last_id = cp.last_id
         self.n_blended = cp.n_blended
         self.flags = cp.flags
+
+
+def _scatter(outs, sels, n):
+    """Per-group composite outputs back to pixel order."""
+    color = torch.zeros(n, 3, dtype=F64)
+    depth = torch.zeros(n, dtype=F64)
+    final_t = torch.ones(n, dtype=F64)
+    last_id = torch.full((n,), -1, dtype=torch.long)
+    n_bl = torch.zeros(n, dtype=torch.long)
+    flags = torch.zeros(n, dtype=torch.bool)
+    for o, sel in zip(outs, sels):
+        color[sel] = o.color.detach()
+        depth[sel] = o.depth.detach()
+        final_t[sel] = o.final_t.detach()
+        last_id[sel] = o.last_id
+        n_bl[sel] = o.n_blended
+        flags[sel] = o.flags
+    return color, depth, final_t, last_id, n_bl, flags

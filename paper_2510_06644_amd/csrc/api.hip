@@ -457,7 +457,7 @@ int32_t rtgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t pa
 
 int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
-  if (flags & ~(RTGS_FWD_SAVE_STATE | RTGS_FWD_STATS))
+  if (flags & ~(RTGS_FWD_SAVE_STATE | RTGS_FWD_STATS | RTGS_FWD_REUSE_LISTS))
     return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d (sample_log2 goes in the sessions)",
                 flags);
   WsLayout L;
@@ -474,7 +474,8 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   r = upload_table(h, ss, ns, w, st, true, flags, B);
   if (r) return r;
   StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
-  hipError_t e = launch_forward_prep(B, w, h->d_scalars, st, tm);
+  hipError_t e = launch_forward_prep(B, w, h->d_scalars, (flags & RTGS_FWD_REUSE_LISTS) != 0,
+                                     st, tm);
   if (e == hipSuccess) e = launch_raster_fwd(B, w, (flags & RTGS_FWD_STATS) != 0, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_fwd launch");
   h->last_stream = st;

@@ -100,13 +100,17 @@ __device__ __forceinline__ void split(double x, float& hi, float& lo) {
 }
 
 // Step 1-1 + the tile rectangle of Step 1-2 + per-tile pair counts.
+// REUSE: the tile lists (and with them each Gaussian's tile rectangle, pair
+// count and slots) stay those of the workspace's last full forward; only the
+// raster records are recomputed for the current pose.
+template <bool REUSE>
 __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W) {
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.block_base; });
   const SessionDev& S = B.sess[s];
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
   // the call's counters start at zero (the binning passes run after this kernel)
-  if (blockIdx.x == 0 && threadIdx.x < 8) W.counters[threadIdx.x] = 0;
+  if (!REUSE && blockIdx.x == 0 && threadIdx.x < 8) W.counters[threadIdx.x] = 0;
   if (li >= S.n) return;
   const int gid = S.gauss_base + li;
   float vm[12];
@@ -150,6 +154,11 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
     r.col = make_float4(0.f, 0.f, 0.f, (float)P.z);
     r.ext = make_float4(0.f, 0.f, 0.f, 0.f);
     W.rec[gid] = r;
+  }
+  if (REUSE) {
+    const int4 ref = W.rect[gid];
+    if (S.visible) S.visible[li] = ref.z >= ref.x ? 1 : 0;
+    return;
   }
   W.rect[gid] = rect;
   const bool vis = rect.z >= rect.x;
@@ -600,7 +609,14 @@ __global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
 }  // namespace
 
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
-                               hipStream_t st, StageTimer* tm) {
+                               bool reuse_lists, hipStream_t st, StageTimer* tm) {
+  if (reuse_lists) {
+    if (b.b_total > 0) {
+      Scope sc(tm, kStPreprocess, st);
+      k_preprocess<true><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+    }
+    return hipGetLastError();
+  }
   const size_t lds = sizeof(uint32_t) * (size_t)(b.t_max > 0 ? b.t_max : 1);
   if (b.b_total <= 0) {
     // no Gaussians: k_preprocess (which zeroes the counters) does not run
@@ -609,7 +625,7 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
   }
   if (b.b_total > 0) {
     Scope sc(tm, kStPreprocess, st);
-    k_preprocess<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+    k_preprocess<false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
   }
   if (b.c_total > 0) {
     Scope sc(tm, kStBinCount, st);

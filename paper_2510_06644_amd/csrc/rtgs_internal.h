@@ -180,7 +180,7 @@ struct Scope {
 
 // ---- launch wrappers (defined in the .hip files) ----
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
-                               hipStream_t st, StageTimer* tm);
+                               bool reuse_lists, hipStream_t st, StageTimer* tm);
 hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, hipStream_t st,
                              StageTimer* tm);
 hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st,

@@ -29,6 +29,7 @@ RTGS_ERR_HIP = -3
 RTGS_ERR_WORKSPACE = -4
 RTGS_FWD_SAVE_STATE = 1
 RTGS_FWD_STATS = 2
+RTGS_FWD_REUSE_LISTS = 4
 RTGS_PROFILE_STAGES = 16
 STAGES = ("init", "preprocess", "scan", "emit", "sort", "raster_fwd", "adam", "raster_bwd",
           "preprocess_bwd", "pose_reduce", "bin_count", "merge")
@@ -468,13 +469,37 @@ class Renderer:
 
     # ------------------------------------------------------------------ managed calls
     def forward(self, scene, viewmat, cam: Cam, gauss_mask=None, pixel_mask=None,
-                save_state=True, stream=None, sample_log2=0):
+                save_state=True, stream=None, sample_log2=0, reuse_lists_of=None):
         """Render one frame; returns a FwdState (outputs + the workspace the
         matching backward needs).  Each forward gets its own workspace from
-        torch's caching allocator, so several forwards may await backward."""
+        torch's caching allocator, so several forwards may await backward.
+
+        reuse_lists_of: a FwdState of an earlier full forward of the same
+        frame geometry; its tile lists and depth order are reused (projection
+        only, no binning or sort) and its workspace is shared, so that
+        state's own backward must already have run."""
         n = scene[0].shape[0]
         dev = scene[0].device
         h, w = cam.height, cam.width
+        if reuse_lists_of is not None:
+            ref = reuse_lists_of
+            if (ref.n, ref.cam.width, ref.cam.height, ref.sample_log2) != (n, w, h, sample_log2):
+                raise ValueError("reuse_lists_of: different frame geometry")
+            out = FwdState(ws=ref.ws, cap=ref.cap, cam=cam, n=n, sample_log2=sample_log2,
+                           color=torch.empty(3, h, w, device=dev),
+                           depth=torch.empty(h, w, device=dev),
+                           alpha=torch.empty(h, w, device=dev),
+                           final_T=torch.empty(h, w, device=dev) if save_state else None,
+                           last_idx=(torch.empty(h, w, dtype=torch.int32, device=dev)
+                                     if save_state else None),
+                           visible=torch.empty(n, dtype=torch.uint8, device=dev),
+                           pairs=ref.pairs)
+            render_fwd(self.handle, *scene, viewmat, cam, ref.ws, ref.cap, out.color, out.depth,
+                       out.alpha, out.final_T, out.last_idx, out.visible, gauss_mask=gauss_mask,
+                       pixel_mask=pixel_mask,
+                       flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | RTGS_FWD_REUSE_LISTS
+                       | (int(sample_log2) << RTGS_SAMPLE_SHIFT), stream=stream)
+            return out
         est = int(self.ppg * n) + 4 * _tiles(w, h)
         cap = max(self.cap, est, self.min_cap)
         while True:

@@ -334,6 +334,24 @@ def test_tile_lists_cover_every_fragment():
         assert g in members[tiles[pi]]
 
 
+def test_render_through_current_tile_lists_equals_global_order():
+    # lists built at the same pose hold every fragment of their tile in the
+    # global (z, id) order, so compositing through them changes nothing
+    cam = CAM64
+    sc = _c0_small(n=300, seed=13)
+    u, v, ex, ey, z, valid, p = _stage32(sc, cam)
+    ranges, ids = binning.tile_lists(u, v, ex, ey, z, valid, 64, 64)
+    a = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam))
+    b = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam), tile_lists=(16, 16, ranges, ids))
+    for f in ("color", "depth", "final_t"):
+        assert torch.allclose(getattr(a, f), getattr(b, f), rtol=1e-12, atol=1e-14), f
+    assert torch.equal(a.last_id, b.last_id) and torch.equal(a.n_blended, b.n_blended)
+    # frozen lists in reverse order do change the image (the order is used)
+    rev = np.concatenate([ids[r0:r1][::-1] for r0, r1 in ranges])
+    c = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam), tile_lists=(16, 16, ranges, rev))
+    assert not torch.allclose(a.color, c.color, atol=1e-3)
+
+
 # ---------------------------------------------------------------- Eq. (7), Sec. 4
 def test_importance_score_by_hand():
     gm = np.array([[3.0, 4.0, 0.0], [0, 0, 0]])
