@@ -452,13 +452,13 @@ __device__ void bitonic_sort(P a, int n) {
   }
 }
 
-// Merge sort of one tile's 64-bit keys with NT threads holding 4 keys each
-// (lists up to 4 NT keys; the tail is padded with all-ones keys, which no
-// real key equals since depth bits of a finite float are below 0x7f800000).
-// Each thread sorts its 4 keys in registers, then log2(NT) merge levels run
-// through two LDS buffers: a thread finds where its 4 outputs start on the
-// merge path of its pair of runs by binary search and merges 4 keys.  One
-// barrier per level, instead of one per bitonic stage.
+// Merge sort of one tile's 64-bit keys: the list is padded to N keys (a power
+// of two, n <= N <= K NT) with all-ones keys, which no real key equals since
+// depth bits of a finite float are below 0x7f800000.  The first N / K threads
+// each sort K keys in registers, then log2(N / K) merge levels run through two
+// LDS buffers: a thread finds where its K outputs start on the merge path of
+// its pair of runs by binary search and merges K keys.  One barrier per level
+// (all NT threads take it), instead of one per bitonic stage.
 constexpr unsigned long long kKeyPad = ~0ull;
 constexpr int kSortPerThread = 4;
 
@@ -468,49 +468,72 @@ __device__ __forceinline__ void cas(unsigned long long& a, unsigned long long& b
   b = hi;
 }
 
-template <int NT>
+// Sorting networks: 5 comparators for 4 keys, Batcher's 19 for 8.
+__device__ __forceinline__ void sort_network(unsigned long long (&k)[4]) {
+  cas(k[0], k[1]); cas(k[2], k[3]);
+  cas(k[0], k[2]); cas(k[1], k[3]);
+  cas(k[1], k[2]);
+}
+__device__ __forceinline__ void sort_network(unsigned long long (&k)[8]) {
+  cas(k[0], k[1]); cas(k[2], k[3]); cas(k[4], k[5]); cas(k[6], k[7]);
+  cas(k[0], k[2]); cas(k[1], k[3]); cas(k[4], k[6]); cas(k[5], k[7]);
+  cas(k[1], k[2]); cas(k[5], k[6]);
+  cas(k[0], k[4]); cas(k[1], k[5]); cas(k[2], k[6]); cas(k[3], k[7]);
+  cas(k[2], k[4]); cas(k[3], k[5]);
+  cas(k[1], k[2]); cas(k[3], k[4]); cas(k[5], k[6]);
+}
+
+// Smallest power of two >= max(n, lo).
+__device__ __forceinline__ int pow2_at_least(int n, int lo) {
+  int p = lo;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+template <int NT, int K>
 __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, int n,
                                 unsigned long long* buf0, unsigned long long* buf1) {
-  constexpr int K = kSortPerThread, N = K * NT;
+  const int N = pow2_at_least(n, K);
   const int t = threadIdx.x;
-  unsigned long long k[K];
+  const bool act = K * t < N;
+  if (act) {
+    unsigned long long k[K];
 #pragma unroll
-  for (int s = 0; s < K; ++s) k[s] = K * t + s < n ? keys[K * t + s] : kKeyPad;
-  cas(k[0], k[1]);
-  cas(k[2], k[3]);
-  cas(k[0], k[2]);
-  cas(k[1], k[3]);
-  cas(k[1], k[2]);
+    for (int s = 0; s < K; ++s) k[s] = K * t + s < n ? keys[K * t + s] : kKeyPad;
+    sort_network(k);
 #pragma unroll
-  for (int s = 0; s < K; ++s) buf0[K * t + s] = k[s];
+    for (int s = 0; s < K; ++s) buf0[K * t + s] = k[s];
+  }
   __syncthreads();
   unsigned long long* src = buf0;
   unsigned long long* dst = buf1;
   for (int L = K; L < N; L <<= 1) {
-    const int pos = K * t;
-    const int base = pos & ~(2 * L - 1);
-    const int r = pos - base;
-    const unsigned long long* A = src + base;
-    const unsigned long long* Bv = src + base + L;
-    // number of A keys among the first r outputs (ties: A first)
-    int lo = r > L ? r - L : 0, hi = r < L ? r : L;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (A[mid] <= Bv[r - 1 - mid]) lo = mid + 1;
-      else hi = mid;
-    }
-    int i = lo, j = r - lo;
-    unsigned long long x = i < L ? A[i] : kKeyPad, y = j < L ? Bv[j] : kKeyPad;
+    if (act) {
+      const int pos = K * t;
+      const int base = pos & ~(2 * L - 1);
+      const int r = pos - base;
+      const unsigned long long* A = src + base;
+      const unsigned long long* Bv = src + base + L;
+      // number of A keys among the first r outputs (ties: A first)
+      int lo = r > L ? r - L : 0, hi = r < L ? r : L;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] <= Bv[r - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+      }
+      int i = lo, j = r - lo;
+      unsigned long long x = i < L ? A[i] : kKeyPad, y = j < L ? Bv[j] : kKeyPad;
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-      const bool take_a = j >= L || (i < L && x <= y);
-      dst[pos + s] = take_a ? x : y;
-      if (take_a) {
-        ++i;
-        x = i < L ? A[i] : kKeyPad;
-      } else {
-        ++j;
-        y = j < L ? Bv[j] : kKeyPad;
+      for (int s = 0; s < K; ++s) {
+        const bool take_a = j >= L || (i < L && x <= y);
+        dst[pos + s] = take_a ? x : y;
+        if (take_a) {
+          ++i;
+          x = i < L ? A[i] : kKeyPad;
+        } else {
+          ++j;
+          y = j < L ? Bv[j] : kKeyPad;
+        }
       }
     }
     __syncthreads();
@@ -538,11 +561,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_tiles(WsPtrs W) {
     }
     return;
   }
-  merge_sort_tile<kBlock>(W.keys + st, W.ids + st, n, b0, b1);
+  merge_sort_tile<kBlock, kSortPerThread>(W.keys + st, W.ids + st, n, b0, b1);
 }
 
-// Queued long lists: up to 4096 keys by the LDS merge sort with 1024
-// threads, longer ones by the bitonic network in place in global memory.
+// Queued long lists, up to 4096 keys, by the LDS merge sort with 1024
+// threads; longer ones are queued again for k_sort_huge_tiles.
 constexpr int kBigThreads = 1024;
 __global__ __launch_bounds__(kBigThreads) void k_sort_big_tiles(WsPtrs W) {
   __shared__ unsigned long long b0[kSortPerThread * kBigThreads], b1[kSortPerThread * kBigThreads];
@@ -553,7 +576,29 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big_tiles(WsPtrs W) {
     const int64_t en = min((int64_t)W.tile_start[t + 1], W.cap);
     const int n = (int)(en - st);
     if (n <= kSortPerThread * kBigThreads) {
-      merge_sort_tile<kBigThreads>(W.keys + st, W.ids + st, n, b0, b1);
+      merge_sort_tile<kBigThreads, kSortPerThread>(W.keys + st, W.ids + st, n, b0, b1);
+    } else if (threadIdx.x == 0) {
+      const unsigned long long q2 = atomicAdd((unsigned long long*)&W.counters[3], 1ull);
+      W.huge_tiles[q2] = (uint32_t)t;
+    }
+    __syncthreads();
+  }
+}
+
+// Lists above 4096 keys: up to 8192 by the LDS merge sort with 8 keys per
+// thread (128 KB of LDS, one workgroup per CU), longer ones by the bitonic
+// network in place in global memory.
+constexpr int kHugePerThread = 8;
+__global__ __launch_bounds__(kBigThreads) void k_sort_huge_tiles(WsPtrs W) {
+  __shared__ unsigned long long b0[kHugePerThread * kBigThreads], b1[kHugePerThread * kBigThreads];
+  const long long count = W.counters[3];
+  for (long long q = blockIdx.x; q < count; q += gridDim.x) {
+    const int t = (int)W.huge_tiles[q];
+    const int64_t st = min((int64_t)W.tile_start[t], W.cap);
+    const int64_t en = min((int64_t)W.tile_start[t + 1], W.cap);
+    const int n = (int)(en - st);
+    if (n <= kHugePerThread * kBigThreads) {
+      merge_sort_tile<kBigThreads, kHugePerThread>(W.keys + st, W.ids + st, n, b0, b1);
     } else {
       unsigned long long* g = W.keys + st;
       bitonic_sort(g, n);
@@ -646,6 +691,7 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
     Scope sc(tm, kStSort, st);
     k_sort_tiles<<<b.t_total, kBlock, 0, st>>>(w);
     k_sort_big_tiles<<<b.t_total < 512 ? b.t_total : 512, kBigThreads, 0, st>>>(w);
+    k_sort_huge_tiles<<<b.t_total < 256 ? b.t_total : 256, kBigThreads, 0, st>>>(w);
   }
   return hipGetLastError();
 }
