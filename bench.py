@@ -222,13 +222,16 @@ def as_written_variant(R, params, view, rc, opt, tc, td, iters=60):
             "pruned": int(n_masked.item()), "active_pixels": int(n_act.item())}
 
 
-def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False):
+def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False, mask_prune=False):
     """Tracking at 640x480 with 100k Gaussians: the map frozen, the camera
     starting 2 cm / 1 degree off the pose its target frame was rendered
     from; each iteration is render_fwd, the loss gradient, render_bwd to the
     pose only and pose_update (Adam on xi, then T <- Exp(-step) T).
     reuse_lists: iterations after the first reuse its tile lists and depth
-    order (projection only; Sec. 3, Observation 6)."""
+    order (projection only; Sec. 3, Observation 6).
+    mask_prune: the mask-prune schedule of Sec. 4.1 (prune.MaskPruneTracker:
+    windows of one full iteration and K masked iterations on its lists, the
+    masked Gaussians removed at the next full iteration)."""
     import torch
     from paper_2510_06644_amd import pose, rtgs, synth
     spec = synth.CONFIGS["c1"]
@@ -248,10 +251,19 @@ def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False):
         c = float(((v[:, :3].trace() - 1.0) / 2.0).clamp(-1.0, 1.0))
         return {"t_cm": t, "r_deg": float(np.degrees(np.arccos(c)))}
 
+    tracker = [None]
+
     def run(view, n):
         m = torch.zeros(6, device="cuda")
         v = torch.zeros(6, device="cuda")
         first = None
+        if mask_prune:
+            from paper_2510_06644_amd import prune
+            tr = tracker[0] = prune.MaskPruneTracker(R, scene, rc)
+            for it in range(1, n + 1):
+                g = tr.iteration(view, lambda st: l1_grads(st.color, st.depth, tc, td))
+                rtgs.pose_update([(view, g, m, v, lr_rho, lr_phi, it)])
+            return
         for it in range(1, n + 1):
             st = R.forward(scene, view, rc, reuse_lists_of=first)
             if reuse_lists and first is None:
@@ -271,9 +283,15 @@ def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False):
     torch.cuda.synchronize()
     R.verify()
     ms = e0.elapsed_time(e1) / iters
-    return {"workload": "640x480_100k_tracking", "reuse_lists": reuse_lists, "iters": iters,
-            "ms_per_iter": ms, "iters_per_s": 1000.0 / ms, "pose_err_start": err(start),
-            "pose_err_end": err(view)}
+    out = {"workload": "640x480_100k_tracking", "reuse_lists": reuse_lists, "iters": iters,
+           "ms_per_iter": ms, "iters_per_s": 1000.0 / ms, "pose_err_start": err(start),
+           "pose_err_end": err(view)}
+    if mask_prune:
+        tr = tracker[0]
+        out.update(mask_prune=True, gaussians_end=tr.n, full_iters=tr.full_iters,
+                   masked_iters=tr.masked_iters,
+                   windows=[[k, r] for k, r in tr.sched.windows])
+    return out
 
 
 def cpu_baseline(sc, cam, sample=192, seed=5):
@@ -398,6 +416,7 @@ def main():
     log("tracking 640x480 / 100k")
     tracking = tracking_run()
     tracking_reuse = tracking_run(reuse_lists=True)
+    tracking_prune = tracking_run(mask_prune=True)
     serve = None
     if args.serve_seconds > 0:
         serve = {}
@@ -446,6 +465,7 @@ def main():
         "as_written": variant,
         "tracking": tracking,
         "tracking_reuse_lists": tracking_reuse,
+        "tracking_mask_prune": tracking_prune,
         "serving": serve,
         "cpu_baseline": cpu,
     }

@@ -67,6 +67,10 @@ extern "C" {
 #define RTGS_GRAD_COV3D       4   /* also write g_cov3d (needs RTGS_GRAD_MAP)  */
 #define RTGS_GRAD_RECOMPUTE_STATE 8 /* final_T/last_idx were not saved: the
                                        backward recomputes them first          */
+#define RTGS_GRAD_SCORE      16   /* without RTGS_GRAD_MAP: write g_means and
+                                     g_cov3d only, the inputs of the
+                                     importance score of Sec. 4.1 (the raster
+                                     pass of the pose-only backward)          */
 
 /* ---- downsampled rendering (Sec. 4.2) ----
  * A frame downsampled to one pixel in 2^j (j = 2, 3, 4; 1 also accepted) is
@@ -323,6 +327,50 @@ int32_t prune_by_grad(rtgs_handle_t h, const float* g_means,
                       const uint8_t* mask_in, int32_t n, float lambda,
                       float max_ratio, uint8_t* mask_out,
                       int32_t* n_masked_dev, float* score_out, void* stream);
+
+/* Mask-prune schedule (Sec. 4.1): Gaussians masked for K iterations are then
+ * permanently removed.  compact_by_mask copies the rows i with drop[i] == 0
+ * of each item, in index order, to the front of its dst: row k of dst is
+ * the k-th kept row of src.  items is a HOST array of n_items
+ * (<= RTGS_COMPACT_MAX_ITEMS); src and dst are device arrays of n rows of
+ * row_bytes (> 0) each, dst not overlapping src, 4-byte aligned when
+ * row_bytes is a multiple of 4; dst needs room for the kept rows only.
+ * drop: device uint8 [n]; n_kept (device int32) receives the kept count.
+ * scratch: device memory of rtgs_compact_scratch_size(n) bytes.  n = 0 is a
+ * no-op that writes n_kept = 0 (src and dst may then be NULL).
+ * Errors: INVALID_ARG, WORKSPACE, HIP. */
+#define RTGS_COMPACT_MAX_ITEMS 24
+typedef struct rtgs_compact_item {
+  const void* src;
+  void* dst;
+  int32_t row_bytes;
+} rtgs_compact_item;
+
+uint64_t rtgs_compact_scratch_size(int32_t n);
+int32_t compact_by_mask(const uint8_t* drop, int32_t n,
+                        const rtgs_compact_item* items, int32_t n_items,
+                        void* scratch, uint64_t scratch_bytes,
+                        int32_t* n_kept, void* stream);
+
+/* The tile rectangle of every Gaussian after a full render_fwd on ws (the
+ * same n, width, height, sample_log2 and pair_capacity as that call):
+ * rect_out (device int32 [n][4]) = (x0, y0, x1, y1) in tiles, inclusive,
+ * x1 < x0 for a Gaussian that touches no tile.  The Gaussian's pairs are
+ * exactly the tiles of its rectangle.  Errors: INVALID_ARG, WORKSPACE, HIP. */
+int32_t rtgs_tile_rects(int32_t n, int32_t width, int32_t height,
+                        int32_t sample_log2, int64_t pair_capacity,
+                        const void* ws, uint64_t ws_bytes, int32_t* rect_out,
+                        void* stream);
+
+/* Change of the tile-Gaussian intersections between two sets of rectangles
+ * (Sec. 4.1: the ratio that sets the next pruning interval): out (device
+ * int64 [2]) receives out[0] = sum over Gaussians i with skip[i] == 0 of the
+ * tiles in exactly one of rect_ref[i] and rect_cur[i], out[1] = sum of the
+ * tiles of rect_ref[i]; the ratio is out[0] / out[1].  skip may be NULL.
+ * Errors: INVALID_ARG, HIP. */
+int32_t tile_pair_change(const int32_t* rect_ref, const int32_t* rect_cur,
+                         const uint8_t* skip, int32_t n, int64_t* out,
+                         void* stream);
 
 /* Dynamic downsampling (Sec. 4.2) as a pixel mask: keep 1 pixel in 2^j,
  * one per block of 2^ceil(j/2) x 2^floor(j/2) pixels (4x4, 4x2, 2x2 for

@@ -76,3 +76,25 @@ def tile_lists(u, v, ex, ey, z, valid, width, height, tile_w=TILE, tile_h=TILE):
     ends = np.cumsum(counts)
     ranges = np.stack([ends - counts, ends], 1)
     return ranges, gid
+
+
+def pair_change(rect_ref, rect_cur, skip=None):
+    """Change of the tile-Gaussian intersections between two sets of tile
+    rectangles (the ratio of Sec. 4.1 that sets the next pruning interval),
+    by brute force over explicit tile sets: returns (pairs in exactly one of
+    the two rectangles, pairs of rect_ref), summed over the Gaussians i with
+    skip[i] false.  Rectangles are rows (x0, y0, x1, y1), inclusive, empty
+    when x1 < x0 or y1 < y0."""
+    def tiles(r):
+        x0, y0, x1, y1 = (int(t) for t in r)
+        return {(x, y) for x in range(x0, x1 + 1) for y in range(y0, y1 + 1)}
+
+    changed = ref = 0
+    for i, (a, b) in enumerate(zip(rect_ref, rect_cur)):
+        if skip is not None and skip[i]:
+            continue
+        ta, tb = tiles(a), tiles(b)
+        changed += len(ta ^ tb)
+        ref += len(ta)
+    return changed, ref
+

@@ -250,6 +250,8 @@ int32_t check_session(const rtgs_session& s, int idx, bool fwd, int32_t flags) {
       return fail(RTGS_ERR_INVALID_ARG, "session %d: POSE needs g_pose6 and/or g_viewmat", idx);
     if ((flags & RTGS_GRAD_COV3D) && (!(flags & RTGS_GRAD_MAP) || (g.n > 0 && !s.g_cov3d)))
       return fail(RTGS_ERR_INVALID_ARG, "session %d: COV3D needs MAP and g_cov3d", idx);
+    if ((flags & RTGS_GRAD_SCORE) && g.n > 0 && (!s.g_means || !s.g_cov3d))
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: SCORE needs g_means and g_cov3d", idx);
   }
   return RTGS_OK;
 }
@@ -317,6 +319,9 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
         d.g_opac = s.g_opacity_logits;
         d.g_colors = s.g_colors;
         d.g_cov3d = (flags & RTGS_GRAD_COV3D) ? s.g_cov3d : nullptr;
+      } else if (flags & RTGS_GRAD_SCORE) {
+        d.g_means = s.g_means;
+        d.g_cov3d = s.g_cov3d;
       }
       d.g_pose6 = (flags & RTGS_GRAD_POSE) ? s.g_pose6 : nullptr;
       d.g_viewmat = (flags & RTGS_GRAD_POSE) ? s.g_viewmat : nullptr;
@@ -487,10 +492,11 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
 
 int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
-  const int32_t known = RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_COV3D | RTGS_GRAD_RECOMPUTE_STATE;
+  const int32_t known = RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_COV3D |
+                        RTGS_GRAD_RECOMPUTE_STATE | RTGS_GRAD_SCORE;
   if (flags & ~known) return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
-  if (!(flags & (RTGS_GRAD_POSE | RTGS_GRAD_MAP)))
-    return fail(RTGS_ERR_INVALID_ARG, "render_bwd needs RTGS_GRAD_POSE and/or RTGS_GRAD_MAP");
+  if (!(flags & (RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_SCORE)))
+    return fail(RTGS_ERR_INVALID_ARG, "render_bwd needs RTGS_GRAD_POSE, MAP or SCORE");
   WsLayout L;
   WsPtrs w;
   int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w);
@@ -700,6 +706,81 @@ int32_t pose_update(const rtgs_pose_item* items, int32_t n, double beta1, double
     hipError_t e = launch_pose_update(a, st);
     if (e != hipSuccess) return hip_fail(e, "pose_update launch");
   }
+  return RTGS_OK;
+}
+
+uint64_t rtgs_compact_scratch_size(int32_t n) {
+  const uint64_t nb = n > 0 ? ((uint64_t)n + kCompactBlock - 1) / kCompactBlock : 0;
+  return 4 * (nb + 1);
+}
+
+int32_t compact_by_mask(const uint8_t* drop, int32_t n, const rtgs_compact_item* items,
+                        int32_t n_items, void* scratch, uint64_t scratch_bytes, int32_t* n_kept,
+                        void* stream) {
+  if (n < 0) return fail(RTGS_ERR_INVALID_ARG, "n = %d", n);
+  if (n_items < 0 || n_items > kCompactMaxItems || (n_items > 0 && !items))
+    return fail(RTGS_ERR_INVALID_ARG, "bad item list (n_items = %d)", n_items);
+  if (!n_kept || !scratch || (n > 0 && !drop))
+    return fail(RTGS_ERR_INVALID_ARG, "null drop mask, count or scratch");
+  if (scratch_bytes < rtgs_compact_scratch_size(n))
+    return fail(RTGS_ERR_WORKSPACE, "compaction scratch %llu < %llu bytes",
+                (unsigned long long)scratch_bytes,
+                (unsigned long long)rtgs_compact_scratch_size(n));
+  CompactArgs a{};
+  for (int i = 0; i < n_items; ++i) {
+    const rtgs_compact_item& it = items[i];
+    if ((n > 0 && (!it.src || !it.dst)) || it.row_bytes <= 0)
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: null array or row_bytes %d", i, it.row_bytes);
+    const uint64_t bytes = (uint64_t)n * (uint64_t)it.row_bytes;
+    const uintptr_t s0 = (uintptr_t)it.src, d0 = (uintptr_t)it.dst;
+    if (n > 0 && s0 < d0 + bytes && d0 < s0 + bytes)
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: dst overlaps src", i);
+    if (it.row_bytes % 4 == 0 && ((s0 | d0) & 3u))
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: rows of %d bytes need 4-byte alignment", i,
+                  it.row_bytes);
+    a.item[i].src = static_cast<const unsigned char*>(it.src);
+    a.item[i].dst = static_cast<unsigned char*>(it.dst);
+    a.item[i].row_bytes = it.row_bytes;
+  }
+  a.n_items = n_items;
+  a.n = n;
+  a.drop = drop;
+  a.block_keep = static_cast<uint32_t*>(scratch);
+  a.n_kept = n_kept;
+  hipError_t e = launch_compact(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "compact_by_mask launch");
+  return RTGS_OK;
+}
+
+int32_t rtgs_tile_rects(int32_t n, int32_t width, int32_t height, int32_t sample_log2,
+                        int64_t pair_capacity, const void* ws, uint64_t ws_bytes,
+                        int32_t* rect_out, void* stream) {
+  if (!ws || (n > 0 && !rect_out)) return fail(RTGS_ERR_INVALID_ARG, "null argument");
+  int32_t r = check_cap(pair_capacity);
+  if (r) return r;
+  Counts g;
+  r = geometry(&n, &width, &height, 1, g, &sample_log2);
+  if (r) return r;
+  const WsLayout L = make_layout(g, pair_capacity);
+  if (ws_bytes < L.total) return fail(RTGS_ERR_WORKSPACE, "workspace too small");
+  if (n == 0) return RTGS_OK;
+  const WsPtrs w = ws_ptrs(const_cast<void*>(ws), L);
+  Batch B{};
+  B.n_total = (int32_t)g.n_total;
+  B.t_total = (int32_t)g.t_total;
+  hipError_t e = launch_debug_stage(B, w, nullptr, rect_out, nullptr, nullptr, 0,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rtgs_tile_rects launch");
+  return RTGS_OK;
+}
+
+int32_t tile_pair_change(const int32_t* rect_ref, const int32_t* rect_cur, const uint8_t* skip,
+                         int32_t n, int64_t* out, void* stream) {
+  if (n < 0 || !out || (n > 0 && (!rect_ref || !rect_cur)))
+    return fail(RTGS_ERR_INVALID_ARG, "bad arguments (n = %d)", n);
+  hipError_t e = launch_rect_change(rect_ref, rect_cur, skip, n, out,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "tile_pair_change launch");
   return RTGS_OK;
 }
 

@@ -152,7 +152,9 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
     r.pos = make_float4(0.f, 0.f, 0.f, 0.f);
     r.conic = make_float4(0.f, 0.f, 0.f, 0.f);
     r.col = make_float4(0.f, 0.f, 0.f, (float)P.z);
-    r.ext = make_float4(0.f, 0.f, 0.f, 0.f);
+    // a negative alpha-ellipse bound fails every quadrant test: a culled or
+    // masked Gaussian left in a reused list costs the rasterizer nothing
+    r.ext = make_float4(0.f, 0.f, -1.f, 0.f);
     W.rec[gid] = r;
   }
   if (REUSE) {

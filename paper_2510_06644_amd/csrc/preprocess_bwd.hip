@@ -84,6 +84,9 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
   const bool want_map = (flags & RTGS_GRAD_MAP) != 0;
   const bool want_cov = (flags & RTGS_GRAD_COV3D) != 0 && S.g_cov3d != nullptr;
+  // score inputs only (dL/dmu, dL/dSigma) on the pose-only raster path
+  const bool want_score = !want_map && (flags & RTGS_GRAD_SCORE) != 0 && S.g_means != nullptr &&
+                          S.g_cov3d != nullptr;
   double pose[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // dL/dW (9), dL/dt (3)
   if (li < S.n) {
     const int gid = S.gauss_base + li;
@@ -181,6 +184,16 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
         for (int j = 0; j < 3; ++j) pose[3 * i + j] = dW[3 * i + j] + gp3[i] * mu[j];
         pose[9 + i] = gp3[i];
       }
+      if (want_score) {
+        for (int k = 0; k < 3; ++k) gm[k] = vm[k] * gx + vm[4 + k] * gy + vm[8 + k] * gz;
+        double GT0[3], GT1[3];
+        for (int k = 0; k < 3; ++k) {
+          GT0[k] = Gxx * T0[k] + Gxy * T1[k];
+          GT1[k] = Gxy * T0[k] + Gyy * T1[k];
+        }
+        const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
+        for (int k = 0; k < 6; ++k) gsig[k] = T0[ii[k]] * GT0[jj[k]] + T1[ii[k]] * GT1[jj[k]];
+      }
       if (want_map) {
         // dL/dmu = W^T dL/dp
         for (int k = 0; k < 3; ++k) gm[k] = vm[k] * gx + vm[4 + k] * gy + vm[8 + k] * gz;
@@ -223,6 +236,10 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
       if (S.g_opac) S.g_opac[li] = (float)go_eta;
       if (S.g_colors) for (int k = 0; k < 3; ++k) S.g_colors[3 * li + k] = (float)gcol[k];
       if (want_cov) for (int k = 0; k < 6; ++k) S.g_cov3d[6 * li + k] = (float)gsig[k];
+    }
+    if (want_score) {
+      for (int k = 0; k < 3; ++k) S.g_means[3 * li + k] = (float)gm[k];
+      for (int k = 0; k < 6; ++k) S.g_cov3d[6 * li + k] = (float)gsig[k];
     }
   }
   // block partial of the pose gradient: wave shuffles, then the 4 waves in LDS

@@ -255,6 +255,27 @@ constexpr int kAdamPerThread = 4;
 
 constexpr int kPruneScratchWords = 4096;
 
+// Stable compaction of per-Gaussian arrays by a drop mask (the permanent
+// removal of the mask-prune schedule).
+constexpr int kCompactMaxItems = 24;
+constexpr int kCompactBlock = 1024;
+struct CompactItemDev {
+  const unsigned char* src;
+  unsigned char* dst;
+  int32_t row_bytes;
+};
+struct CompactArgs {
+  CompactItemDev item[kCompactMaxItems];
+  int32_t n_items;
+  int32_t n;
+  const uint8_t* drop;
+  uint32_t* block_keep;    // [ceil(n / kCompactBlock) + 1] scratch
+  int32_t* n_kept;
+};
+hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
+hipError_t launch_rect_change(const int32_t* a, const int32_t* b, const uint8_t* skip, int n,
+                              int64_t* out, hipStream_t st);
+
 // ---- device helpers ----
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 

@@ -37,6 +37,7 @@ RTGS_GRAD_POSE = 1
 RTGS_GRAD_MAP = 2
 RTGS_GRAD_COV3D = 4
 RTGS_GRAD_RECOMPUTE_STATE = 8
+RTGS_GRAD_SCORE = 16
 RTGS_STATE_IDLE = 0
 RTGS_STATE_EXECUTING = 1
 RTGS_MAX_SESSIONS = 64
@@ -47,7 +48,8 @@ EXPORTS = (
     "rtgs_workspace_size_batched", "render_fwd", "render_bwd", "render_fwd_batched",
     "render_bwd_batched", "prune_by_grad", "downsample_mask", "rtgs_downsample_log2_ratio",
     "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum", "rtgs_profile_enable",
-    "rtgs_profile_read", "adam_step", "loss_l1_grad", "pose_update",
+    "rtgs_profile_read", "adam_step", "loss_l1_grad", "pose_update", "compact_by_mask",
+    "rtgs_compact_scratch_size", "rtgs_tile_rects", "tile_pair_change",
 )
 
 vp = ctypes.c_void_p
@@ -55,6 +57,10 @@ i32 = ctypes.c_int32
 i64 = ctypes.c_int64
 u64 = ctypes.c_uint64
 f32 = ctypes.c_float
+
+
+class CCompactItem(ctypes.Structure):
+    _fields_ = [("src", vp), ("dst", vp), ("row_bytes", i32)]
 
 
 class CGaussians(ctypes.Structure):
@@ -122,6 +128,12 @@ def lib():
                                              i32, vp]
             L.prune_by_grad.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp]
             L.downsample_mask.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+            L.rtgs_compact_scratch_size.argtypes = [i32]
+            L.rtgs_compact_scratch_size.restype = u64
+            L.compact_by_mask.argtypes = [vp, i32, ctypes.POINTER(CCompactItem), i32, vp, u64,
+                                          vp, vp]
+            L.rtgs_tile_rects.argtypes = [i32, i32, i32, i32, i64, vp, u64, vp, vp]
+            L.tile_pair_change.argtypes = [vp, vp, vp, i32, vp, vp]
             L.pose_update.argtypes = [ctypes.POINTER(CPoseItem), i32, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, vp]
             L.loss_l1_grad.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp]
@@ -315,6 +327,53 @@ def prune_by_grad(handle, g_means, g_cov3d, visible, mask_in, lam, max_ratio, ma
     _check(lib().prune_by_grad(handle.ptr, _p(g_means), _p(g_cov3d), _p(visible), _p(mask_in),
                                n, float(lam), float(max_ratio), _p(mask_out), _p(n_masked),
                                _p(score_out), _stream(stream)))
+
+
+RTGS_COMPACT_MAX_ITEMS = 24
+
+
+def compact_by_mask(drop, pairs, n_kept, scratch=None, stream=None):
+    """Stable removal of the rows i with drop[i] != 0 (drop: device uint8 [n]):
+    for each (src, dst) pair of contiguous device tensors with n rows, dst[:k]
+    receives the kept rows of src in order (k is written to the device int32
+    n_kept).  dst needs at least the kept rows."""
+    n = drop.numel()
+    pairs = list(pairs)
+    if len(pairs) > RTGS_COMPACT_MAX_ITEMS:
+        raise ValueError(f"compact_by_mask: at most {RTGS_COMPACT_MAX_ITEMS} arrays")
+    arr = (CCompactItem * max(len(pairs), 1))()
+    for k, (src, dst) in enumerate(pairs):
+        if not (src.is_contiguous() and dst.is_contiguous()) or src.dtype != dst.dtype:
+            raise ValueError("compact_by_mask: contiguous src / dst of one dtype")
+        if src.shape[0] != n or src.shape[1:] != dst.shape[1:]:
+            raise ValueError("compact_by_mask: src has n rows and dst the same row shape")
+        row = src[0].numel() * src.element_size() if n else max(src.element_size(), 1)
+        _p(src), _p(dst)            # device, contiguous
+        arr[k] = CCompactItem(src.data_ptr(), dst.data_ptr(), row)
+    need = int(lib().rtgs_compact_scratch_size(n))
+    if scratch is None:
+        scratch = torch.empty(max(need, 4), dtype=torch.uint8, device=drop.device)
+    _check(lib().compact_by_mask(_p(drop), n, arr, len(pairs), _p(scratch),
+                                 scratch.numel() * scratch.element_size(), _p(n_kept),
+                                 _stream(stream)))
+
+
+def rtgs_tile_rects(st, rect_out, stream=None):
+    """Tile rectangles (x0, y0, x1, y1) of the Gaussians of a full forward's
+    state st into rect_out (device int32 [n, 4])."""
+    _check(lib().rtgs_tile_rects(st.n, st.cam.width, st.cam.height, int(st.sample_log2), st.cap,
+                                 _p(st.ws), st.ws.numel() * st.ws.element_size(), _p(rect_out),
+                                 _stream(stream)))
+
+
+def tile_pair_change(rect_ref, rect_cur, skip, out, stream=None):
+    """out (device int64 [2]) = (pairs in exactly one of the two rectangles,
+    pairs of rect_ref), over the Gaussians with skip == 0 (skip may be None)."""
+    n = rect_ref.shape[0]
+    if tuple(rect_cur.shape) != (n, 4) or tuple(rect_ref.shape) != (n, 4):
+        raise ValueError("tile_pair_change: two [n, 4] rectangle arrays")
+    _check(lib().tile_pair_change(_p(rect_ref), _p(rect_cur), _p(skip), n, _p(out),
+                                  _stream(stream)))
 
 
 def pose_update(items, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
@@ -529,12 +588,16 @@ class Renderer:
             cap = self.cap
 
     def backward(self, scene, viewmat, cam: Cam, st: "FwdState", dL_dcolor, dL_ddepth,
-                 dL_dalpha=None, pose=True, map_grads=True, cov3d=False, gauss_mask=None,
+                 dL_dalpha=None, pose=True, map_grads=True, cov3d=False, score=False,
+                 gauss_mask=None,
                  pixel_mask=None, stream=None):
         n = st.n
         dev = scene[0].device
         flags = (RTGS_GRAD_POSE if pose else 0) | (RTGS_GRAD_MAP if map_grads else 0)
         flags |= RTGS_GRAD_COV3D if cov3d else 0
+        # score: dL/dmu and dL/dSigma only (importance-score inputs), on the
+        # pose-only raster path
+        flags |= RTGS_GRAD_SCORE if score and not map_grads else 0
         if st.final_T is None:
             flags |= RTGS_GRAD_RECOMPUTE_STATE
         flags |= int(st.sample_log2) << RTGS_SAMPLE_SHIFT
@@ -546,6 +609,9 @@ class Renderer:
             g["opacity_logits"] = torch.empty(n, device=dev)
             g["colors"] = torch.empty(n, 3, device=dev)
         if cov3d:
+            g["cov3d"] = torch.empty(n, 6, device=dev)
+        if score and not map_grads:
+            g["means"] = torch.empty(n, 3, device=dev)
             g["cov3d"] = torch.empty(n, 6, device=dev)
         if pose:
             g["pose"] = torch.empty(6, device=dev)

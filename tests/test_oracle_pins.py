@@ -491,3 +491,23 @@ def test_pose_update_first_step_closed_forms():
     new, m, v = oracle.pose_update(vm, np.zeros(6), np.zeros(6), np.zeros(6), 3, 0.01, 0.02)
     np.testing.assert_allclose(new, vm, atol=0)
     assert not m.any() and not v.any()
+
+
+def test_pair_change_closed_forms():
+    """Symmetric difference of tile sets: identical rectangles change
+    nothing, disjoint ones change both areas, a rectangle inside another
+    changes the difference of areas, empty rectangles have no tiles, and
+    skipped Gaussians count for nothing."""
+    from oracle.binning import pair_change
+    a = np.array([[0, 0, 2, 1], [0, 0, 1, 1], [0, 0, 3, 3], [5, 5, 4, 4], [1, 1, 1, 1]])
+    b = np.array([[0, 0, 2, 1], [4, 4, 5, 6], [1, 1, 2, 2], [0, 0, 0, 0], [1, 1, 2, 1]])
+    assert pair_change(a[:1], b[:1]) == (0, 6)
+    assert pair_change(a[1:2], b[1:2]) == (4 + 6, 4)
+    assert pair_change(a[2:3], b[2:3]) == (16 - 4, 16)
+    assert pair_change(a[3:4], b[3:4]) == (1, 0)
+    assert pair_change(a[4:5], b[4:5]) == (1, 1)
+    total = pair_change(a, b)
+    assert total == (0 + 10 + 12 + 1 + 1, 6 + 4 + 16 + 0 + 1)
+    skip = np.array([0, 1, 0, 1, 0], dtype=bool)
+    assert pair_change(a, b, skip) == (0 + 12 + 1, 6 + 16 + 1)
+
