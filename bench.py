@@ -348,6 +348,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 512 MiB device copy (scales PMC byte counters)")
+    ap.add_argument("--no-tracking", action="store_true",
+                    help="skip the tracking lines (profiler runs of the mapping step)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the serving trace (0 disables the serving runs)")
     args = ap.parse_args()
@@ -413,10 +415,12 @@ def main():
             mapping_step(R2, params2, view2, rc2, opt2, tc2, td2)
         R2.cap = R.cap
         variant = as_written_variant(R2, params2, view2, rc2, opt2, tc2, td2)
-    log("tracking 640x480 / 100k")
-    tracking = tracking_run()
-    tracking_reuse = tracking_run(reuse_lists=True)
-    tracking_prune = tracking_run(mask_prune=True)
+    tracking = tracking_reuse = tracking_prune = None
+    if not args.no_tracking:
+        log("tracking 640x480 / 100k")
+        tracking = tracking_run()
+        tracking_reuse = tracking_run(reuse_lists=True)
+        tracking_prune = tracking_run(mask_prune=True)
     serve = None
     if args.serve_seconds > 0:
         serve = {}

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
         const float al = contrib ? f.alpha : 0.f;
         const float om = contrib ? f.om : 1.f;
         const float rom = __builtin_amdgcn_rcpf(om);
-        const float Tj = contrib ? Tc * rom : Tc;       // T before this fragment
+        const float Tj = Tc * rom;                     // T before this fragment (rcp(1) = 1)
         const float w = al * Tj;
         // (colour, depth) of the fragment dotted with the upstream gradient
         float cg = col.x * g0;
