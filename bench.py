@@ -318,12 +318,14 @@ def cpu_baseline(sc, cam, sample=192, seed=5):
             "seconds": dt}
 
 
-def serving_run(seconds, warmup_s, downsample, mode, seed=4242, rate=30.0):
+def serving_run(seconds, warmup_s, downsample, mode, seed=4242, rate=30.0, async_mapping=False,
+                map_every=1, prune=False, prune_ratio=0.1, max_map_batch=16):
     """The 16-session serving mix on a Poisson trace (rate Hz per session)."""
     from paper_2510_06644_amd import serving
     specs = serving.serving_mix()
-    ex = serving.GpuExecutor(0)
-    cfg = serving.ServeConfig(mode=mode, downsample=downsample)
+    ex = serving.GpuExecutor(0, prune=prune, prune_ratio=prune_ratio)
+    cfg = serving.ServeConfig(mode=mode, downsample=downsample, async_mapping=async_mapping,
+                              map_every=map_every, max_map_batch=max_map_batch)
     eng = serving.Engine(specs, ex, cfg)
     eng.preopen()
     ex.warmup(specs, iters=1)
@@ -438,6 +440,14 @@ def main():
                           rate=rate)
         rep["rate_hz_per_session"] = rate
         serve["batched_downsampled_60pct_load"] = rep
+        # the paper's full algorithm at 30 Hz: downsampling (Sec. 4.2), pruning
+        # per tracked frame (Sec. 4.1), keyframe mapping as a background job
+        # (a frame's latency is the time to its pose), batched and one at a time
+        for mode in ("batched", "serial"):
+            log(f"serving {mode} with pruning and asynchronous mapping")
+            rep = serving_run(args.serve_seconds, min(0.5, args.serve_seconds / 4), True, mode,
+                              async_mapping=True, map_every=4, prune=True)
+            serve[f"rtgs_{mode}"] = rep
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")

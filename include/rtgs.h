@@ -70,7 +70,8 @@ extern "C" {
 #define RTGS_GRAD_SCORE      16   /* without RTGS_GRAD_MAP: write g_means and
                                      g_cov3d only, the inputs of the
                                      importance score of Sec. 4.1 (the raster
-                                     pass of the pose-only backward)          */
+                                     pass of the pose-only backward); a
+                                     session passing neither is skipped       */
 
 /* ---- downsampled rendering (Sec. 4.2) ----
  * A frame downsampled to one pixel in 2^j (j = 2, 3, 4; 1 also accepted) is
@@ -257,6 +258,26 @@ int32_t loss_l1_grad(const float* color, const float* depth,
                      float w_depth, float* dL_dcolor, float* dL_ddepth,
                      void* stream);
 
+/* loss_l1_grad for several frames (e.g. the sessions of one batched
+ * iteration): items is a HOST array of n_items; each entry has the meaning
+ * of the single-frame arguments (its own size, mask and count).  One launch
+ * per 32 items.  Errors: as loss_l1_grad. */
+typedef struct rtgs_loss_item {
+  const float* color;
+  const float* depth;
+  const float* target_color;
+  const float* target_depth;
+  const uint8_t* pixel_mask;
+  const int32_t* n_active_dev;
+  float* dL_dcolor;
+  float* dL_ddepth;
+  int32_t width;
+  int32_t height;
+} rtgs_loss_item;
+
+int32_t loss_l1_grad_batched(const rtgs_loss_item* items, int32_t n_items,
+                             float w_color, float w_depth, void* stream);
+
 /* Parameter update of the mapping stage: the Gaussian gradients of Step 5
  * update the 3D Gaussian parameters (Sec. 3.1).  The paper names no
  * optimiser; this is Adam without weight decay.  For each group (a HOST
@@ -332,9 +353,10 @@ int32_t prune_by_grad(rtgs_handle_t h, const float* g_means,
  * permanently removed.  compact_by_mask copies the rows i with drop[i] == 0
  * of each item, in index order, to the front of its dst: row k of dst is
  * the k-th kept row of src.  items is a HOST array of n_items
- * (<= RTGS_COMPACT_MAX_ITEMS); src and dst are device arrays of n rows of
- * row_bytes (> 0) each, dst not overlapping src, 4-byte aligned when
- * row_bytes is a multiple of 4; dst needs room for the kept rows only.
+ * (<= RTGS_COMPACT_MAX_ITEMS); src is a device array of n rows of row_bytes
+ * (> 0) each, dst one of dst_rows rows (kept rows past dst_rows are not
+ * written), the two not overlapping, 4-byte aligned when row_bytes is a
+ * multiple of 4.
  * drop: device uint8 [n]; n_kept (device int32) receives the kept count.
  * scratch: device memory of rtgs_compact_scratch_size(n) bytes.  n = 0 is a
  * no-op that writes n_kept = 0 (src and dst may then be NULL).
@@ -344,6 +366,7 @@ typedef struct rtgs_compact_item {
   const void* src;
   void* dst;
   int32_t row_bytes;
+  int32_t dst_rows;
 } rtgs_compact_item;
 
 uint64_t rtgs_compact_scratch_size(int32_t n);

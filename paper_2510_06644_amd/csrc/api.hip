@@ -250,8 +250,9 @@ int32_t check_session(const rtgs_session& s, int idx, bool fwd, int32_t flags) {
       return fail(RTGS_ERR_INVALID_ARG, "session %d: POSE needs g_pose6 and/or g_viewmat", idx);
     if ((flags & RTGS_GRAD_COV3D) && (!(flags & RTGS_GRAD_MAP) || (g.n > 0 && !s.g_cov3d)))
       return fail(RTGS_ERR_INVALID_ARG, "session %d: COV3D needs MAP and g_cov3d", idx);
-    if ((flags & RTGS_GRAD_SCORE) && g.n > 0 && (!s.g_means || !s.g_cov3d))
-      return fail(RTGS_ERR_INVALID_ARG, "session %d: SCORE needs g_means and g_cov3d", idx);
+    if ((flags & RTGS_GRAD_SCORE) && !(flags & RTGS_GRAD_MAP) && (!s.g_means != !s.g_cov3d))
+      return fail(RTGS_ERR_INVALID_ARG, "session %d: SCORE takes both g_means and g_cov3d "
+                  "(or neither, to skip the session)", idx);
   }
   return RTGS_OK;
 }
@@ -670,6 +671,41 @@ int32_t loss_l1_grad(const float* color, const float* depth, const float* target
   return RTGS_OK;
 }
 
+int32_t loss_l1_grad_batched(const rtgs_loss_item* items, int32_t n_items, float w_color,
+                             float w_depth, void* stream) {
+  if (n_items < 0 || (n_items > 0 && !items))
+    return fail(RTGS_ERR_INVALID_ARG, "bad item list (n_items = %d)", n_items);
+  if (!std::isfinite(w_color) || !std::isfinite(w_depth))
+    return fail(RTGS_ERR_INVALID_ARG, "weights must be finite");
+  for (int i = 0; i < n_items; ++i) {
+    const rtgs_loss_item& it = items[i];
+    if (it.width <= 0 || it.height <= 0)
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: image %d x %d", i, it.width, it.height);
+    if (!it.color || !it.depth || !it.target_color || !it.target_depth || !it.dL_dcolor ||
+        !it.dL_ddepth)
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: null image or gradient", i);
+    if (it.pixel_mask && !it.n_active_dev)
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: a pixel mask needs its active-pixel count", i);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int first = 0; first < n_items; first += kLossMaxItems) {
+    LossBatchArgs a{};
+    int blocks = 0;
+    for (int i = first; i < n_items && i < first + kLossMaxItems; ++i) {
+      const rtgs_loss_item& it = items[i];
+      LossItemDev& d = a.item[a.n++];
+      d.a = LossArgs{it.color, it.depth, it.target_color, it.target_depth, it.pixel_mask,
+                     it.n_active_dev, it.dL_dcolor, it.dL_ddepth, it.width, it.height,
+                     w_color, w_depth};
+      d.block_base = blocks;
+      blocks += (int)(((int64_t)it.width * it.height + 255) / 256);
+    }
+    hipError_t e = launch_l1_grad_batched(a, blocks, st);
+    if (e != hipSuccess) return hip_fail(e, "loss_l1_grad_batched launch");
+  }
+  return RTGS_OK;
+}
+
 int32_t pose_update(const rtgs_pose_item* items, int32_t n, double beta1, double beta2,
                     double eps, void* stream) {
   if (n < 0 || (n > 0 && !items)) return fail(RTGS_ERR_INVALID_ARG, "bad item list (n = %d)", n);
@@ -729,11 +765,14 @@ int32_t compact_by_mask(const uint8_t* drop, int32_t n, const rtgs_compact_item*
   CompactArgs a{};
   for (int i = 0; i < n_items; ++i) {
     const rtgs_compact_item& it = items[i];
-    if ((n > 0 && (!it.src || !it.dst)) || it.row_bytes <= 0)
-      return fail(RTGS_ERR_INVALID_ARG, "item %d: null array or row_bytes %d", i, it.row_bytes);
-    const uint64_t bytes = (uint64_t)n * (uint64_t)it.row_bytes;
+    if ((n > 0 && !it.src) || (it.dst_rows > 0 && !it.dst) || it.row_bytes <= 0 ||
+        it.dst_rows < 0)
+      return fail(RTGS_ERR_INVALID_ARG, "item %d: null array, row_bytes %d or dst_rows %d", i,
+                  it.row_bytes, it.dst_rows);
+    const uint64_t sb = (uint64_t)n * (uint64_t)it.row_bytes;
+    const uint64_t db = (uint64_t)it.dst_rows * (uint64_t)it.row_bytes;
     const uintptr_t s0 = (uintptr_t)it.src, d0 = (uintptr_t)it.dst;
-    if (n > 0 && s0 < d0 + bytes && d0 < s0 + bytes)
+    if (sb > 0 && db > 0 && s0 < d0 + db && d0 < s0 + sb)
       return fail(RTGS_ERR_INVALID_ARG, "item %d: dst overlaps src", i);
     if (it.row_bytes % 4 == 0 && ((s0 | d0) & 3u))
       return fail(RTGS_ERR_INVALID_ARG, "item %d: rows of %d bytes need 4-byte alignment", i,
@@ -741,6 +780,7 @@ int32_t compact_by_mask(const uint8_t* drop, int32_t n, const rtgs_compact_item*
     a.item[i].src = static_cast<const unsigned char*>(it.src);
     a.item[i].dst = static_cast<unsigned char*>(it.dst);
     a.item[i].row_bytes = it.row_bytes;
+    a.item[i].dst_rows = it.dst_rows;
   }
   a.n_items = n_items;
   a.n = n;

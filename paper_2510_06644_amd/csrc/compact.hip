@@ -67,6 +67,7 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact_scatter(CompactArgs a
   pos += (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
   for (int k = 0; k < a.n_items; ++k) {
     const CompactItemDev& it = a.item[k];
+    if ((int64_t)pos >= it.dst_rows) continue;
     const int rb = it.row_bytes;
     const unsigned char* src = it.src + (int64_t)i * rb;
     unsigned char* dst = it.dst + (int64_t)pos * rb;

@@ -9,11 +9,12 @@
 namespace rtgs {
 namespace {
 
+static_assert(sizeof(LossBatchArgs) <= 4000, "loss table must fit the kernel arguments");
+
 __device__ __forceinline__ float sgn(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
-__global__ __launch_bounds__(256) void k_l1_grad(LossArgs a) {
+__device__ __forceinline__ void l1_grad_pixel(const LossArgs& a, int64_t p) {
   const int64_t hw = (int64_t)a.w * a.h;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= hw) return;
   const float n = a.n_active ? fmaxf((float)*a.n_active, 1.f) : (float)hw;
   const float sc = a.w_color / (3.f * n), sd = a.w_depth / n;
@@ -26,6 +27,23 @@ __global__ __launch_bounds__(256) void k_l1_grad(LossArgs a) {
   a.g_depth[p] = m * sd * sgn(a.depth[p] - a.t_depth[p]);
 }
 
+__global__ __launch_bounds__(256) void k_l1_grad(LossArgs a) {
+  l1_grad_pixel(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Block b belongs to the last item whose block_base <= b.
+__global__ __launch_bounds__(256) void k_l1_grad_batched(LossBatchArgs a) {
+  int lo = 0, hi = a.n - 1;
+  const int b = (int)blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.item[mid].block_base <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const LossItemDev& it = a.item[lo];
+  l1_grad_pixel(it.a, (int64_t)(b - it.block_base) * 256 + threadIdx.x);
+}
+
 }  // namespace
 
 hipError_t launch_l1_grad(const LossArgs& a, hipStream_t st) {
@@ -33,6 +51,12 @@ hipError_t launch_l1_grad(const LossArgs& a, hipStream_t st) {
   if (hw <= 0) return hipSuccess;
   const int64_t blocks = (hw + 255) / 256;
   k_l1_grad<<<(unsigned)blocks, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_grad_batched(const LossBatchArgs& a, int total_blocks, hipStream_t st) {
+  if (a.n <= 0 || total_blocks <= 0) return hipSuccess;
+  k_l1_grad_batched<<<(unsigned)total_blocks, 256, 0, st>>>(a);
   return hipGetLastError();
 }
 

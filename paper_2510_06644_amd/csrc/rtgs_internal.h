@@ -235,6 +235,18 @@ struct LossArgs {
 };
 hipError_t launch_l1_grad(const LossArgs& a, hipStream_t st);
 
+// Several frames' loss gradients in one launch (up to kLossMaxItems).
+constexpr int kLossMaxItems = 32;
+struct LossItemDev {
+  LossArgs a;
+  int32_t block_base;       // first block of this item
+};
+struct LossBatchArgs {
+  LossItemDev item[kLossMaxItems];
+  int32_t n;
+};
+hipError_t launch_l1_grad_batched(const LossBatchArgs& a, int total_blocks, hipStream_t st);
+
 // Pose update of up to kPoseMaxItems sessions in one launch.
 constexpr int kPoseMaxItems = 48;
 struct PoseItemDev {
@@ -263,6 +275,7 @@ struct CompactItemDev {
   const unsigned char* src;
   unsigned char* dst;
   int32_t row_bytes;
+  int32_t dst_rows;
 };
 struct CompactArgs {
   CompactItemDev item[kCompactMaxItems];

@@ -13,6 +13,7 @@ pair-capacity management on top.
 from __future__ import annotations
 
 import ctypes
+import math
 import dataclasses
 import os
 import threading
@@ -49,7 +50,7 @@ EXPORTS = (
     "render_bwd_batched", "prune_by_grad", "downsample_mask", "rtgs_downsample_log2_ratio",
     "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum", "rtgs_profile_enable",
     "rtgs_profile_read", "adam_step", "loss_l1_grad", "pose_update", "compact_by_mask",
-    "rtgs_compact_scratch_size", "rtgs_tile_rects", "tile_pair_change",
+    "rtgs_compact_scratch_size", "rtgs_tile_rects", "tile_pair_change", "loss_l1_grad_batched",
 )
 
 vp = ctypes.c_void_p
@@ -59,8 +60,14 @@ u64 = ctypes.c_uint64
 f32 = ctypes.c_float
 
 
+class CLossItem(ctypes.Structure):
+    _fields_ = [("color", vp), ("depth", vp), ("target_color", vp), ("target_depth", vp),
+                ("pixel_mask", vp), ("n_active_dev", vp), ("dL_dcolor", vp), ("dL_ddepth", vp),
+                ("width", i32), ("height", i32)]
+
+
 class CCompactItem(ctypes.Structure):
-    _fields_ = [("src", vp), ("dst", vp), ("row_bytes", i32)]
+    _fields_ = [("src", vp), ("dst", vp), ("row_bytes", i32), ("dst_rows", i32)]
 
 
 class CGaussians(ctypes.Structure):
@@ -134,6 +141,7 @@ def lib():
                                           vp, vp]
             L.rtgs_tile_rects.argtypes = [i32, i32, i32, i32, i64, vp, u64, vp, vp]
             L.tile_pair_change.argtypes = [vp, vp, vp, i32, vp, vp]
+            L.loss_l1_grad_batched.argtypes = [ctypes.POINTER(CLossItem), i32, f32, f32, vp]
             L.pose_update.argtypes = [ctypes.POINTER(CPoseItem), i32, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, vp]
             L.loss_l1_grad.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp]
@@ -329,6 +337,27 @@ def prune_by_grad(handle, g_means, g_cov3d, visible, mask_in, lam, max_ratio, ma
                                _p(score_out), _stream(stream)))
 
 
+def loss_l1_grad_batched(items, w_color=1.0, w_depth=0.5, stream=None):
+    """items: iterable of (color, depth, target_color, target_depth, dL_dcolor,
+    dL_ddepth, pixel_mask or None, n_active or None); loss_l1_grad for each,
+    one launch per 32 frames."""
+    items = list(items)
+    arr = (CLossItem * max(len(items), 1))()
+    for k, (c, d, tc, td, gc, gd, mask, cnt) in enumerate(items):
+        _, h, w = c.shape
+        for t, shp in ((c, (3, h, w)), (tc, (3, h, w)), (gc, (3, h, w)), (d, (h, w)),
+                       (td, (h, w)), (gd, (h, w))):
+            _f32(t, shp, "loss image")
+        if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != (h, w)):
+            raise ValueError("pixel_mask must be uint8 [H, W]")
+        if mask is not None and cnt is None:
+            raise ValueError("a pixel mask needs its device active-pixel count")
+        arr[k] = CLossItem(*(t.data_ptr() if t is not None else None
+                             for t in (c, d, tc, td, mask, cnt, gc, gd)), w, h)
+    _check(lib().loss_l1_grad_batched(arr, len(items), float(w_color), float(w_depth),
+                                      _stream(stream)))
+
+
 RTGS_COMPACT_MAX_ITEMS = 24
 
 
@@ -347,9 +376,9 @@ def compact_by_mask(drop, pairs, n_kept, scratch=None, stream=None):
             raise ValueError("compact_by_mask: contiguous src / dst of one dtype")
         if src.shape[0] != n or src.shape[1:] != dst.shape[1:]:
             raise ValueError("compact_by_mask: src has n rows and dst the same row shape")
-        row = src[0].numel() * src.element_size() if n else max(src.element_size(), 1)
+        row = math.prod(src.shape[1:]) * src.element_size()
         _p(src), _p(dst)            # device, contiguous
-        arr[k] = CCompactItem(src.data_ptr(), dst.data_ptr(), row)
+        arr[k] = CCompactItem(src.data_ptr(), dst.data_ptr(), row, dst.shape[0])
     need = int(lib().rtgs_compact_scratch_size(n))
     if scratch is None:
         scratch = torch.empty(max(need, 4), dtype=torch.uint8, device=drop.device)

@@ -89,6 +89,34 @@ class Frame:
         return "track" if self.track_left > 0 else "map"
 
 
+@dataclasses.dataclass
+class MapJob:
+    """The mapping iterations of one keyframe, run beside the session's later
+    tracking frames when mapping is asynchronous (ServeConfig.async_mapping):
+    the keyframe's result (its pose) is ready when its tracking ends, and its
+    map update follows, as in keyframe-based SLAM systems that map in a
+    separate thread.  A newer keyframe of the session replaces a job that has
+    not started yet."""
+    session: int
+    index: int
+    arrival: float                  # the keyframe's arrival
+    created: float
+    map_left: int
+    frame: object                   # the keyframe (its target frame)
+    log2_ratio: int = 0
+    started: float = -1.0
+    done_event: object = None
+    done_time: float = -1.0
+
+    @property
+    def phase(self):
+        return "map"
+
+    @property
+    def remaining(self):
+        return self.map_left
+
+
 def poisson_trace(n_sessions, rate_hz, duration_s, seed):
     """Per-session exponential inter-arrival times; list of (t, session, index)
     sorted by time."""
@@ -117,6 +145,13 @@ class ServeConfig:
     hbm_budget: float = 200e9       # resident maps + optimiser state (bytes)
     ws_budget: float = 40e9         # per-step workspace (bytes)
     mode: str = "batched"           # or "serial"
+    # keyframe mapping as a per-session background job (MapJob); a frame's
+    # latency is then the time to its pose (end of tracking)
+    async_mapping: bool = False
+    # with async_mapping: while tracking frames are in flight, map jobs advance
+    # on one engine step in map_every (tracking first); 1 = every step
+    map_every: int = 1
+    max_map_batch: int = 16         # map jobs in flight at once (async_mapping)
 
 
 # --------------------------------------------------------------------------- engine
@@ -140,6 +175,10 @@ class Engine:
         self.iters = 0
         self.batch_sizes = []
         self.last_key = [-1] * len(self.specs)
+        self.map_pending = {}                  # session -> MapJob not started
+        self.map_active = []
+        self.map_finished = []
+        self.map_superseded = 0
 
     # ---- admission -------------------------------------------------------
     def _try_open(self, s):
@@ -177,10 +216,12 @@ class Engine:
             j = _log2_ratio(index, k, self.cfg.m)
         if key:
             self.last_key[s] = index
-        self.pending.append(Frame(s, index, t, key, self.cfg.track_iters,
-                                  self.cfg.map_iters if key else 0, j))
+        maps = self.cfg.map_iters if key and not self.cfg.async_mapping else 0
+        self.pending.append(Frame(s, index, t, key, self.cfg.track_iters, maps, j))
 
     def _admit(self, now):
+        if self.cfg.async_mapping and self.cfg.mode == "serial" and self.map_active:
+            return                            # one item at a time
         cap = 1 if self.cfg.mode == "serial" else self.cfg.max_batch
         ws = sum(self.ex.step_bytes(self.specs[f.session], f) for f in self.active)
         busy = {f.session for f in self.active}
@@ -204,9 +245,38 @@ class Engine:
             ws += need
         keep.extend(self.pending)
         self.pending = keep
+        if self.cfg.async_mapping:
+            self._admit_maps(now)
+
+    def _admit_maps(self, now):
+        serial = self.cfg.mode == "serial"
+        if serial and (self.active or self.pending or self.map_active):
+            return                            # one item at a time, tracking first
+        cap = 1 if serial else min(self.cfg.max_batch, self.cfg.max_map_batch)
+        ws = sum(self.ex.step_bytes(self.specs[j.session], j) for j in self.map_active)
+        busy = {j.session for j in self.map_active}
+        for s in sorted(self.map_pending, key=lambda v: self.map_pending[v].created):
+            if len(self.map_active) >= cap:
+                break
+            if s in busy:
+                continue
+            j = self.map_pending[s]
+            need = self.ex.step_bytes(self.specs[s], j)
+            if ws + need > self.cfg.ws_budget and self.map_active:
+                continue
+            if not self._try_open(s):
+                continue
+            del self.map_pending[s]
+            j.started = now
+            self.ex.start_map(j, self.specs[s])
+            self.map_active.append(j)
+            busy.add(s)
+            ws += need
 
     # ---- one engine step ---------------------------------------------------
     def step(self, now):
+        if self.cfg.async_mapping:
+            return self._step_async(now)
         self._admit(now)
         if not self.active:
             return False
@@ -238,6 +308,49 @@ class Engine:
         self.active = still
         return True
 
+    def _step_async(self, now):
+        """One iteration of every admitted tracking frame, then one of every
+        admitted keyframe map job."""
+        self._admit(now)
+        if not self.active and not self.map_active:
+            return False
+        map_turn = not self.active or self.steps % max(1, self.cfg.map_every) == 0
+        for phase, group in (("track", self.active), ("map", self.map_active)):
+            if not group or (phase == "map" and not map_turn):
+                continue
+            ev = self.ex.run_iteration(phase, group, [self.specs[x.session] for x in group])
+            for x in group:
+                if phase == "track":
+                    x.track_left -= 1
+                else:
+                    x.map_left -= 1
+                if x.remaining == 0:
+                    x.done_event = ev
+            self.iters += len(group)
+        self.steps += 1
+        self.batch_sizes.append(len(self.active) + len(self.map_active))
+        still = []
+        for f in self.active:
+            if f.remaining > 0:
+                still.append(f)
+                continue
+            self.ex.finish_frame(f, self.specs[f.session])
+            self.finished.append(f)
+            if f.keyframe and self.cfg.map_iters > 0:
+                if f.session in self.map_pending:
+                    self.map_superseded += 1
+                self.map_pending[f.session] = MapJob(f.session, f.index, f.arrival, now,
+                                                     self.cfg.map_iters, f)
+        self.active = still
+        still = []
+        for j in self.map_active:
+            if j.remaining > 0:
+                still.append(j)
+            else:
+                self.map_finished.append(j)
+        self.map_active = still
+        return True
+
     def preopen(self):
         """Open (make resident) every session the HBM budget admits."""
         for s in range(len(self.specs)):
@@ -257,14 +370,14 @@ class Engine:
                 self.submit(t, s, idx)
                 i += 1
             if not self.step(now):
-                if i >= len(trace) and not self.pending:
+                if i >= len(trace) and not self.pending and not self.map_pending:
                     break
                 if i < len(trace):
                     wait = trace[i][0] - (self.clock() - t0)
                     if wait > 0:
                         self.ex.idle(wait)
         self.ex.sync()
-        for f in self.finished:
+        for f in self.finished + self.map_finished:
             f.done_time = self.ex.event_time(f.done_event)
         return self.report(warmup_s=warmup_s)
 
@@ -276,7 +389,8 @@ class Engine:
             key = f"{self.specs[f.session].width}x{self.specs[f.session].height}"
             lat.setdefault(key, []).append(f.done_time - f.arrival)
         every = [x for v in lat.values() for x in v]
-        span = max((f.done_time for f in self.finished), default=0.0)
+        span = max((f.done_time for f in self.finished + self.map_finished), default=0.0)
+        maps = [j.done_time - j.arrival for j in self.map_finished if j.arrival >= warmup_s]
 
         def pct(v, q):
             return float(np.percentile(np.asarray(v) * 1e3, q)) if v else float("nan")
@@ -291,6 +405,9 @@ class Engine:
             "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
             "span_s": span,
             "max_resident_bytes": self.max_resident,
+            "async_mapping": self.cfg.async_mapping,
+            "map_jobs": len(self.map_finished), "map_superseded": self.map_superseded,
+            "map_p50_ms": pct(maps, 50), "map_p99_ms": pct(maps, 99),
         }
 
 
@@ -344,6 +461,9 @@ class FakeExecutor:
     def finish_frame(self, f, spec):
         pass
 
+    def start_map(self, job, spec):
+        pass
+
     def run_iteration(self, phase, frames, specs):
         cost = self.launch_s
         for f, sp in zip(frames, specs):
@@ -370,7 +490,8 @@ class GpuExecutor:
     """Runs sessions on the HIP library with batched launches."""
 
     def __init__(self, device=0, lr_pose=(1e-3, 3e-3), track_noise_seed=0, n_targets=4,
-                 capacity_factor=2.0):
+                 capacity_factor=2.0, prune=False, prune_ratio=0.1, prune_cap=0.5,
+                 prune_lam=0.8):
         import torch
 
         from . import rtgs
@@ -385,6 +506,14 @@ class GpuExecutor:
         self.base_event = None
         self.base_wall = None
         self.overflows = 0
+        # adaptive pruning (Sec. 4.1) per tracked frame: the frame's first
+        # iteration scores the map and masks up to prune_ratio of the visible
+        # Gaussians, its other iterations render without them, and the frame's
+        # end removes them; never more than prune_cap of the initial map
+        self.prune = prune
+        self.prune_ratio = prune_ratio
+        self.prune_cap = prune_cap
+        self.prune_lam = prune_lam
 
     # ---- footprint -----------------------------------------------------------
     def session_bytes(self, spec):
@@ -435,16 +564,25 @@ class GpuExecutor:
             viewmat=torch.eye(3, 4, dtype=torch.float32, device=self.dev).contiguous(),
             m=torch.zeros(6, device=self.dev), v=torch.zeros(6, device=self.dev), t=0,
             last_T=None,
-            out=dict(color=torch.empty(3, spec.height, spec.width, device=self.dev),
-                     depth=torch.empty(spec.height, spec.width, device=self.dev),
-                     alpha=torch.empty(spec.height, spec.width, device=self.dev),
-                     final_T=torch.empty(spec.height, spec.width, device=self.dev),
-                     last_idx=torch.empty(spec.height, spec.width, dtype=torch.int32,
-                                          device=self.dev)),
+            out=self._outs(spec), out_map=self._outs(spec),
             gpose=torch.zeros(6, device=self.dev),
+            n0=spec.n, removed=0, mask=None,
+            visible=torch.empty(spec.n, dtype=torch.uint8, device=self.dev),
+            mask_count=torch.zeros(1, dtype=torch.int32, device=self.dev),
+            h_count=torch.zeros(1, dtype=torch.int32).pin_memory(),
+            ev_count=torch.cuda.Event(),
             pmask=torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev),
             pcount=torch.zeros(1, dtype=torch.int32, device=self.dev))
         torch.cuda.synchronize(self.dev)
+
+    def _outs(self, spec):
+        torch = self.torch
+        return dict(color=torch.empty(3, spec.height, spec.width, device=self.dev),
+                    depth=torch.empty(spec.height, spec.width, device=self.dev),
+                    alpha=torch.empty(spec.height, spec.width, device=self.dev),
+                    final_T=torch.empty(spec.height, spec.width, device=self.dev),
+                    last_idx=torch.empty(spec.height, spec.width, dtype=torch.int32,
+                                         device=self.dev))
 
     def close_session(self, s):
         """Evict: the session's tensors and optimiser state move to host memory."""
@@ -453,10 +591,13 @@ class GpuExecutor:
             return
         S["params"] = [p.cpu() for p in S["params"]]
         S["opt"].to("cpu").rebind(S["params"])
-        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount"):
+        if S["mask"] is not None:
+            self._remove_masked(S)
+        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount", "visible", "mask_count"):
             S[k] = S[k].cpu()
         S["targets"] = [(c.cpu(), d.cpu()) for c, d in S["targets"]]
         S["out"] = {k: v.cpu() for k, v in S["out"].items()}
+        S["out_map"] = {k: v.cpu() for k, v in S["out_map"].items()}
         S["last_T"] = None
         S["offloaded"] = True
 
@@ -465,15 +606,39 @@ class GpuExecutor:
         S = self.sessions[s]
         S["params"] = [p.to(self.dev) for p in S["params"]]
         S["opt"].to(self.dev).rebind(S["params"])
-        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount"):
+        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount", "visible", "mask_count"):
             S[k] = S[k].to(self.dev)
         S["targets"] = [(c.to(self.dev), d.to(self.dev)) for c, d in S["targets"]]
         S["out"] = {k: v.to(self.dev) for k, v in S["out"].items()}
+        S["out_map"] = {k: v.to(self.dev) for k, v in S["out_map"].items()}
         S["offloaded"] = False
 
     # ---- frames ----------------------------------------------------------------
+    def _remove_masked(self, S):
+        """Permanent removal of the masked Gaussians (map, Adam moments)."""
+        torch, rtgs = self.torch, self.rtgs
+        S["ev_count"].synchronize()             # recorded a frame ago
+        n = S["params"][0].shape[0]
+        k = n - int(S["h_count"].item())
+        mask, S["mask"] = S["mask"], None
+        if k >= n:
+            return
+        opt = S["opt"]
+        srcs = list(S["params"]) + list(opt.exp_avg) + list(opt.exp_avg_sq)
+        outs = [torch.empty((k,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device)
+                for t in srcs]
+        rtgs.compact_by_mask(mask, list(zip(srcs, outs)), S["mask_count"])
+        np_ = len(S["params"])
+        S["params"] = outs[:np_]
+        opt.rebind(S["params"])
+        opt.exp_avg = outs[np_:2 * np_]
+        opt.exp_avg_sq = outs[2 * np_:]
+        S["visible"] = torch.empty(k, dtype=torch.uint8, device=self.dev)
+        S["removed"] += n - k
+
     def start_frame(self, f, spec):
         S = self.sessions[f.session]
+        f.first = self.prune
         f.target = S["targets"][f.index % self.n_targets]
         f.mask = None
         if f.log2_ratio > 0 and S["last_T"] is not None:
@@ -483,6 +648,18 @@ class GpuExecutor:
     def finish_frame(self, f, spec):
         S = self.sessions[f.session]
         S["last_T"] = S["out"]["final_T"]
+        if S["mask"] is not None:
+            self._remove_masked(S)
+        if f.keyframe:
+            f.pose_end = S["viewmat"].clone()       # the keyframe's tracked pose
+
+    def start_map(self, job, spec):
+        """A keyframe's map job renders at the keyframe's tracked pose, into
+        buffers of its own (the session's next frames track meanwhile)."""
+        S = self.sessions[job.session]
+        job.target = job.frame.target
+        job.mask = None
+        job.viewmat = job.frame.pose_end
 
     # ---- one iteration for a group of frames -----------------------------------
     def run_iteration(self, phase, frames, specs):
@@ -491,9 +668,12 @@ class GpuExecutor:
         cap = 0
         for f in frames:
             S = self.sessions[f.session]
-            o = S["out"]
+            job = isinstance(f, MapJob)
+            o = S["out_map"] if job else S["out"]
             items.append(dict(scene=tuple(p.detach() for p in S["params"]),
-                              viewmat=S["viewmat"], cam=S["cam"], pixel_mask=f.mask,
+                              viewmat=f.viewmat if job else S["viewmat"], cam=S["cam"],
+                              pixel_mask=f.mask, gauss_mask=S["mask"],
+                              visible=S["visible"] if phase == "track" else None,
                               sample_log2=f.log2_ratio if f.mask is not None else 0,
                               color=o["color"], depth=o["depth"], alpha=o["alpha"],
                               final_T=o["final_T"], last_idx=o["last_idx"]))
@@ -504,20 +684,34 @@ class GpuExecutor:
         ws = torch.empty(rtgs.rtgs_workspace_size_batched(ns, ws_, hs_, cap),
                          dtype=torch.uint8, device=self.dev)
         rtgs.render_fwd_batched(self.handle, items, ws, cap)
-        # L1 colour + 0.5 L1 depth over the active pixels of each frame
+        # L1 colour + 0.5 L1 depth over the active pixels of each frame, one
+        # launch for the group
+        losses = []
         for f, it in zip(frames, items):
             S = self.sessions[f.session]
             gc = torch.empty_like(it["color"])
             gd = torch.empty_like(it["depth"])
-            rtgs.loss_l1_grad(it["color"], it["depth"], f.target[0], f.target[1], gc, gd,
-                              pixel_mask=f.mask,
-                              n_active=S["pcount"] if f.mask is not None else None)
+            losses.append((it["color"], it["depth"], f.target[0], f.target[1], gc, gd, f.mask,
+                           S["pcount"] if f.mask is not None else None))
             it["dL_dcolor"] = gc
             it["dL_ddepth"] = gd
+        rtgs.loss_l1_grad_batched(losses)
         if phase == "track":
+            flags = rtgs.RTGS_GRAD_POSE
+            scored = []
             for f, it in zip(frames, items):
-                it["g_pose6"] = self.sessions[f.session]["gpose"]
-            rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=rtgs.RTGS_GRAD_POSE)
+                S = self.sessions[f.session]
+                it["g_pose6"] = S["gpose"]
+                if getattr(f, "first", False):
+                    n = S["params"][0].shape[0]
+                    it["g_means"] = torch.empty(n, 3, device=self.dev)
+                    it["g_cov3d"] = torch.empty(n, 6, device=self.dev)
+                    scored.append((f, it))
+                    flags |= rtgs.RTGS_GRAD_SCORE
+            rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=flags)
+            for f, it in scored:
+                self._mask_lowest(self.sessions[f.session], it)
+                f.first = False
             self._pose_step(frames)
         else:
             grads = []
@@ -535,6 +729,17 @@ class GpuExecutor:
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         return ev
+
+    def _mask_lowest(self, S, it):
+        n = S["params"][0].shape[0]
+        budget = max(0.0, self.prune_cap * S["n0"] - S["removed"])
+        ratio = min(self.prune_ratio, budget / max(n, 1), 0.5)
+        mask = self.torch.zeros(n, dtype=self.torch.uint8, device=self.dev)
+        self.rtgs.prune_by_grad(self.handle, it["g_means"], it["g_cov3d"], S["visible"], None,
+                                self.prune_lam, ratio, mask, S["mask_count"])
+        S["h_count"].copy_(S["mask_count"], non_blocking=True)
+        S["ev_count"].record()
+        S["mask"] = mask
 
     def _pose_step(self, frames, b1=0.9, b2=0.999, eps=1e-8):
         """Adam on xi = (rho, phi) for every session of the group, then the
@@ -561,6 +766,7 @@ class GpuExecutor:
                 self.start_frame(f, spec)
                 for _ in range(iters):
                     self.run_iteration(phase, [f], [spec])
+            self.sessions[s]["mask"] = None          # warm-up masks are not kept
         self.sync()
 
     def start_clock(self):

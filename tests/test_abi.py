@@ -83,7 +83,7 @@ def test_null_handle_and_bad_arguments_are_rejected_before_any_gpu_work():
     assert L.rtgs_selftest_wave_sum(None, None, -1, None) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.pose_update(None, -1, 0.9, 0.999, 1e-8, None) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.compact_by_mask(None, -1, None, 0, None, 0, None, None) == rtgs.RTGS_ERR_INVALID_ARG
-    items = (rtgs.CCompactItem * 1)(rtgs.CCompactItem(8, 8, 4))
+    items = (rtgs.CCompactItem * 1)(rtgs.CCompactItem(8, 8, 4, 10))
     scratch = ctypes.c_void_p(64)
     cnt = ctypes.c_void_p(128)
     # the same address as src and dst: overlap is refused on the host
@@ -91,13 +91,14 @@ def test_null_handle_and_bad_arguments_are_rejected_before_any_gpu_work():
                              None) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.compact_by_mask(ctypes.c_void_p(256), 10, items, 25, scratch, 64, cnt,
                              None) == rtgs.RTGS_ERR_INVALID_ARG
-    items2 = (rtgs.CCompactItem * 1)(rtgs.CCompactItem(1024, 4096, 4))
+    items2 = (rtgs.CCompactItem * 1)(rtgs.CCompactItem(1024, 4096, 4, 10))
     assert L.compact_by_mask(ctypes.c_void_p(256), 10, items2, 1, scratch, 0, cnt,
                              None) == rtgs.RTGS_ERR_WORKSPACE
     assert int(L.rtgs_compact_scratch_size(0)) == 4
     assert int(L.rtgs_compact_scratch_size(1024)) == 8
     assert int(L.rtgs_compact_scratch_size(1025)) == 12
     assert L.tile_pair_change(None, None, None, 5, None, None) == rtgs.RTGS_ERR_INVALID_ARG
+    assert L.loss_l1_grad_batched(None, 3, 1.0, 0.5, None) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.rtgs_tile_rects(4, 16, 16, 0, 1024, None, 0, None, None) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.pose_update(None, 0, 1.5, 0.999, 1e-8, None) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.adam_step(None, None, 0, 0.9, 0.999, 1e-8, None) == rtgs.RTGS_ERR_INVALID_ARG

@@ -56,3 +56,30 @@ def test_l1_gradient_rejects_mask_without_count():
         rtgs.loss_l1_grad(c, d, tc, td, torch.empty_like(c), torch.empty_like(d),
                           pixel_mask=torch.ones(8, 8, dtype=torch.uint8, device="cuda"))
     assert e.value.code == rtgs.RTGS_ERR_INVALID_ARG
+
+
+def test_batched_loss_equals_single_frame_calls():
+    """loss_l1_grad_batched over frames of different sizes, with and without
+    masks, gives bit for bit the single-frame results (34 frames: two
+    launches)."""
+    say("test_batched_loss_equals_single_frame_calls")
+    items, singles = [], []
+    for k in range(34):
+        h, w = 17 + 7 * (k % 5), 23 + 11 * (k % 3)
+        c, d, tc, td = (t.cuda() for t in _frames(h, w, 100 + k))
+        mask = cnt = None
+        if k % 2:
+            ft = torch.rand(h, w, generator=torch.Generator().manual_seed(k)).cuda()
+            mask = torch.empty(h, w, dtype=torch.uint8, device="cuda")
+            cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+            rtgs.downsample_mask(ft, 2, mask, cnt)
+        gc = torch.full((3, h, w), float("nan"), device="cuda")
+        gd = torch.full((h, w), float("nan"), device="cuda")
+        items.append((c, d, tc, td, gc, gd, mask, cnt))
+        sc, sd = torch.empty_like(gc), torch.empty_like(gd)
+        rtgs.loss_l1_grad(c, d, tc, td, sc, sd, pixel_mask=mask, n_active=cnt)
+        singles.append((sc, sd))
+    rtgs.loss_l1_grad_batched(items)
+    torch.cuda.synchronize()
+    for (c, d, tc, td, gc, gd, mask, cnt), (sc, sd) in zip(items, singles):
+        assert torch.equal(gc, sc) and torch.equal(gd, sd)

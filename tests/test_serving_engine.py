@@ -84,3 +84,36 @@ def test_downsampling_schedule_follows_keyframes():
     js = [f.log2_ratio for f in eng.pending]
     assert js == [0, 4, 3, 2, 2, 2, 2, 2, 0, 4, 3, 2]
     assert [f.keyframe for f in eng.pending][:9] == [True] + [False] * 7 + [True]
+
+
+def test_async_mapping_runs_keyframe_jobs_beside_tracking():
+    """Keyframe mapping as a background job: every frame finishes when its
+    tracking ends; each keyframe's job either runs (20 iterations) or is
+    replaced by the session's next keyframe before it starts; a session has
+    at most one job running; frame latency drops against mapping in line."""
+    cfg = ServeConfig(async_mapping=True)
+    eng, ex, rep = _run(cfg)
+    trace = serving.poisson_trace(16, 30.0, 3.0, 3)
+    assert len(eng.finished) == len(trace)
+    keys = sum(1 for f in eng.finished if f.keyframe)
+    assert rep["map_jobs"] + rep["map_superseded"] == keys
+    assert rep["map_jobs"] > 0
+    assert eng.iters == 10 * len(eng.finished) + 20 * rep["map_jobs"]
+    for phase, sessions in ex.log:
+        assert len(sessions) == len(set(sessions))
+    for j in eng.map_finished:
+        assert j.done_time >= j.arrival
+    _, _, sync = _run(ServeConfig())
+    assert rep["p99_ms"] < sync["p99_ms"]
+
+
+def test_async_mapping_serial_runs_one_item_at_a_time():
+    eng, ex, rep = _run(ServeConfig(mode="serial", async_mapping=True), duration=1.0,
+                        rate=5.0)
+    for phase, sessions in ex.log:
+        assert len(sessions) == 1
+    # no step runs a tracking frame and a map job together
+    steps = [len(x[1]) for x in ex.log]
+    assert sum(steps) == eng.iters and len(ex.log) == eng.steps
+    assert len(eng.finished) == len(serving.poisson_trace(16, 5.0, 1.0, 3))
+
