@@ -319,13 +319,15 @@ def cpu_baseline(sc, cam, sample=192, seed=5):
 
 
 def serving_run(seconds, warmup_s, downsample, mode, seed=4242, rate=30.0, async_mapping=False,
-                map_every=1, prune=False, prune_ratio=0.1, max_map_batch=16):
+                map_every=1, prune=False, prune_ratio=0.1, max_map_batch=16,
+                overlap_frames=False):
     """The 16-session serving mix on a Poisson trace (rate Hz per session)."""
     from paper_2510_06644_amd import serving
     specs = serving.serving_mix()
     ex = serving.GpuExecutor(0, prune=prune, prune_ratio=prune_ratio)
     cfg = serving.ServeConfig(mode=mode, downsample=downsample, async_mapping=async_mapping,
-                              map_every=map_every, max_map_batch=max_map_batch)
+                              map_every=map_every, max_map_batch=max_map_batch,
+                              overlap_frames=overlap_frames)
     eng = serving.Engine(specs, ex, cfg)
     eng.preopen()
     ex.warmup(specs, iters=1)
@@ -446,7 +448,8 @@ def main():
         for mode in ("batched", "serial"):
             log(f"serving {mode} with pruning and asynchronous mapping")
             rep = serving_run(args.serve_seconds, min(0.5, args.serve_seconds / 4), True, mode,
-                              async_mapping=True, map_every=4, prune=True)
+                              async_mapping=True, map_every=4, prune=True,
+                              overlap_frames=mode == "batched")
             serve[f"rtgs_{mode}"] = rep
     cpu = None
     if not args.no_cpu_baseline:

@@ -152,6 +152,9 @@ class ServeConfig:
     # on one engine step in map_every (tracking first); 1 = every step
     map_every: int = 1
     max_map_batch: int = 16         # map jobs in flight at once (async_mapping)
+    # a session's next frame may start before its previous frame's tracking
+    # ends; it starts from the session's latest pose estimate
+    overlap_frames: bool = False
 
 
 # --------------------------------------------------------------------------- engine
@@ -228,8 +231,8 @@ class Engine:
         keep = collections.deque()
         while self.pending and len(self.active) < cap:
             f = self.pending.popleft()
-            if f.session in busy:             # a session's frames run in order
-                keep.append(f)
+            if f.session in busy and not self.cfg.overlap_frames:
+                keep.append(f)                # a session's frames run in order
                 continue
             need = self.ex.step_bytes(self.specs[f.session], f)
             if ws + need > self.cfg.ws_budget and self.active:
@@ -566,7 +569,7 @@ class GpuExecutor:
             last_T=None,
             out=self._outs(spec), out_map=self._outs(spec),
             gpose=torch.zeros(6, device=self.dev),
-            n0=spec.n, removed=0, mask=None,
+            n0=spec.n, removed=0, mask=None, inflight=0, scoring=False,
             visible=torch.empty(spec.n, dtype=torch.uint8, device=self.dev),
             mask_count=torch.zeros(1, dtype=torch.int32, device=self.dev),
             h_count=torch.zeros(1, dtype=torch.int32).pin_memory(),
@@ -637,21 +640,36 @@ class GpuExecutor:
         S["removed"] += n - k
 
     def start_frame(self, f, spec):
+        """A frame tracks its own pose from the session's latest estimate, with
+        its own Adam state and output buffers (frames of one session may
+        overlap).  Pruning: the first frame of a mask window scores the map."""
+        torch = self.torch
         S = self.sessions[f.session]
-        f.first = self.prune
+        S["inflight"] += 1
+        f.first = self.prune and S["mask"] is None and not S["scoring"]
+        S["scoring"] = S["scoring"] or f.first
         f.target = S["targets"][f.index % self.n_targets]
+        f.viewmat = S["viewmat"].clone()
+        f.m = torch.zeros(6, device=self.dev)
+        f.v = torch.zeros(6, device=self.dev)
+        f.t = 0
+        f.gpose = torch.zeros(6, device=self.dev)
+        f.out = self._outs(spec)
         f.mask = None
+        f.pcount = None
         if f.log2_ratio > 0 and S["last_T"] is not None:
-            self.rtgs.downsample_mask(S["last_T"], f.log2_ratio, S["pmask"], S["pcount"])
-            f.mask = S["pmask"]
+            f.mask = torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev)
+            f.pcount = torch.zeros(1, dtype=torch.int32, device=self.dev)
+            self.rtgs.downsample_mask(S["last_T"], f.log2_ratio, f.mask, f.pcount)
 
     def finish_frame(self, f, spec):
         S = self.sessions[f.session]
-        S["last_T"] = S["out"]["final_T"]
-        if S["mask"] is not None:
+        S["viewmat"] = f.viewmat                    # the session's latest pose
+        S["last_T"] = f.out["final_T"]
+        f.pose_end = f.viewmat                      # a keyframe's tracked pose
+        S["inflight"] -= 1
+        if S["mask"] is not None and S["inflight"] == 0:
             self._remove_masked(S)
-        if f.keyframe:
-            f.pose_end = S["viewmat"].clone()       # the keyframe's tracked pose
 
     def start_map(self, job, spec):
         """A keyframe's map job renders at the keyframe's tracked pose, into
@@ -669,9 +687,9 @@ class GpuExecutor:
         for f in frames:
             S = self.sessions[f.session]
             job = isinstance(f, MapJob)
-            o = S["out_map"] if job else S["out"]
+            o = S["out_map"] if job else getattr(f, "out", S["out"])
             items.append(dict(scene=tuple(p.detach() for p in S["params"]),
-                              viewmat=f.viewmat if job else S["viewmat"], cam=S["cam"],
+                              viewmat=getattr(f, "viewmat", S["viewmat"]), cam=S["cam"],
                               pixel_mask=f.mask, gauss_mask=S["mask"],
                               visible=S["visible"] if phase == "track" else None,
                               sample_log2=f.log2_ratio if f.mask is not None else 0,
@@ -692,7 +710,7 @@ class GpuExecutor:
             gc = torch.empty_like(it["color"])
             gd = torch.empty_like(it["depth"])
             losses.append((it["color"], it["depth"], f.target[0], f.target[1], gc, gd, f.mask,
-                           S["pcount"] if f.mask is not None else None))
+                           getattr(f, "pcount", None) if f.mask is not None else None))
             it["dL_dcolor"] = gc
             it["dL_ddepth"] = gd
         rtgs.loss_l1_grad_batched(losses)
@@ -701,7 +719,7 @@ class GpuExecutor:
             scored = []
             for f, it in zip(frames, items):
                 S = self.sessions[f.session]
-                it["g_pose6"] = S["gpose"]
+                it["g_pose6"] = f.gpose
                 if getattr(f, "first", False):
                     n = S["params"][0].shape[0]
                     it["g_means"] = torch.empty(n, 3, device=self.dev)
@@ -740,16 +758,15 @@ class GpuExecutor:
         S["h_count"].copy_(S["mask_count"], non_blocking=True)
         S["ev_count"].record()
         S["mask"] = mask
+        S["scoring"] = False
 
     def _pose_step(self, frames, b1=0.9, b2=0.999, eps=1e-8):
-        """Adam on xi = (rho, phi) for every session of the group, then the
+        """Adam on xi = (rho, phi) for every frame of the group, then the
         re-linearisation T <- Exp(-step) T: one pose_update launch."""
         items = []
         for f in frames:
-            S = self.sessions[f.session]
-            S["t"] += 1
-            items.append((S["viewmat"], S["gpose"], S["m"], S["v"], self.lr_rho, self.lr_phi,
-                          S["t"]))
+            f.t += 1
+            items.append((f.viewmat, f.gpose, f.m, f.v, self.lr_rho, self.lr_phi, f.t))
         self.rtgs.pose_update(items, b1, b2, eps)
 
     # ---- clock ----------------------------------------------------------------
@@ -759,6 +776,7 @@ class GpuExecutor:
     def warmup(self, specs, iters=2):
         """One untimed tracking and mapping iteration per open session (first
         launches, allocator growth)."""
+        torch = self.torch
         for s in list(self.sessions):
             spec = self.sessions[s]["spec"]
             for phase in ("track", "map"):
@@ -766,7 +784,10 @@ class GpuExecutor:
                 self.start_frame(f, spec)
                 for _ in range(iters):
                     self.run_iteration(phase, [f], [spec])
-            self.sessions[s]["mask"] = None          # warm-up masks are not kept
+            S = self.sessions[s]                     # warm-up frames are not kept
+            S["mask"], S["scoring"], S["inflight"] = None, False, 0
+            S["viewmat"] = torch.eye(3, 4, dtype=torch.float32, device=self.dev).contiguous()
+            S["last_T"] = None
         self.sync()
 
     def start_clock(self):
