@@ -49,11 +49,24 @@ KERNEL_SOURCES = ("paper_2510_06644_amd/csrc/raster.hip", "paper_2510_06644_amd/
 
 
 def kernel_hash():
+    """Digest of what the raster kernels are compiled from: raster.hip, the
+    device helpers of rtgs_internal.h and the layouts of the structures they
+    read (session table, batch, workspace pointers, Gaussian record)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+            text = fh.read()
+        if f.endswith("rtgs_internal.h"):
+            src = text.decode()
+            parts = [m.group(0) for m in re.finditer(
+                r"struct (?:alignas\(\d+\) )?(?:SessionDev|Batch|WsPtrs|GaussRec)\b[^{]*\{.*?\n\};",
+                src, re.S)]
+            dev = src.find("// ---- device helpers ----")
+            parts.append(src[dev:] if dev >= 0 else src)
+            text = "\n".join(parts).encode()
+        h.update(text)
     return h.hexdigest()[:16]
 
 
