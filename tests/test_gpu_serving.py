@@ -113,3 +113,36 @@ def test_short_open_loop_trace_both_modes():
             f"{rep['p99_ms']:.1f} ms iters/s {rep['iters_per_s']:.0f} batch {rep['mean_batch']:.1f}")
         assert rep["frames"] == len(trace)
         assert rep["p50_ms"] > 0
+
+
+def test_pruned_async_overlapping_serving_keeps_maps_consistent():
+    """The served form of the algorithm: pruning per tracked frame, keyframe
+    mapping as a background job, overlapping frames.  Every frame finishes,
+    every keyframe's job runs or is replaced, each map loses some and at most
+    half of its Gaussians, and the map and Adam moments keep one row count
+    (the batch composition follows the wall clock, so two runs need not
+    match)."""
+    say("test_pruned_async_overlapping_serving_keeps_maps_consistent")
+    specs = [SessionSpec(320, 240, 20_000, "c0", 40 + k) for k in range(3)]
+    trace = serving.poisson_trace(len(specs), 60.0, 0.4, 13)
+    ex = GpuExecutor(0, n_targets=2, prune=True, prune_ratio=0.2)
+    cfg = ServeConfig(track_iters=4, map_iters=3, keyframe_every=3, downsample=True,
+                      async_mapping=True, map_every=2, overlap_frames=True)
+    eng = Engine(specs, ex, cfg)
+    rep = eng.run(trace)
+    say(f"  {rep['frames']} frames, {rep['map_jobs']} map jobs "
+        f"({rep['map_superseded']} replaced), p99 {rep['p99_ms']:.1f} ms")
+    assert rep["frames"] == len(trace)
+    keys = sum(1 for f in eng.finished if f.keyframe)
+    assert rep["map_jobs"] + rep["map_superseded"] == keys
+    ex.verify()
+    assert ex.overflows == 0
+    for s in range(len(specs)):
+        S = ex.sessions[s]
+        n = S["params"][0].shape[0]
+        assert S["n0"] // 2 <= n < S["n0"], (n, S["n0"])   # pruned, at most 50%
+        assert n == S["n0"] - S["removed"]
+        opt = S["opt"]
+        for t in list(S["params"]) + opt.exp_avg + opt.exp_avg_sq:
+            assert t.shape[0] == n and bool(torch.isfinite(t).all())
+        assert S["inflight"] == 0 and S["mask"] is None
