@@ -254,7 +254,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
   __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch], s_cn[kBwdBatch];
   __shared__ unsigned s_m[kBwdBatch];
-  __shared__ float s_part[4][kBwdBatch * kStride];
+  // per wave: kStride floats per entry, then one float that takes the
+  // reduce-scatter outputs no entry needs
+  __shared__ float s_part[4][kBwdBatch * kStride + 1];
   __shared__ int s_hi;
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
@@ -365,10 +367,18 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
         wave_reduce_scatter<NV>(v, x);
         if ((lane & 15) == 15) {
           const int row = lane >> 4;
+          // x[j] is value wave_scatter_index(NV, row, j) = that of j = 0, plus
+          // 2 j; an output that only even rows carry is written by odd rows
+          // (as 0) to the spare float, so every store is made by all four
+          // row ends at once
+          float* dst = part + k * kStride + wave_scatter_index(NV, row, 0);
 #pragma unroll
-          for (int j = 0; j < 3; ++j)
-            if ((row & 1) + 2 * j < NV / 2)
-              part[k * kStride + wave_scatter_index(NV, row, j)] = x[j];
+          for (int j = 0; j < 3; ++j) {
+            if (1 + 2 * j < NV / 2)
+              dst[2 * j] = x[j];
+            else if (2 * j < NV / 2)
+              ((row & 1) ? part + kBwdBatch * kStride - 2 * j : dst)[2 * j] = x[j];
+          }
         }
       };
       while (m) {

@@ -324,6 +324,9 @@ __device__ __forceinline__ float row_sum_to_lane15(float v) {
   v += dpp_f<kDppRowShr2, 0xf, true>(v);
   v += dpp_f<kDppRowShr4, 0xf, true>(v);
   v += dpp_f<kDppRowShr8, 0xf, true>(v);
+  // keep the last step a single DPP add in every lane: otherwise the add is
+  // sunk into the caller's lane-15-only branch as a separate move and add
+  asm volatile("" : "+v"(v));
   return v;
 }
 
