@@ -50,9 +50,14 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t k = k0 + 16 * j;
-        const float* p = W.partial + (first + k) * NV;
+        // a slot is NV floats at an 8-byte aligned offset: NV / 2 8-byte loads
+        const float2* p = reinterpret_cast<const float2*>(W.partial + (first + k) * NV);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[j][i] = k < n ? p[i] : 0.f;
+        for (int i = 0; i < NV / 2; ++i) {
+          const float2 x = k < n ? p[i] : make_float2(0.f, 0.f);
+          v[j][2 * i] = x.x;
+          v[j][2 * i + 1] = x.y;
+        }
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
