@@ -648,8 +648,10 @@ __global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
   if ((lane & 15) == 15) {
     const int row = lane >> 4;
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      if ((row & 1) + 2 * j < NV / 2) out[(int64_t)w * NV + wave_scatter_index(NV, row, j)] = x[j];
+    for (int j = 0; j < 3; ++j) {
+      const int idx = wave_scatter_index(NV, row, j);
+      if (idx >= 0) out[(int64_t)w * NV + idx] = x[j];
+    }
   }
 }
 

@@ -367,17 +367,17 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
         wave_reduce_scatter<NV>(v, x);
         if ((lane & 15) == 15) {
           const int row = lane >> 4;
-          // x[j] is value wave_scatter_index(NV, row, j) = that of j = 0, plus
-          // 2 j; an output that only even rows carry is written by odd rows
-          // (as 0) to the spare float, so every store is made by all four
-          // row ends at once
+          // x[j] is value wave_scatter_index(NV, row, j): that of j = 0 plus
+          // 2 j, or for the output only odd rows carry, that minus 1; even
+          // rows write that output to the spare float, so every store is
+          // made by all four row ends at once
           float* dst = part + k * kStride + wave_scatter_index(NV, row, 0);
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
             if (1 + 2 * j < NV / 2)
               dst[2 * j] = x[j];
             else if (2 * j < NV / 2)
-              ((row & 1) ? part + kBwdBatch * kStride - 2 * j : dst)[2 * j] = x[j];
+              ((row & 1) ? dst : part + kBwdBatch * kStride + 1 - 2 * j)[2 * j - 1] = x[j];
           }
         }
       };

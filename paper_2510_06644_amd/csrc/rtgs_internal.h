@@ -353,10 +353,11 @@ __device__ __forceinline__ float swap16_add(float a, float b) {
 // Wavefront reduce-scatter of NV (even, <= 12) per-lane values.  Two
 // lane-swap steps each halve the number of values a lane carries while
 // adding pairs of lanes; the (at most 3) values left are then summed along
-// each 16-lane row.  Lane 16 r + 15 (row r) ends with, in x[s], the
-// wavefront total of value
-//   wave_scatter_index(NV, r, s) = (r >> 1) * NV / 2 + (r & 1) + 2 s
-// for every s with (r & 1) + 2 s < NV / 2.  About 3 NV instructions
+// each 16-lane row.  With NV / 2 odd, the last value after the first swap has
+// no partner for the second: it is summed along each row as it is, and the
+// total of row 2i is added into row 2i + 1 by a row broadcast.  Lane 16 r + 15
+// (row r) ends with, in x[s], the wavefront total of value
+// wave_scatter_index(NV, r, s) where that is >= 0.  About 3 NV instructions
 // instead of the 6 NV of a full tree per value.
 template <int NV>
 __device__ __forceinline__ void wave_reduce_scatter(const float (&v)[NV], float (&x)[3]) {
@@ -367,17 +368,27 @@ __device__ __forceinline__ void wave_reduce_scatter(const float (&v)[NV], float 
   for (int i = 0; i < H; ++i) w[i] = swap32_add(v[i], v[i + H]);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    if (2 * j < H) {
-      x[j] = swap16_add(w[2 * j], 2 * j + 1 < H ? w[2 * j + 1] : 0.f);
-      x[j] = row_sum_to_lane15(x[j]);
+    if (2 * j + 1 < H) {
+      x[j] = row_sum_to_lane15(swap16_add(w[2 * j], w[2 * j + 1]));
+    } else if (2 * j < H) {
+      x[j] = row_sum_to_lane15(w[2 * j]);
+      // rows 1 and 3 add lane 15 of rows 0 and 2 (even rows end with
+      // something meaningless, which wave_scatter_index excludes)
+      x[j] += dpp_f<kDppRowBcast15, 0xf, true>(x[j]);
+      asm volatile("" : "+v"(x[j]));   // one DPP add in every lane (see above)
     } else {
       x[j] = 0.f;
     }
   }
 }
 
+// The value whose total lane 16 row + 15 holds in x[s] after
+// wave_reduce_scatter<NV>, or -1 if that output carries none.
 __device__ __forceinline__ int wave_scatter_index(int nv, int row, int s) {
-  return (row >> 1) * (nv / 2) + (row & 1) + 2 * s;
+  const int h = nv / 2;
+  if (2 * s + 1 < h) return (row >> 1) * h + (row & 1) + 2 * s;
+  if (2 * s < h) return (row & 1) ? (row >> 1) * h + 2 * s : -1;
+  return -1;
 }
 
 // Raster-side alpha of one (pixel, Gaussian) pair: the same instructions in
