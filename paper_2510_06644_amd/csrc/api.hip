@@ -511,7 +511,10 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
   hipError_t e = hipSuccess;
   if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, false, st, tm);
-  if (e == hipSuccess) e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, st, tm);
+  bool alpha_grad = false;            // some session passes dL/dA
+  for (int i = 0; i < ns; ++i) alpha_grad = alpha_grad || ss[i].dL_dalpha != nullptr;
+  if (e == hipSuccess)
+    e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, alpha_grad, st, tm);
   if (e == hipSuccess) e = launch_preprocess_bwd(B, w, flags, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_bwd launch");
   h->last_stream = st;

@@ -245,11 +245,12 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 }
 
 // NV = 10 (all parameters: u, v, a, b, c, o, r, g, b, z) or 6 (pose only:
-// u, v, a, b, c, z).  Each (tile, Gaussian) pair gets the sum of its pixels'
+// u, v, a, b, c, z).  GA: some session has an alpha-image gradient (without
+// one, its term of dL/dalpha is left out rather than added as zero).  Each (tile, Gaussian) pair gets the sum of its pixels'
 // gradients in slot pair_slot(); the sum is formed in a fixed order (lane
 // swaps and DPP row sums inside each wave, then the four waves in order), so the result is
 // bitwise reproducible and no float atomics are used.
-template <int NV>
+template <int NV, bool GA>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
   __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch], s_cn[kBwdBatch];
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
     g1 = S.dl_color[hw + c.pix];
     g2 = S.dl_color[2 * hw + c.pix];
     gD = S.dl_depth[c.pix];
-    if (S.dl_alpha) gA = S.dl_alpha[c.pix];
+    if (GA && S.dl_alpha) gA = S.dl_alpha[c.pix];
   }
   const float gAT = gA * Tc;        // dA/dalpha_j = T_final / (1 - alpha_j)
   if (tid == 0) s_hi = -1;
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
         cg = __builtin_fmaf(col.z, g2, cg);
         cg = __builtin_fmaf(col.w, gD, cg);
         // dL/dalpha_j = T_j (c_j - S_j) . g + T_final gA / (1 - alpha_j)
-        const float dla = __builtin_fmaf(Tj, cg - SG, gAT * rom);
+        const float dla = GA ? __builtin_fmaf(Tj, cg - SG, gAT * rom) : Tj * (cg - SG);
         SG = __builtin_fmaf(al, cg, om * SG);
         Tc = Tj;
         // the clamp alpha = 0.99 has no gradient to o or to the power
@@ -450,15 +451,22 @@ hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st,
-                             StageTimer* tm) {
+hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, bool alpha_grad,
+                             hipStream_t st, StageTimer* tm) {
   if (b.t_total <= 0) return hipGetLastError();
   const int grid = 8 * ((b.t_total + 7) / 8);
   Scope sc(tm, kStRasterBwd, st);
-  if (pose_only)
-    k_raster_bwd<6><<<grid, kBlock, 0, st>>>(b, w);
-  else
-    k_raster_bwd<10><<<grid, kBlock, 0, st>>>(b, w);
+  if (pose_only) {
+    if (alpha_grad)
+      k_raster_bwd<6, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_bwd<6, false><<<grid, kBlock, 0, st>>>(b, w);
+  } else {
+    if (alpha_grad)
+      k_raster_bwd<10, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_bwd<10, false><<<grid, kBlock, 0, st>>>(b, w);
+  }
   return hipGetLastError();
 }
 

@@ -185,7 +185,8 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
                                bool reuse_lists, hipStream_t st, StageTimer* tm);
 hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, hipStream_t st,
                              StageTimer* tm);
-hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, hipStream_t st,
+hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, bool alpha_grad,
+                             hipStream_t st,
                              StageTimer* tm);
 hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st,
                                  StageTimer* tm);

@@ -129,12 +129,14 @@ def _cov6(m):
     return np.stack([m[:, 0, 0], m[:, 0, 1], m[:, 0, 2], m[:, 1, 1], m[:, 1, 2], m[:, 2, 2]], 1)
 
 
-@pytest.mark.parametrize("posed", [False, True])
-def test_backward_all_gradients_c0(renderer, posed):
-    say(f"test_backward c0 posed={posed}")
+@pytest.mark.parametrize("posed,alpha_grad", [(False, True), (True, True), (True, False)])
+def test_backward_all_gradients_c0(renderer, posed, alpha_grad):
+    # alpha_grad: with and without an alpha-image gradient (the kernel
+    # leaves that term out when no session passes one)
+    say(f"test_backward c0 posed={posed} alpha_grad={alpha_grad}")
     xi = synth.pose_offset(32, 0.05, 3.0) if posed else None
     sc, cam, view = _case("c0", xi)
-    g, ref, keep = _grad_case(renderer, sc, cam, view)
+    g, ref, keep = _grad_case(renderer, sc, cam, view, alpha_grad=alpha_grad)
     pairs = [("means", ref.means), ("log_scales", ref.log_scales), ("quats", ref.quats),
              ("opacity_logits", ref.opacity_logits), ("colors", ref.colors)]
     for name, r in pairs:
