@@ -150,15 +150,17 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   // list positions fit in int32: the pair capacity is below 2^31
   const int start = (int)min((int64_t)W.tile_start[tile], W.cap);
   const int end = (int)min((int64_t)W.tile_start[tile + 1], W.cap);
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
+  // T carries the pixel's stop in its sign: T > 0 while the pixel walks
+  // (T >= 1e-4 > 0 until the stop), -T once it has stopped (or never walks),
+  // so the per-entry test is one compare and no flag is carried across the loop
+  float T = active ? 1.f : -1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   int last = -1;
   int stop = end;               // list position where the pixel stopped
   int nblend = 0;
-  bool done = !active;
   // the Gaussian id this thread stages next (loaded one batch ahead)
   uint32_t nid = start + tid < end ? W.ids[start + tid] : 0u;
   for (int b0 = start; b0 < end; b0 += kBlock) {
-    if (__syncthreads_and(done)) break;
+    if (__syncthreads_and(!(T > 0.f))) break;
     const int e = b0 + tid;
     if (e < end) {
       const GaussRec r = W.rec[nid];
@@ -178,11 +180,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
       auto step = [&](int k) {
         const Frag f = frag_alpha(s_r0[k], s_r1[k], pxf, pyf);
         const float tn = T * f.om;
-        const bool hit = !done && !(f.alpha < kAlphaMin);
-        const bool low = tn < kTMin;
-        const bool stop_here = hit && low;
-        const bool blend = hit && !low;
-        done = done || stop_here;
+        const bool hit = T > 0.f && !(f.alpha < kAlphaMin);
+        const bool stop_here = hit && tn < kTMin;
+        const bool blend = hit && !stop_here;
         if (STATS) stop = stop_here ? b0 + k : stop;
         const float w = blend ? f.alpha * T : 0.f;       // adds exactly 0 otherwise
         const float4 col = s_r2[k];
@@ -190,12 +190,12 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         C1 = __builtin_fmaf(w, col.y, C1);
         C2 = __builtin_fmaf(w, col.z, C2);
         D = __builtin_fmaf(w, col.w, D);
-        T = blend ? tn : T;
+        T = blend ? tn : (stop_here ? -T : T);
         last = blend ? b0 + k : last;
         if (STATS) nblend += blend ? 1 : 0;
       };
       while (m) {
-        if (__ballot(!done) == 0) break;               // the whole wave has stopped
+        if (__ballot(T > 0.f) == 0) break;             // the whole wave has stopped
         step(64 * q + __builtin_ctzll(m));
         m &= m - 1;
         if (m) {                                       // two entries per check
@@ -206,6 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     }
     __syncthreads();
   }
+  T = fabsf(T);
   if (!c.inside) return;
   const int64_t hw = (int64_t)S.width * S.height;
   // every pixel of the lane's block: the sample gets its result, the others
