@@ -181,8 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         const Frag f = frag_alpha(s_r0[k], s_r1[k], pxf, pyf);
         const float tn = T * f.om;
         const bool hit = T > 0.f && !(f.alpha < kAlphaMin);
-        const bool stop_here = hit && tn < kTMin;
-        const bool blend = hit && !stop_here;
+        const bool blend = hit && !(tn < kTMin);
+        const bool stop_here = hit != blend;              // hit and T would fall below 1e-4
         if (STATS) stop = stop_here ? b0 + k : stop;
         const float w = blend ? f.alpha * T : 0.f;       // adds exactly 0 otherwise
         const float4 col = s_r2[k];
