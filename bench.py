@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--cpu-sample", type=int, default=896)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 512 MiB device copy (scales PMC byte counters)")
     ap.add_argument("--no-tracking", action="store_true",

@@ -229,12 +229,14 @@ def test_capacity_overflow_is_reported_then_recovers():
 
 
 @pytest.mark.parametrize("n,span,lo,hi", [(900, 8, 700, 1024), (2500, 8, 1025, 4096),
-                                          (6000, 8, 4097, 10 ** 9), (9000, 24, 1025, 4096)])
+                                          (6000, 8, 4097, 8192), (9000, 8, 8193, 10 ** 9),
+                                          (9000, 24, 1025, 4096)])
 def test_long_tile_lists_take_each_sort_path(renderer, n, span, lo, hi):
     # n small Gaussians over a span x span pixel square from (4, 4): one tile
     # (span 8) or four (span 24); the longest list selects the path: the
     # one-workgroup merge sort (<= 1024 keys), the queued 1024-thread merge
-    # sort (<= 4096) or the in-place global sort
+    # sort (<= 4096), the 8-keys-per-thread merge sort (<= 8192) or the
+    # in-place global sort
     say(f"test_long_tile_lists n={n} span={span}")
     cam = synth.Camera(32, 32, 25.6, 25.6, 16.0, 16.0)
     rng = np.random.default_rng(8)
