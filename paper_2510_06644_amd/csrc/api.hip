@@ -146,6 +146,7 @@ WsLayout make_layout(const Counts& c, int64_t cap) {
   L.huge_tiles = take(4 * (t + 1));
   L.keys = take(8 * (uint64_t)cap);
   L.ids = take(4 * (uint64_t)cap);
+  L.qmask = take((uint64_t)cap);
   L.partial = take(4 * 10 * (uint64_t)cap);
   L.state_t = take(4 * (uint64_t)c.px_total);
   L.state_last = take(4 * (uint64_t)c.px_total);
@@ -178,6 +179,7 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.huge_tiles = reinterpret_cast<uint32_t*>(base + L.huge_tiles);
   w.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
   w.ids = reinterpret_cast<uint32_t*>(base + L.ids);
+  w.qmask = reinterpret_cast<uint8_t*>(base + L.qmask);
   w.partial = reinterpret_cast<float*>(base + L.partial);
   w.state_t = reinterpret_cast<float*>(base + L.state_t);
   w.state_last = reinterpret_cast<int32_t*>(base + L.state_last);

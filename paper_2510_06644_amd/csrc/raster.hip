@@ -167,7 +167,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
       s_r0[tid] = r.pos;
       s_r1[tid] = conic_log2(r.conic);
       s_r2[tid] = r.col;
-      s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
+      const unsigned qm = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx,
+                                    S.sub_sy);
+      s_m[tid] = qm;
+      W.qmask[e] = (uint8_t)qm;     // for the backward, which walks no entry unstaged here
     }
     if (e + kBlock < end) nid = W.ids[e + kBlock];
     __syncthreads();
@@ -252,7 +255,7 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 // swaps and DPP row sums inside each wave, then the four waves in order), so the result is
 // bitwise reproducible and no float atomics are used.
 template <int NV, bool GA>
-__global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
   __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch], s_cn[kBwdBatch];
   __shared__ unsigned s_m[kBwdBatch];
@@ -312,7 +315,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(Batch B, WsPtrs W) {
       s_r1[tid] = conic_log2(r.conic);
       s_r2[tid] = r.col;
       s_cn[tid] = r.conic;
-      s_m[tid] = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx, S.sub_sy);
+      // the forward staged every entry up to the last blended one of any
+      // pixel of the tile, and saved its quadrant mask
+      s_m[tid] = W.qmask[b0 + tid];
     }
     {
       const int nb0 = max(b0 - kBwdBatch, start);

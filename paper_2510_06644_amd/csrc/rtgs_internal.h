@@ -89,6 +89,7 @@ struct WsLayout {
   uint64_t huge_tiles;  // uint32[T]: tiles whose list is too long for the 4096-key sort
   uint64_t keys;        // uint64[cap]
   uint64_t ids;         // uint32[cap]
+  uint64_t qmask;       // uint8[cap]: quadrants of its tile each list entry can reach
   uint64_t partial;     // float[cap][10]: per (tile, Gaussian) merged 2D gradient
   uint64_t state_t;     // float[pixels]: recomputed final T
   uint64_t state_last;  // int32[pixels]: recomputed last position
@@ -136,6 +137,7 @@ struct WsPtrs {
   uint32_t* huge_tiles;
   unsigned long long* keys;
   uint32_t* ids;
+  uint8_t* qmask;
   float* partial;
   float* state_t;
   int32_t* state_last;
