@@ -260,8 +260,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch], s_cn[kBwdBatch];
   __shared__ unsigned s_m[kBwdBatch];
   // per wave: kStride floats per entry, then one float that takes the
-  // reduce-scatter outputs no entry needs
-  __shared__ float s_part[4][kBwdBatch * kStride + 1];
+  // reduce-scatter outputs no entry needs; rows padded to 16 bytes so they
+  // are cleared with 16-byte stores
+  constexpr int kPartRow = (kBwdBatch * kStride + 1 + 3) & ~3;
+  __shared__ __align__(16) float s_part[4][kPartRow];
   __shared__ int s_hi;
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
@@ -324,7 +326,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       if (tid < b0 - nb0) nid = W.ids[nb0 + tid];
     }
     // zero this batch's partial sums (each wave its own)
-    for (int i = lane; i < kBwdBatch * kStride; i += 64) part[i] = 0.f;
+    for (int i = lane; i < kBwdBatch * kStride / 4; i += 64)
+      reinterpret_cast<float4*>(part)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     for (int q = kBwdBatch / 64 - 1; q >= 0; --q) {
       unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
