@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_group_sums(Batch B, WsPtrs W) {
   tile_groups(S, g, c0, c1);
   const uint32_t* h = W.hist + S.hist_base + (t - S.tile_base);
   uint32_t sum = 0;
-#pragma unroll 4
+#pragma unroll 8
   for (int c = c0; c < c1; ++c) sum += h[(int64_t)c * ts];
   W.gsum[(int64_t)g * B.t_total + t] = sum;
 }
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_group_scan(Batch B, WsPtrs W) {
   int c0, c1;
   tile_groups(S, g, c0, c1);
   uint32_t* h = W.hist + S.hist_base + (t - S.tile_base);
-#pragma unroll 4
+#pragma unroll 8
   for (int c = c0; c < c1; ++c) {
     const uint32_t v = h[(int64_t)c * ts];
     h[(int64_t)c * ts] = run;
@@ -333,30 +333,37 @@ __global__ __launch_bounds__(kBlock) void k_tile_group_scan(Batch B, WsPtrs W) {
   }
 }
 
-// Exclusive scan of n values in[0..n) into out[0..n]; out[n] = total.
+// Exclusive scan of n values in[0..n) into out[0..n]; out[n] = total.  Each
+// thread sums a contiguous run; the run sums are scanned inside each wave by
+// lane shifts, then across the waves through LDS (part[kScanThreads / 64]),
+// so two barriers in all.
 __device__ uint32_t block_scan_1024(const uint32_t* in, uint32_t* out, int n, uint32_t* part) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (n + kScanThreads - 1) / kScanThreads;
   const int beg = min(tid * per, n), end = min(beg + per, n);
   uint32_t sum = 0;
   for (int i = beg; i < end; ++i) sum += in[i];
-  part[tid] = sum;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t add = tid >= off ? part[tid - off] : 0u;
-    __syncthreads();
-    part[tid] += add;
-    __syncthreads();
+  uint32_t x = sum;                       // inclusive scan of the run sums in the wave
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
-  uint32_t run = part[tid] - sum;
+  if (lane == 63) part[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int q = 0; q < kScanThreads / 64; ++q) {
+    const uint32_t v = part[q];
+    before += q < wave ? v : 0u;
+    total += v;
+  }
+  uint32_t run = before + x - sum;
   for (int i = beg; i < end; ++i) {
     const uint32_t v = in[i];
     out[i] = run;
     run += v;
   }
-  const uint32_t total = part[kScanThreads - 1];
   if (tid == 0) out[n] = total;
-  __syncthreads();
+  __syncthreads();                        // part is reused by the next call
   return total;
 }
 
@@ -364,7 +371,7 @@ __device__ uint32_t block_scan_1024(const uint32_t* in, uint32_t* out, int n, ui
 // per-chunk totals), and the pair total.
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_total, int c_total,
                                                              unsigned long long* max_pairs) {
-  __shared__ uint32_t part[kScanThreads];
+  __shared__ uint32_t part[kScanThreads / 64];
   const uint32_t total = block_scan_1024(W.tile_count, W.tile_start, t_total, part);
   block_scan_1024(W.chunk_total, W.chunk_off, c_total, part);
   if (threadIdx.x == 0) {
