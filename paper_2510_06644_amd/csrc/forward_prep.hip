@@ -42,10 +42,8 @@ __device__ __forceinline__ void project_one(const SessionDev& S, const float* vm
   const double mx = S.means[3 * li + 0], my = S.means[3 * li + 1], mz = S.means[3 * li + 2];
   const double qw = S.quats[4 * li + 0], qx = S.quats[4 * li + 1];
   const double qy = S.quats[4 * li + 2], qz = S.quats[4 * li + 3];
-  const double s0 = exp((double)S.log_scales[3 * li + 0]);
-  const double s1 = exp((double)S.log_scales[3 * li + 1]);
-  const double s2 = exp((double)S.log_scales[3 * li + 2]);
-  o = 1.0 / (1.0 + exp(-(double)S.opac[li]));
+  double ss[3];
+  activate(S, li, ss, o);
   P.ok = false;
   // camera-space centre p = R_c mu + t_c
   const double x = vm[0] * mx + vm[1] * my + vm[2] * mz + vm[3];
@@ -61,7 +59,6 @@ __device__ __forceinline__ void project_one(const SessionDev& S, const float* vm
                  2 * (a * b + w * c), 1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
                  2 * (a * c - w * b), 2 * (b * c + w * a), 1 - 2 * (a * a + b * b)};
   // M = R diag(s); Sigma = M M^T
-  const double ss[3] = {s0, s1, s2};
   double M[9];
   for (int r = 0; r < 3; ++r)
     for (int k = 0; k < 3; ++k) M[3 * r + k] = R[3 * r + k] * ss[k];
@@ -128,7 +125,7 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
     split(P.v, vh, vl);
     const float zf = (float)P.z;
     // bounding box of the alpha = 1/255 ellipse: d^T M d <= 2 ln(255 o)
-    const double t = 2.0 * log(255.0 * o);
+    const double t = 2.0 * (double)logf((float)(255.0 * o));
     const float ex = (float)sqrt(t * P.sxx);
     const float ey = (float)sqrt(t * P.syy);
     GaussRec r;

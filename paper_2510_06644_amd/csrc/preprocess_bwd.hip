@@ -115,9 +115,8 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
       const double mx = S.means[3 * li], my = S.means[3 * li + 1], mz = S.means[3 * li + 2];
       const double qw = S.quats[4 * li], qx = S.quats[4 * li + 1];
       const double qy = S.quats[4 * li + 2], qz = S.quats[4 * li + 3];
-      const double sc[3] = {exp((double)S.log_scales[3 * li]), exp((double)S.log_scales[3 * li + 1]),
-                            exp((double)S.log_scales[3 * li + 2])};
-      const double o = 1.0 / (1.0 + exp(-(double)S.opac[li]));
+      double sc[3], o;
+      activate(S, li, sc, o);
       const double x = vm[0] * mx + vm[1] * my + vm[2] * mz + vm[3];
       const double y = vm[4] * mx + vm[5] * my + vm[6] * mz + vm[7];
       const double z = vm[8] * mx + vm[9] * my + vm[10] * mz + vm[11];

@@ -394,6 +394,16 @@ __device__ __forceinline__ int wave_scatter_index(int nv, int row, int s) {
   return -1;
 }
 
+// Activations of Eq. 1's parameters (scales exp(l), opacity sigmoid(eta)),
+// evaluated in float32 from the float32 parameters (about 1e-7 relative, far
+// inside the float32 rendering) and widened for the float64 projection: the
+// float64 exp is a long software routine on the GPU.
+__device__ __forceinline__ void activate(const SessionDev& S, int li, double (&sc)[3], double& o) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) sc[k] = (double)expf(S.log_scales[3 * li + k]);
+  o = (double)(1.f / (1.f + expf(-S.opac[li])));
+}
+
 // Raster-side alpha of one (pixel, Gaussian) pair: the same instructions in
 // the forward and the backward so both take the same skip decisions.
 // r0 = (u_hi, v_hi, u_lo, v_lo); k = (A, B, C, opacity), the conic (a, b, c)
