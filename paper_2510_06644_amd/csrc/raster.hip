@@ -89,18 +89,20 @@ __device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile) {
 // over the box [x0, x1] x [y0, y1] of offsets d (a convex quadratic: zero if
 // the box holds the centre, otherwise reached on an edge, where it is a 1D
 // quadratic minimised in closed form and clamped to the edge).
-__device__ __forceinline__ float box_min_quad(float a, float b, float c, float x0, float x1,
-                                              float y0, float y1) {
+// ia, ic: 1/a and 1/c (0 where a or c is not positive), shared by the four
+// quadrants of an entry.
+__device__ __forceinline__ float box_min_quad(float a, float b, float c, float ia, float ic,
+                                              float x0, float x1, float y0, float y1) {
   if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
   float m = 3.0e38f;
   const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const float X = xs[e];                           // edge dx = X
-    const float dy = fminf(y1, fmaxf(y0, c > 0.f ? -b * X / c : 0.f));
+    const float dy = fminf(y1, fmaxf(y0, -b * X * ic));
     m = fminf(m, a * X * X + 2.f * b * X * dy + c * dy * dy);
     const float Y = ys[e];                           // edge dy = Y
-    const float dx = fminf(x1, fmaxf(x0, a > 0.f ? -b * Y / a : 0.f));
+    const float dx = fminf(x1, fmaxf(x0, -b * Y * ia));
     m = fminf(m, a * dx * dx + 2.f * b * dx * Y + c * Y * Y);
   }
   return m;
@@ -115,12 +117,13 @@ __device__ __forceinline__ unsigned quad_mask(float4 r0, float4 r1, float4 ex, i
   const float u = r0.x + r0.z, v = r0.y + r0.w;
   const float t = ex.z * (1.f + 1e-3f) + 1e-3f;
   const float wx = (float)((8 << sx) - 1), wy = (float)((8 << sy) - 1);
+  const float ia = r1.x > 0.f ? 1.f / r1.x : 0.f, ic = r1.z > 0.f ? 1.f / r1.z : 0.f;
   unsigned m = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const float qx = (float)(tx0 + ((w & 1) * 8 << sx)) + 0.5f - u;
     const float qy = (float)(ty0 + ((w >> 1) * 8 << sy)) + 0.5f - v;
-    const float q = box_min_quad(r1.x, r1.y, r1.z, qx, qx + wx, qy, qy + wy);
+    const float q = box_min_quad(r1.x, r1.y, r1.z, ia, ic, qx, qx + wx, qy, qy + wy);
     m |= (q <= t) ? (1u << w) : 0u;
   }
   return m;
