@@ -65,11 +65,12 @@ __device__ __forceinline__ void project_one(const SessionDev& S, const float* vm
   // EWA Jacobian with the field-of-view clamp
   const double limx = kFovClamp * 0.5 * S.width / S.fx;
   const double limy = kFovClamp * 0.5 * S.height / S.fy;
-  const double rx = x / z, ry = y / z;
+  const double iz = 1.0 / z;      // once: a float64 division is a long instruction sequence
+  const double rx = x * iz, ry = y * iz;
   const double tx = fmin(limx, fmax(-limx, rx));
   const double ty = fmin(limy, fmax(-limy, ry));
-  const double j00 = S.fx / z, j02 = -S.fx * tx / z;
-  const double j11 = S.fy / z, j12 = -S.fy * ty / z;
+  const double j00 = S.fx * iz, j02 = -S.fx * tx * iz;
+  const double j11 = S.fy * iz, j12 = -S.fy * ty * iz;
   // T = J W (2x3), W = R_c
   double T0[3], T1[3];
   for (int k = 0; k < 3; ++k) {

@@ -120,8 +120,9 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
       const double x = vm[0] * mx + vm[1] * my + vm[2] * mz + vm[3];
       const double y = vm[4] * mx + vm[5] * my + vm[6] * mz + vm[7];
       const double z = vm[8] * mx + vm[9] * my + vm[10] * mz + vm[11];
-      const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-      const double w = qw / qn, a = qx / qn, b = qy / qn, c = qz / qn;
+      // reciprocals taken once (a float64 division is a long instruction sequence)
+      const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz), iqn = 1.0 / qn;
+      const double w = qw * iqn, a = qx * iqn, b = qy * iqn, c = qz * iqn;
       const double R[9] = {1 - 2 * (b * b + c * c), 2 * (a * b - w * c), 2 * (a * c + w * b),
                            2 * (a * b + w * c), 1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
                            2 * (a * c - w * b), 2 * (b * c + w * a), 1 - 2 * (a * a + b * b)};
@@ -130,10 +131,11 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
         for (int k = 0; k < 3; ++k) M[3 * r + k] = R[3 * r + k] * sc[k];
       const double limx = kFovClamp * 0.5 * S.width / S.fx;
       const double limy = kFovClamp * 0.5 * S.height / S.fy;
-      const double rx = x / z, ry = y / z;
+      const double iz = 1.0 / z, iz2 = iz * iz, iz3 = iz2 * iz;
+      const double rx = x * iz, ry = y * iz;
       const bool inx = rx > -limx && rx < limx, iny = ry > -limy && ry < limy;
       const double tx = fmin(limx, fmax(-limx, rx)), ty = fmin(limy, fmax(-limy, ry));
-      const double j00 = S.fx / z, j02 = -S.fx * tx / z, j11 = S.fy / z, j12 = -S.fy * ty / z;
+      const double j00 = S.fx * iz, j02 = -S.fx * tx * iz, j11 = S.fy * iz, j12 = -S.fy * ty * iz;
       double T0[3], T1[3], A0[3], A1[3];
       for (int k = 0; k < 3; ++k) {
         T0[k] = j00 * vm[k] + j02 * vm[8 + k];
@@ -175,13 +177,12 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
         dW[6 + k] = j02 * dT0[k] + j12 * dT1[k];
       }
       // dL/dp from u, v, J and the depth output
-      const double z2 = z * z, z3 = z2 * z;
-      double gx = gu * S.fx / z + (inx ? dj02 * (-S.fx / z2) : 0.0);
-      double gy = gv * S.fy / z + (iny ? dj12 * (-S.fy / z2) : 0.0);
-      const double dj02dz = S.fx * tx / z2 + (inx ? S.fx * x / z3 : 0.0);
-      const double dj12dz = S.fy * ty / z2 + (iny ? S.fy * y / z3 : 0.0);
-      double gz = gdep - gu * S.fx * x / z2 - gv * S.fy * y / z2 - dj00 * S.fx / z2 -
-                  dj11 * S.fy / z2 + dj02 * dj02dz + dj12 * dj12dz;
+      double gx = gu * S.fx * iz + (inx ? dj02 * (-S.fx * iz2) : 0.0);
+      double gy = gv * S.fy * iz + (iny ? dj12 * (-S.fy * iz2) : 0.0);
+      const double dj02dz = S.fx * tx * iz2 + (inx ? S.fx * x * iz3 : 0.0);
+      const double dj12dz = S.fy * ty * iz2 + (iny ? S.fy * y * iz3 : 0.0);
+      double gz = gdep - gu * S.fx * x * iz2 - gv * S.fy * y * iz2 - dj00 * S.fx * iz2 -
+                  dj11 * S.fy * iz2 + dj02 * dj02dz + dj12 * dj12dz;
       // view matrix: dL/dW = dL/dW|cov + dL/dp mu^T, dL/dt = dL/dp
       const double gp3[3] = {gx, gy, gz}, mu[3] = {mx, my, mz};
       for (int i = 0; i < 3; ++i) {
@@ -216,10 +217,10 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
         const double gz4 = 2 * (-2 * c * dR[0] - w * dR[1] + a * dR[2] + w * dR[3] - 2 * c * dR[4] +
                                 b * dR[5] + a * dR[6] + b * dR[7]);
         const double dot = w * gw + a * gx4 + b * gy4 + c * gz4;
-        gq[0] = (gw - w * dot) / qn;
-        gq[1] = (gx4 - a * dot) / qn;
-        gq[2] = (gy4 - b * dot) / qn;
-        gq[3] = (gz4 - c * dot) / qn;
+        gq[0] = (gw - w * dot) * iqn;
+        gq[1] = (gx4 - a * dot) * iqn;
+        gq[2] = (gy4 - b * dot) * iqn;
+        gq[3] = (gz4 - c * dot) * iqn;
         go_eta = go * o * (1.0 - o);
         if (want_cov) {
           // dL/dSigma = T^T G' T
