@@ -339,8 +339,13 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
     if (ts > tmax) tmax = ts;
     pbase += (int64_t)s.cam.width * s.cam.height;
   }
-  e = hipMemcpyAsync(w.table, t, sizeof(SessionDev) * ns, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(session table)");
+  // one session travels in the launch arguments (Batch::one); a table is
+  // uploaded only for several
+  if (ns > 1) {
+    e = hipMemcpyAsync(w.table, t, sizeof(SessionDev) * ns, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(session table)");
+  }
+  B.one = t[0];
   e = hipEventRecord(h->ring_ev[slot], st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   B.sess = w.table;

@@ -105,7 +105,7 @@ template <bool REUSE>
 __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W) {
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.block_base; });
-  const SessionDev& S = B.sess[s];
+  const SessionDev& S = session_of(B, s);
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
   // the call's counters start at zero (the binning passes run after this kernel)
   if (!REUSE && blockIdx.x == 0 && threadIdx.x < 8) W.counters[threadIdx.x] = 0;
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   __shared__ uint32_t s_wave[kBinThreads / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
-  const SessionDev& S = B.sess[s];
+  const SessionDev& S = session_of(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
   for (int t = threadIdx.x; t < ts; t += kBinThreads) s_hist[t] = 0u;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_group_sums(Batch B, WsPtrs W) {
   if (t >= B.t_total) return;
   const int s = find_session(B.sess, B.n_sessions, t,
                              [](const SessionDev& x) { return x.tile_base; });
-  const SessionDev& S = B.sess[s];
+  const SessionDev& S = session_of(B, s);
   const int ts = S.tiles_x * S.tiles_y;
   int c0, c1;
   tile_groups(S, g, c0, c1);
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_group_scan(Batch B, WsPtrs W) {
   if (t >= B.t_total) return;
   const int s = find_session(B.sess, B.n_sessions, t,
                              [](const SessionDev& x) { return x.tile_base; });
-  const SessionDev& S = B.sess[s];
+  const SessionDev& S = session_of(B, s);
   const int ts = S.tiles_x * S.tiles_y;
   uint32_t run = 0;
   for (int q = 0; q < g; ++q) run += W.gsum[(int64_t)q * B.t_total + t];
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   __shared__ uint32_t s_wave[kBinThreads / 64];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.chunk_base; });
-  const SessionDev& S = B.sess[s];
+  const SessionDev& S = session_of(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
   const uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
   __shared__ double s_red[kGaussPerBlock / 64][12];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.block_base; });
-  const SessionDev& S = B.sess[s];
+  const SessionDev& S = session_of(B, s);
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
   const bool want_map = (flags & RTGS_GRAD_MAP) != 0;
   const bool want_cov = (flags & RTGS_GRAD_COV3D) != 0 && S.g_cov3d != nullptr;
@@ -266,10 +266,11 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
 // view-matrix gradient, and the pose (left-perturbation) gradient from it.
 __global__ __launch_bounds__(256) void k_pose_reduce(Batch B, WsPtrs W) {
   __shared__ double s_acc[256][12];
-  const SessionDev& S = B.sess[blockIdx.x];
+  const SessionDev& S = session_of(B, blockIdx.x);
   const int b0 = S.block_base;
-  const int b1 = (blockIdx.x + 1 < (unsigned)B.n_sessions) ? B.sess[blockIdx.x + 1].block_base
-                                                           : B.b_total;
+  const int b1 = (blockIdx.x + 1 < (unsigned)B.n_sessions)
+                     ? session_of(B, blockIdx.x + 1).block_base
+                     : B.b_total;
   double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = b0 + (int)threadIdx.x; b < b1; b += 256)
     for (int k = 0; k < 12; ++k) acc[k] += W.pose_part[(int64_t)b * 16 + k];

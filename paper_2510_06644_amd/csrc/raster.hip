@@ -54,7 +54,7 @@ struct TileCtx {
 __device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile) {
   TileCtx c;
   c.s = find_session(B.sess, B.n_sessions, tile, [](const SessionDev& x) { return x.tile_base; });
-  const SessionDev& S = B.sess[c.s];
+  const SessionDev& S = session_of(B, c.s);
   c.lt = tile - S.tile_base;
   c.tile_x0 = (c.lt % S.tiles_x) << (4 + S.sub_sx);
   c.tile_y0 = (c.lt / S.tiles_x) << (4 + S.sub_sy);
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
   const TileCtx c = tile_ctx(B, tile);
-  const SessionDev& S = B.sess[c.s];
+  const SessionDev& S = session_of(B, c.s);
   const int tid = threadIdx.x;
   const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
   const TileCtx c = tile_ctx(B, tile);
-  const SessionDev& S = B.sess[c.s];
+  const SessionDev& S = session_of(B, c.s);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ltx = c.lt % S.tiles_x, lty = c.lt / S.tiles_x;
   const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);

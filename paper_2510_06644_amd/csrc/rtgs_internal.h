@@ -148,13 +148,15 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L);
 
 // Batch geometry passed by value to every kernel.
 struct Batch {
-  const SessionDev* sess;
+  const SessionDev* sess;   // device session table (read when n_sessions > 1)
   int32_t n_sessions;
   int32_t n_total;      // Gaussians over all sessions
   int32_t t_total;      // tiles over all sessions
   int32_t b_total;      // per-Gaussian blocks over all sessions
   int32_t c_total;      // binning chunks over all sessions
   int32_t t_max;        // largest tile count of one session
+  SessionDev one;       // the session of a one-session batch, passed with the launch
+                        // arguments instead of through a table upload
 };
 
 // Stages that the handle's profiler can bracket with HIP events.
@@ -304,6 +306,11 @@ __device__ __forceinline__ int find_session(const SessionDev* s, int n, int key,
     if (base(s[mid]) <= key) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// Session s of a batch.
+__device__ __forceinline__ const SessionDev& session_of(const Batch& B, int s) {
+  return B.n_sessions == 1 ? B.one : B.sess[s];
 }
 
 // DPP control words (GFX9 encoding).
