@@ -143,7 +143,6 @@ WsLayout make_layout(const Counts& c, int64_t cap) {
   L.tile_count = take(4 * (t + 1));
   L.tile_start = take(4 * (t + 1));
   L.big_tiles = take(4 * (t + 1));
-  L.huge_tiles = take(4 * (t + 1));
   L.keys = take(8 * (uint64_t)cap);
   L.ids = take(4 * (uint64_t)cap);
   L.qmask = take((uint64_t)cap);
@@ -176,7 +175,6 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.tile_count = reinterpret_cast<uint32_t*>(base + L.tile_count);
   w.tile_start = reinterpret_cast<uint32_t*>(base + L.tile_start);
   w.big_tiles = reinterpret_cast<uint32_t*>(base + L.big_tiles);
-  w.huge_tiles = reinterpret_cast<uint32_t*>(base + L.huge_tiles);
   w.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
   w.ids = reinterpret_cast<uint32_t*>(base + L.ids);
   w.qmask = reinterpret_cast<uint8_t*>(base + L.qmask);

@@ -497,9 +497,11 @@ __device__ __forceinline__ int pow2_at_least(int n, int lo) {
   return p;
 }
 
-template <int NT, int K>
+// KEYS_OUT: write the sorted keys back to keys_out instead of their ids.
+template <int NT, int K, bool KEYS_OUT = false>
 __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, int n,
-                                unsigned long long* buf0, unsigned long long* buf1) {
+                                unsigned long long* buf0, unsigned long long* buf1,
+                                unsigned long long* keys_out = nullptr) {
   const int N = pow2_at_least(n, K);
   const int t = threadIdx.x;
   const bool act = K * t < N;
@@ -548,7 +550,34 @@ __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, i
     src = dst;
     dst = tmp;
   }
-  for (int i = t; i < n; i += NT) ids[i] = (uint32_t)src[i];
+  for (int i = t; i < n; i += NT) {
+    if (KEYS_OUT)
+      keys_out[i] = src[i];
+    else
+      ids[i] = (uint32_t)src[i];
+  }
+}
+
+// The ids of the merge of two sorted key runs A[0..na) and B[0..nb) (global
+// memory), each thread writing a contiguous share of the outputs after a
+// merge-path search for its start (ties: A first).
+__device__ void merge_runs_to_ids(const unsigned long long* A, int na,
+                                  const unsigned long long* Bv, int nb, uint32_t* ids) {
+  const int n = na + nb;
+  const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int r = min((int)threadIdx.x * per, n), r1 = min(r + per, n);
+  if (r >= r1) return;
+  int lo = max(0, r - nb), hi = min(r, na);       // A keys among the first r outputs
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (A[mid] <= Bv[r - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  int i = lo, j = r - lo;
+  for (int o = r; o < r1; ++o) {
+    const bool take_a = j >= nb || (i < na && A[i] <= Bv[j]);
+    ids[o] = (uint32_t)(take_a ? A[i++] : Bv[j++]);
+  }
 }
 
 // One workgroup per tile: lists of up to 1024 keys are sorted here; longer
@@ -571,43 +600,32 @@ __global__ __launch_bounds__(kBlock) void k_sort_tiles(WsPtrs W) {
   merge_sort_tile<kBlock, kSortPerThread>(W.keys + st, W.ids + st, n, b0, b1);
 }
 
-// Queued long lists, up to 4096 keys, by the LDS merge sort with 1024
-// threads; longer ones are queued again for k_sort_huge_tiles.
+// Queued long lists: up to 4096 keys by the LDS merge sort with 1024
+// threads; up to 8192 as two such sorts of halves written back as keys, then
+// one merge of the halves from global memory; longer ones by the bitonic
+// network in place in global memory.  One launch whatever the lengths.
 constexpr int kBigThreads = 1024;
+constexpr int kBigKeys = kSortPerThread * kBigThreads;
 __global__ __launch_bounds__(kBigThreads) void k_sort_big_tiles(WsPtrs W) {
-  __shared__ unsigned long long b0[kSortPerThread * kBigThreads], b1[kSortPerThread * kBigThreads];
+  __shared__ unsigned long long b0[kBigKeys], b1[kBigKeys];
   const long long count = W.counters[2];
   for (long long q = blockIdx.x; q < count; q += gridDim.x) {
     const int t = (int)W.big_tiles[q];
     const int64_t st = min((int64_t)W.tile_start[t], W.cap);
     const int64_t en = min((int64_t)W.tile_start[t + 1], W.cap);
     const int n = (int)(en - st);
-    if (n <= kSortPerThread * kBigThreads) {
-      merge_sort_tile<kBigThreads, kSortPerThread>(W.keys + st, W.ids + st, n, b0, b1);
-    } else if (threadIdx.x == 0) {
-      const unsigned long long q2 = atomicAdd((unsigned long long*)&W.counters[3], 1ull);
-      W.huge_tiles[q2] = (uint32_t)t;
-    }
-    __syncthreads();
-  }
-}
-
-// Lists above 4096 keys: up to 8192 by the LDS merge sort with 8 keys per
-// thread (128 KB of LDS, one workgroup per CU), longer ones by the bitonic
-// network in place in global memory.
-constexpr int kHugePerThread = 8;
-__global__ __launch_bounds__(kBigThreads) void k_sort_huge_tiles(WsPtrs W) {
-  __shared__ unsigned long long b0[kHugePerThread * kBigThreads], b1[kHugePerThread * kBigThreads];
-  const long long count = W.counters[3];
-  for (long long q = blockIdx.x; q < count; q += gridDim.x) {
-    const int t = (int)W.huge_tiles[q];
-    const int64_t st = min((int64_t)W.tile_start[t], W.cap);
-    const int64_t en = min((int64_t)W.tile_start[t + 1], W.cap);
-    const int n = (int)(en - st);
-    if (n <= kHugePerThread * kBigThreads) {
-      merge_sort_tile<kBigThreads, kHugePerThread>(W.keys + st, W.ids + st, n, b0, b1);
+    unsigned long long* g = W.keys + st;
+    if (n <= kBigKeys) {
+      merge_sort_tile<kBigThreads, kSortPerThread>(g, W.ids + st, n, b0, b1);
+    } else if (n <= 2 * kBigKeys) {
+      merge_sort_tile<kBigThreads, kSortPerThread, true>(g, nullptr, kBigKeys, b0, b1, g);
+      __syncthreads();
+      merge_sort_tile<kBigThreads, kSortPerThread, true>(g + kBigKeys, nullptr, n - kBigKeys, b0,
+                                                          b1, g + kBigKeys);
+      __threadfence_block();
+      __syncthreads();
+      merge_runs_to_ids(g, kBigKeys, g + kBigKeys, n - kBigKeys, W.ids + st);
     } else {
-      unsigned long long* g = W.keys + st;
       bitonic_sort(g, n);
       for (int i = threadIdx.x; i < n; i += blockDim.x) W.ids[st + i] = (uint32_t)g[i];
     }
@@ -700,7 +718,6 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
     Scope sc(tm, kStSort, st);
     k_sort_tiles<<<b.t_total, kBlock, 0, st>>>(w);
     k_sort_big_tiles<<<b.t_total < 512 ? b.t_total : 512, kBigThreads, 0, st>>>(w);
-    k_sort_huge_tiles<<<b.t_total < 256 ? b.t_total : 256, kBigThreads, 0, st>>>(w);
   }
   return hipGetLastError();
 }

@@ -72,7 +72,7 @@ struct SessionDev {
 // Offsets of the workspace regions (bytes from ws).
 struct WsLayout {
   uint64_t table;       // SessionDev[RTGS_MAX_SESSIONS]
-  uint64_t counters;    // int64[8]: 0 pairs of this call, 2 / 3 entries of big_tiles / huge_tiles
+  uint64_t counters;    // int64[8]: 0 pairs of this call, 2 entries of big_tiles
   uint64_t rec;         // GaussRec[N]: the 64-byte raster record of each Gaussian
   uint64_t rect;        // int4[N]: tile rectangle
   uint64_t cnt;         // uint32[N]: tiles touched
@@ -86,7 +86,6 @@ struct WsLayout {
   uint64_t tile_count;  // uint32[T + 1]
   uint64_t tile_start;  // uint32[T + 1]
   uint64_t big_tiles;   // uint32[T]: tiles whose list is too long for the one-pass sort
-  uint64_t huge_tiles;  // uint32[T]: tiles whose list is too long for the 4096-key sort
   uint64_t keys;        // uint64[cap]
   uint64_t ids;         // uint32[cap]
   uint64_t qmask;       // uint8[cap]: quadrants of its tile each list entry can reach
@@ -134,7 +133,6 @@ struct WsPtrs {
   uint32_t* tile_count;
   uint32_t* tile_start;
   uint32_t* big_tiles;
-  uint32_t* huge_tiles;
   unsigned long long* keys;
   uint32_t* ids;
   uint8_t* qmask;
