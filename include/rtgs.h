@@ -31,7 +31,9 @@
  * - Workspace: the caller allocates `ws` of the size given by
  *   rtgs_workspace_size*, and passes the same `ws` to render_fwd and to the
  *   render_bwd that follows it (the backward reuses the forward's projected
- *   Gaussians, tile lists and depth order: the sort is not redone, Sec. 2.2).
+ *   Gaussians, tile lists and depth order, and each list entry's quadrant
+ *   mask: the sort is not redone, Sec. 2.2); no other render_fwd may use
+ *   that workspace in between.
  * - Pair capacity: the number of (tile, Gaussian) pairs is data dependent.
  *   The caller sizes the pair buffer (`pair_capacity`); if a frame needs more,
  *   the excess pairs are dropped on the device (no fault), the output of that
