@@ -86,6 +86,33 @@ def measured_traffic():
     return rec
 
 
+# Slot-count roofline of the whole iteration: per stage the larger of its
+# algorithmic HBM bytes at 8 TB/s and its algorithmic VALU operations plus
+# three extra slots per transcendental (exp, rcp at quarter rate) at
+# 1024 SIMDs x 16 lanes x 2.4 GHz.  Per-unit counts: forward 12 VALU + 1 exp
+# per list entry visited and 10 per blend; backward 12 + 1 exp per entry up to
+# the last blend and 55 + 1 rcp per blended fragment; bytes 152 (projection)
+# + 176 (its backward) + 392 (Adam, 14 parameters) + 40 (merged 2D gradient)
+# per Gaussian, 12 (emit) + 24 (sort) + 40 (merge) per pair, 48 (loss) per pixel.
+SLOT_RATE = 1024 * 16 * 2.4e9
+HBM_BYTES_PER_S = 8e12
+
+
+def path_roofline(cnt, ms_per_step, bwd_ms, fwd_ms, spec):
+    fwd_us = (12 * cnt["visited"] + 10 * cnt["blended"] + 3 * cnt["visited"]) / SLOT_RATE * 1e6
+    bwd_us = (12 * cnt["visited_to_last"] + 55 * cnt["blended"]
+              + 3 * (cnt["visited_to_last"] + cnt["blended"])) / SLOT_RATE * 1e6
+    hbm_bytes = (760 * spec.n + 76 * cnt["pairs"] + 48 * spec.width * spec.height)
+    hbm_us = hbm_bytes / HBM_BYTES_PER_S * 1e6
+    t_roof = fwd_us + bwd_us + hbm_us
+    return {"model": "sum over stages of max(bytes / 8 TB/s, (VALU ops + 3 per exp or rcp) "
+                     "/ 39.3T lane-slots/s)",
+            "t_roof_us": t_roof, "raster_fwd_us": fwd_us, "raster_bwd_us": bwd_us,
+            "hbm_stages_us": hbm_us, "frac": t_roof / (1000.0 * ms_per_step),
+            "raster_bwd_frac": bwd_us / (1000.0 * bwd_ms),
+            "raster_fwd_frac": fwd_us / (1000.0 * fwd_ms)}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -496,6 +523,7 @@ def main():
                    "gaussians": spec.n, "step": "render_fwd + L1 loss + render_bwd (all map "
                    "parameters) + Adam", "pixels": "full resolution", "prune": False},
         "roofline": roof,
+        "path_roofline": path_roofline(cnt, ms, bwd_ms, fwd_ms, spec),
         "raster_fwd_roofline": {"bound": "alu", "avg_ms": fwd_ms,
                                 "achieved": fwd_flops / (fwd_ms * 1e-3) / 1e12,
                                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
