@@ -860,7 +860,8 @@ int32_t rtgs_query(rtgs_handle_t h, int32_t blocking, int64_t* pairs_needed, int
   unsigned long long got[2] = {0, 0}, zero[2] = {0, 0};
   hipError_t e = hipMemcpyAsync(got, h->d_scalars, sizeof(got), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess) e = hipMemcpyAsync(h->d_scalars, zero, sizeof(zero), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->d_scalars, zero, sizeof(zero), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "rtgs_query");
   if (got[1] > 0) {

@@ -396,7 +396,8 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
   const uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
-  for (int t = threadIdx.x; t < ts; t += kBinThreads) s_cur[t] = W.tile_start[S.tile_base + t] + h[t];
+  for (int t = threadIdx.x; t < ts; t += kBinThreads)
+    s_cur[t] = W.tile_start[S.tile_base + t] + h[t];
   stage_rects(S, W, c, s_rect);
   for (int i = threadIdx.x; i < kChunk; i += kBinThreads) {
     const int li = c * kChunk + i;

@@ -209,7 +209,8 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
         for (int k = 0; k < 3; ++k)
           gl[k] = sc[k] * (R[k] * dM[k] + R[3 + k] * dM[3 + k] + R[6 + k] * dM[6 + k]);
         // R(w, a, b, c) -> unit-quaternion gradient
-        const double gw = 2 * (-c * dR[1] + b * dR[2] + c * dR[3] - a * dR[5] - b * dR[6] + a * dR[7]);
+        const double gw =
+            2 * (-c * dR[1] + b * dR[2] + c * dR[3] - a * dR[5] - b * dR[6] + a * dR[7]);
         const double gx4 = 2 * (b * dR[1] + c * dR[2] + b * dR[3] - 2 * a * dR[4] - w * dR[5] +
                                 c * dR[6] + w * dR[7] - 2 * a * dR[8]);
         const double gy4 = 2 * (-2 * b * dR[0] + a * dR[1] + w * dR[2] + a * dR[3] + c * dR[5] -

@@ -18,12 +18,12 @@
 // as the reverse recurrence) and the normalised suffix colour/depth; the
 // per-fragment 2D gradients of one list entry are summed over the wave by a
 // reduce-scatter (lane swaps across halves and rows, then DPP row sums), the
-// four waves' sums are added in LDS in a fixed order, and the tile's total for that Gaussian is stored in the
-// pair's own slot: the pixel -> tile merge of the paper's Gradient Merging
-// Unit (Sec. 5.3) done with cross-lane operations.  The tile -> Gaussian
-// merge (its Stage Buffer) is a segmented sum over the Gaussian's slots in
-// the preprocessing backward; no float atomics anywhere, so gradients are
-// bitwise reproducible.
+// four waves' sums are added in LDS in a fixed order, and the tile's total for
+// that Gaussian is stored in the pair's own slot: the pixel -> tile merge of
+// the paper's Gradient Merging Unit (Sec. 5.3) done with cross-lane
+// operations.  The tile -> Gaussian merge (its Stage Buffer) is a segmented
+// sum over the Gaussian's slots in the preprocessing backward; no float
+// atomics anywhere, so gradients are bitwise reproducible.
 #include "rtgs_internal.h"
 
 namespace rtgs {
@@ -253,12 +253,15 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 
 // NV = 10 (all parameters: u, v, a, b, c, o, r, g, b, z) or 6 (pose only:
 // u, v, a, b, c, z).  GA: some session has an alpha-image gradient (without
-// one, its term of dL/dalpha is left out rather than added as zero).  Each (tile, Gaussian) pair gets the sum of its pixels'
-// gradients in slot pair_slot(); the sum is formed in a fixed order (lane
-// swaps and DPP row sums inside each wave, then the four waves in order), so the result is
-// bitwise reproducible and no float atomics are used.
+// one, its term of dL/dalpha is left out rather than added as zero).  Each
+// (tile, Gaussian) pair gets the sum of its pixels' gradients in slot
+// pair_slot(); the sum is formed in a fixed order (lane swaps and DPP row sums
+// inside each wave, then the four waves in order), so the result is bitwise
+// reproducible and no float atomics are used.  Eight waves per SIMD: the
+// compiler is held to 64 VGPRs.
 template <int NV, bool GA>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(Batch B, WsPtrs W) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
   __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch], s_cn[kBwdBatch];
   __shared__ unsigned s_m[kBwdBatch];
