@@ -104,3 +104,15 @@ def test_null_handle_and_bad_arguments_are_rejected_before_any_gpu_work():
     assert L.adam_step(None, None, 0, 0.9, 0.999, 1e-8, None) == rtgs.RTGS_ERR_INVALID_ARG
     assert L.loss_l1_grad(None, None, None, None, None, None, 0, 4, 1.0, 0.5, None, None,
                           None) == rtgs.RTGS_ERR_INVALID_ARG
+
+
+def test_missing_library_and_host_tensors_fail_loudly(monkeypatch):
+    """No fallback: a missing librtgs.so raises, and a host tensor is refused
+    before any pointer reaches the library."""
+    import torch
+    monkeypatch.setattr(rtgs, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "librtgs.so"))
+    monkeypatch.setattr(rtgs, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        rtgs.lib()
+    with pytest.raises(ValueError, match="GPU tensors only"):
+        rtgs._p(torch.zeros(4))
