@@ -30,41 +30,42 @@ namespace {
 
 // Tile -> Gaussian merge: 16 lanes (one DPP row) per Gaussian sum its pair
 // slots, strided, then a fixed DPP tree; lane 15 of the row stores the NV
-// totals.  Balanced however many tiles a Gaussian touches, deterministic.
+// totals.  A Gaussian with more than kMergeBig slots (a few hundred of 300k
+// touch up to ~1400 tiles) would make its row the kernel's critical path, so
+// its row hands it to the whole workgroup, whose 256 lanes sum it after the
+// rows are done.  Every sum is in a fixed order: deterministic.
+constexpr int kMergeBig = 128;
+
+// Lane `lane` of `width` adds slots lane, lane + width, ... of the n slots at
+// `first`; four slots are loaded per round, so that a long list does not
+// serialise on one load at a time.
 template <int NV>
-__global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
-  const int gid = blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int sub = threadIdx.x & 15;
-  float acc[NV];
+__device__ __forceinline__ void sum_slots(const WsPtrs& W, int64_t first, int64_t n, int lane,
+                                          int width, float (&acc)[NV]) {
+  for (int64_t k0 = lane; k0 < n; k0 += 4 * width) {
+    float v[4][NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.f;
-  if (gid < B.n_total) {
-    const int64_t first = W.goff[gid];
-    // slots past the pair capacity were never written
-    const int64_t n = min((int64_t)W.cnt[gid], W.cap - first);
-    // lane sub adds slots sub, sub + 16, sub + 32, ... in that order; four
-    // slots are loaded per round so that a Gaussian touching hundreds of
-    // tiles does not serialise on one load at a time
-    for (int64_t k0 = sub; k0 < n; k0 += 64) {
-      float v[4][NV];
+    for (int j = 0; j < 4; ++j) {
+      const int64_t k = k0 + (int64_t)width * j;
+      // a slot is NV floats at an 8-byte aligned offset: NV / 2 8-byte loads
+      const float2* p = reinterpret_cast<const float2*>(W.partial + (first + k) * NV);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t k = k0 + 16 * j;
-        // a slot is NV floats at an 8-byte aligned offset: NV / 2 8-byte loads
-        const float2* p = reinterpret_cast<const float2*>(W.partial + (first + k) * NV);
-#pragma unroll
-        for (int i = 0; i < NV / 2; ++i) {
-          const float2 x = k < n ? p[i] : make_float2(0.f, 0.f);
-          v[j][2 * i] = x.x;
-          v[j][2 * i + 1] = x.y;
-        }
+      for (int i = 0; i < NV / 2; ++i) {
+        const float2 x = k < n ? p[i] : make_float2(0.f, 0.f);
+        v[j][2 * i] = x.x;
+        v[j][2 * i + 1] = x.y;
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += v[j][i];
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v[j][i];
   }
+}
+
+// Sum over the 16 lanes of each DPP row; lane 15 of the row holds the total.
+template <int NV>
+__device__ __forceinline__ void row_sums(float (&acc)[NV]) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     float v = acc[i];
@@ -74,10 +75,60 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
     v += dpp_f<kDppRowShr8, 0xf, true>(v);
     acc[i] = v;
   }
-  if (sub == 15 && gid < B.n_total) {
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
+  __shared__ int s_big[16];
+  __shared__ int s_nbig;
+  __shared__ float s_row[16][NV];
+  const int row = threadIdx.x >> 4;
+  const int gid = blockIdx.x * 16 + row;
+  const int sub = threadIdx.x & 15;
+  if (threadIdx.x == 0) s_nbig = 0;
+  __syncthreads();
+  float acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.f;
+  bool mine = gid < B.n_total;
+  if (mine) {
+    const int64_t first = W.goff[gid];
+    // slots past the pair capacity were never written
+    const int64_t n = min((int64_t)W.cnt[gid], W.cap - first);
+    if (n > kMergeBig) {
+      mine = false;
+      if (sub == 0) s_big[atomicAdd(&s_nbig, 1)] = gid;
+    } else {
+      sum_slots<NV>(W, first, n, sub, 16, acc);
+    }
+  }
+  row_sums<NV>(acc);
+  if (sub == 15 && mine) {
     float* d = W.grad2d + (int64_t)gid * 10;
 #pragma unroll
     for (int i = 0; i < NV; ++i) d[i] = acc[i];
+  }
+  __syncthreads();
+  const int nbig = s_nbig;
+  for (int q = 0; q < nbig; ++q) {
+    // s_big's order depends on timing; each Gaussian's sum does not
+    const int g = s_big[q];
+    const int64_t first = W.goff[g];
+    const int64_t n = min((int64_t)W.cnt[g], W.cap - first);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.f;
+    sum_slots<NV>(W, first, n, (int)threadIdx.x, 256, acc);
+    row_sums<NV>(acc);
+    if (sub == 15)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) s_row[row][i] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+      float t = 0.f;
+      for (int r = 0; r < 16; ++r) t += s_row[r][threadIdx.x];
+      W.grad2d[(int64_t)g * 10 + threadIdx.x] = t;
+    }
+    __syncthreads();                      // s_row is reused by the next one
   }
 }
 

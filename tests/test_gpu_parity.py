@@ -228,6 +228,50 @@ def test_capacity_overflow_is_reported_then_recovers():
     assert rel_err(st2.color.cpu().numpy(), ref.color.numpy(), keep) < IMG_TOL
 
 
+def test_backward_gaussians_touching_many_tiles(renderer):
+    """Per-Gaussian gradients when some Gaussians cover most of a 40 x 32 tile
+    frame: several such Gaussians in one group of 16 consecutive indices (the
+    merge hands each one to a whole workgroup), one alone in another group,
+    and some with a few hundred tiles; dense upstream gradients."""
+    say("test_backward_gaussians_touching_many_tiles")
+    cam = synth.make_camera(640, 512)
+    rng = np.random.default_rng(21)
+    n = 400
+    z = rng.uniform(2.0, 6.0, n)
+    u = rng.uniform(0, 640, n)
+    v = rng.uniform(0, 512, n)
+    sig_px = rng.uniform(3.0, 8.0, n)
+    logit = rng.uniform(-1.0, 2.0, n)
+    big = np.r_[0:6, 20]
+    mid = np.r_[40:44]
+    u[big], v[big], sig_px[big], logit[big] = 320, 256, 150.0, -3.0
+    z[big] = 3.4 + 0.2 * np.arange(len(big))    # distinct depths: no order ties
+    sig_px[mid], logit[mid] = 40.0, -2.0
+    means = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z], 1)
+    log_s = np.log(sig_px * z / cam.fx)[:, None] + rng.uniform(-0.2, 0.2, (n, 3))
+    q = rng.normal(size=(n, 4))
+    sc = synth.Scene(means.astype(np.float32), log_s.astype(np.float32),
+                     (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32),
+                     logit.astype(np.float32), rng.random((n, 3)).astype(np.float32))
+    view = eye_view()
+    st = renderer.forward(dev_scene(sc), torch.from_numpy(view).cuda(), rcam(cam))
+    dbg = st.stage()
+    stg = dbg["stage"]
+    _, ids = binning.tile_lists(stg[:, 0], stg[:, 1], stg[:, 7], stg[:, 8], stg[:, 6],
+                                np.ones(n, bool), cam.width, cam.height)
+    slots = np.bincount(ids, minlength=n)
+    say(f"  slots: big {slots[big].min()}..{slots[big].max()}, "
+        f"mid {slots[mid].min()}..{slots[mid].max()}, others max {np.delete(slots, np.r_[big, mid]).max()}")
+    assert slots[big].min() > 1024 and 128 < slots[mid].min() and slots[mid].max() <= 1024
+    g, ref, _ = _grad_case(renderer, sc, cam, view)
+    for name in ("means", "log_scales", "quats", "opacity_logits", "colors"):
+        r = getattr(ref, name).numpy()
+        e1, e2 = grad_err(g[name], r), norm_err(g[name], r)
+        say(f"  {name}: rel {e1:.2e} norm {e2:.2e}")
+        assert e1 < GRAD_TOL and e2 < GRAD_TOL, name
+    assert rel_err(g["pose"], ref.pose.numpy()) < GRAD_TOL
+
+
 @pytest.mark.parametrize("n,span,lo,hi", [(900, 8, 700, 1024), (2500, 8, 1025, 4096),
                                           (6000, 8, 4097, 8192), (9000, 8, 8193, 10 ** 9),
                                           (9000, 24, 1025, 4096)])
