@@ -28,13 +28,15 @@
 namespace rtgs {
 namespace {
 
-// Tile -> Gaussian merge: 16 lanes (one DPP row) per Gaussian sum its pair
-// slots, strided, then a fixed DPP tree; lane 15 of the row stores the NV
-// totals.  A Gaussian with more than kMergeBig slots (a few hundred of 300k
+// Tile -> Gaussian merge: kMergeLanes lanes (part of a DPP row) per Gaussian
+// sum its pair slots, strided, then a fixed DPP tree; the last of them stores
+// the NV totals.  A Gaussian with more than kMergeBig slots (a few hundred of 300k
 // touch up to ~1400 tiles) would make its row the kernel's critical path, so
 // its row hands it to the whole workgroup, whose 256 lanes sum it after the
 // rows are done.  Every sum is in a fixed order: deterministic.
 constexpr int kMergeBig = 128;
+constexpr int kMergeLanes = 8;            // lanes per Gaussian (a half DPP row)
+constexpr int kMergePerBlock = 256 / kMergeLanes;
 
 // Lane `lane` of `width` adds slots lane, lane + width, ... of the n slots at
 // `first`; four slots are loaded per round, so that a long list does not
@@ -63,8 +65,9 @@ __device__ __forceinline__ void sum_slots(const WsPtrs& W, int64_t first, int64_
   }
 }
 
-// Sum over the 16 lanes of each DPP row; lane 15 of the row holds the total.
-template <int NV>
+// Sums over runs of LANES (8 or 16) lanes of each DPP row; the run's last
+// lane holds its total.
+template <int LANES, int NV>
 __device__ __forceinline__ void row_sums(float (&acc)[NV]) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -72,19 +75,19 @@ __device__ __forceinline__ void row_sums(float (&acc)[NV]) {
     v += dpp_f<kDppRowShr1, 0xf, true>(v);
     v += dpp_f<kDppRowShr2, 0xf, true>(v);
     v += dpp_f<kDppRowShr4, 0xf, true>(v);
-    v += dpp_f<kDppRowShr8, 0xf, true>(v);
+    if (LANES == 16) v += dpp_f<kDppRowShr8, 0xf, true>(v);
     acc[i] = v;
   }
 }
 
 template <int NV>
 __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
-  __shared__ int s_big[16];
+  __shared__ int s_big[kMergePerBlock];
   __shared__ int s_nbig;
   __shared__ float s_row[16][NV];
   const int row = threadIdx.x >> 4;
-  const int gid = blockIdx.x * 16 + row;
-  const int sub = threadIdx.x & 15;
+  const int gid = blockIdx.x * kMergePerBlock + (int)threadIdx.x / kMergeLanes;
+  const int sub = threadIdx.x % kMergeLanes;
   if (threadIdx.x == 0) s_nbig = 0;
   __syncthreads();
   float acc[NV];
@@ -99,11 +102,11 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
       mine = false;
       if (sub == 0) s_big[atomicAdd(&s_nbig, 1)] = gid;
     } else {
-      sum_slots<NV>(W, first, n, sub, 16, acc);
+      sum_slots<NV>(W, first, n, sub, kMergeLanes, acc);
     }
   }
-  row_sums<NV>(acc);
-  if (sub == 15 && mine) {
+  row_sums<kMergeLanes, NV>(acc);
+  if (sub == kMergeLanes - 1 && mine) {
     float* d = W.grad2d + (int64_t)gid * 10;
 #pragma unroll
     for (int i = 0; i < NV; ++i) d[i] = acc[i];
@@ -118,8 +121,8 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.f;
     sum_slots<NV>(W, first, n, (int)threadIdx.x, 256, acc);
-    row_sums<NV>(acc);
-    if (sub == 15)
+    row_sums<16, NV>(acc);
+    if ((threadIdx.x & 15) == 15)
 #pragma unroll
       for (int i = 0; i < NV; ++i) s_row[row][i] = acc[i];
     __syncthreads();
@@ -364,7 +367,7 @@ hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags
                                  StageTimer* tm) {
   if (b.n_total > 0) {
     Scope sc(tm, kStMerge, st);
-    const int grid = (b.n_total + 15) / 16;
+    const int grid = (b.n_total + kMergePerBlock - 1) / kMergePerBlock;
     if (grad_flags & RTGS_GRAD_MAP)
       k_merge<10><<<grid, 256, 0, st>>>(b, w);
     else
