@@ -9,4 +9,4 @@ seeded synthetic scenes.
 Importing this package does not load the native library; the binding loads it
 on first use and raises if it is missing.
 """
-__all__ = ["synth", "rtgs", "autograd", "serving", "slam"]
+__all__ = ["synth", "rtgs", "autograd", "serving", "optim", "pose", "prune"]

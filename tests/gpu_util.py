@@ -45,7 +45,14 @@ def rcam(cam):
 
 
 def cam_tuple(cam):
-    return (cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+    """Camera for the oracle: the intrinsics the library receives, i.e. rounded
+    to float32 (the C ABI's rtgs_camera carries float fx, fy, cx, cy), so
+    that both sides project with the same camera.  0.8 W is not a float32
+    for most W: at 96 px wide, fx = 76.8 rounds by 4e-8 relative, which moves
+    a centre 40 px off axis by 1.6e-6 px and a small Gaussian's alpha by about
+    2e-6 relative."""
+    f = lambda x: float(np.float32(x))
+    return (cam.width, cam.height, f(cam.fx), f(cam.fy), f(cam.cx), f(cam.cy))
 
 
 def rel_err(x, r, mask=None, floor_frac=1e-2):
@@ -62,11 +69,11 @@ def rel_err(x, r, mask=None, floor_frac=1e-2):
 
 
 def grad_err(x, r, floor_frac=1e-2):
-    """Relative error of per-Gaussian gradient vectors: row i of [N, k] is one
-    Gaussian's gradient with respect to one parameter group; its error is
-    |x_i - r_i| / max(|r_i|, floor_frac max_j |r_j|) in the Euclidean norm,
-    and the result is the largest over the rows.  [N] arrays (one scalar per
-    Gaussian) reduce to `rel_err`."""
+    """Relative error of a per-Gaussian gradient [N, k] (row i is Gaussian i's
+    gradient with respect to one parameter group), the larger of two rules:
+    per row, |x_i - r_i| / max(|r_i|, floor_frac max_j |r_j|) in the Euclidean
+    norm; per component, the element rule of `rel_err`.  [N] arrays (one
+    scalar per Gaussian) reduce to `rel_err`."""
     x = np.asarray(x, np.float64)
     r = np.asarray(r, np.float64)
     if r.ndim == 1:
@@ -76,10 +83,67 @@ def grad_err(x, r, floor_frac=1e-2):
         return 0.0
     rn = np.linalg.norm(r, axis=1)
     den = np.maximum(rn, floor_frac * max(rn.max(), 1e-30))
-    return float((np.linalg.norm(x - r, axis=1) / den).max())
+    row = float((np.linalg.norm(x - r, axis=1) / den).max())
+    return max(row, rel_err(x, r, floor_frac=floor_frac))
 
 
 def norm_err(x, r):
     x = np.asarray(x, np.float64).ravel()
     r = np.asarray(r, np.float64).ravel()
     return float(np.linalg.norm(x - r) / max(np.linalg.norm(r), 1e-30))
+
+
+def component_err(x, r, floor_frac=1e-2):
+    """Worst per-component error of a gradient tensor (the element rule of
+    `rel_err`), printed beside `grad_err`."""
+    return rel_err(x, r, floor_frac=floor_frac)
+
+
+MAP_GRADS = ("means", "log_scales", "quats", "opacity_logits", "colors")
+
+
+def full_frame_parity(renderer, sc, cam, view, seed=7, pixel_mask=None, label=""):
+    """Forward and backward of one frame on the GPU against the oracle, over
+    every pixel: stage-independent outputs (colour, depth, alpha, final T,
+    last Gaussian id) element-wise on the pixels the oracle does not flag,
+    and all map gradients plus the pose gradient with dense random upstream
+    gradients (zeroed on flagged pixels on both sides).  Returns the GPU
+    forward state, the oracle forward, the GPU gradients and the oracle
+    gradients for case-specific checks."""
+    import oracle
+    dsc = dev_scene(sc)
+    dview = torch.from_numpy(view).cuda()
+    pm = None if pixel_mask is None else torch.from_numpy(pixel_mask).cuda()
+    st = renderer.forward(dsc, dview, rcam(cam), pixel_mask=pm)
+    torch.cuda.synchronize()
+    ref = oracle.render(sc.arrays(), view, cam_tuple(cam), pixel_mask=pixel_mask)
+    flags = ref.flags.numpy()
+    keep = ~flags
+    say(f"  {label}: flagged pixels {int(flags.sum())} of {flags.size}")
+    assert flags.mean() < 0.002
+    for k, r in (("color", ref.color), ("depth", ref.depth), ("alpha", ref.alpha),
+                 ("final_T", ref.final_t)):
+        e = rel_err(getattr(st, k).cpu().numpy(), r.numpy(), keep)
+        assert e < IMG_TOL, (k, e)
+    ids = st.stage()["ids"]
+    last = st.last_idx.cpu().numpy()
+    gid = np.where(last >= 0, ids[np.maximum(last, 0)], -1)
+    assert np.array_equal(gid[keep], ref.last_id.numpy()[keep])
+    gc, gd, ga = synth.upstream_grads(cam.width, cam.height, seed)
+    gc, gd, ga = gc * keep[None], gd * keep, ga * keep
+    g = renderer.backward(dsc, dview, rcam(cam), st, torch.from_numpy(gc).cuda(),
+                          torch.from_numpy(gd).cuda(), torch.from_numpy(ga).cuda(),
+                          pixel_mask=pm)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    _, rg = oracle.render_with_grads(sc.arrays(), view, cam_tuple(cam), gc, gd, ga,
+                                     pixel_mask=pixel_mask)
+    for name in MAP_GRADS:
+        r = getattr(rg, name).numpy()
+        e1, e2, e3 = grad_err(g[name], r), norm_err(g[name], r), component_err(g[name], r)
+        say(f"  {label} {name}: rel {e1:.2e} norm {e2:.2e} (worst component {e3:.2e})")
+        assert e1 < GRAD_TOL and e2 < GRAD_TOL, name
+    e = rel_err(g["pose"], rg.pose.numpy())
+    say(f"  {label} pose: {e:.2e}")
+    assert e < GRAD_TOL
+    return st, ref, g, rg

@@ -230,9 +230,10 @@ def test_capacity_overflow_is_reported_then_recovers():
 
 def test_backward_gaussians_touching_many_tiles(renderer):
     """Per-Gaussian gradients when some Gaussians cover most of a 40 x 32 tile
-    frame: several such Gaussians in one group of 16 consecutive indices (the
-    merge hands each one to a whole workgroup), one alone in another group,
-    and some with a few hundred tiles; dense upstream gradients."""
+    frame: six such Gaussians in one merge workgroup (32 consecutive indices;
+    the merge hands each one to the whole workgroup), one alone in another
+    workgroup, and some with a few hundred tiles (summed by their own lanes);
+    dense upstream gradients."""
     say("test_backward_gaussians_touching_many_tiles")
     cam = synth.make_camera(640, 512)
     rng = np.random.default_rng(21)
@@ -242,7 +243,7 @@ def test_backward_gaussians_touching_many_tiles(renderer):
     v = rng.uniform(0, 512, n)
     sig_px = rng.uniform(3.0, 8.0, n)
     logit = rng.uniform(-1.0, 2.0, n)
-    big = np.r_[0:6, 20]
+    big = np.r_[0:6, 70]        # 0-5 in workgroup 0, 70 alone in workgroup 2
     mid = np.r_[40:44]
     u[big], v[big], sig_px[big], logit[big] = 320, 256, 150.0, -3.0
     z[big] = 3.4 + 0.2 * np.arange(len(big))    # distinct depths: no order ties

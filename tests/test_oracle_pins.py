@@ -303,6 +303,41 @@ def test_tile_lists_match_bruteforce_loop_with_sorted_tuples():
         assert got == want
 
 
+@pytest.mark.parametrize("tw,th", [(16, 16), (32, 16), (32, 32), (64, 32)])
+def test_tile_lists_at_any_tile_size_match_per_pixel_bruteforce(tw, th):
+    # membership by pixels, not rectangles: Gaussian g is in tile t iff some
+    # pixel (i, j) of t satisfies a - 1 < i < b + 1 on both axes, with
+    # a = (u - e) - 1.5 and b = (u + e) + 0.5 formed in float32 (integers
+    # i in [floor(a), ceil(b)]); then sorted() on (depth bits, id) tuples.
+    # Covers the coarse tiles of downsampled frames and ragged edges.
+    w, h = 100, 70
+    cam = synth.Camera(w, h, 80.0, 80.0, 50.0, 35.0)
+    sc = synth.make_scene(synth.SceneSpec("t", w, h, 250, 17), cam)
+    u, v, ex, ey, z, valid, _ = _stage32(sc, cam)
+    u[:3] = [-9.0, w + 6.0, 50.0]        # partly or wholly off screen
+    ex[:3] = [12.0, 3.0, 60.0]
+    ranges, ids = binning.tile_lists(u, v, ex, ey, z, valid, w, h, tw, th)
+    f = np.float32
+    ax, bx = ((u - ex) - f(1.5)).astype(np.float64), ((u + ex) + f(0.5)).astype(np.float64)
+    ay, by = ((v - ey) - f(1.5)).astype(np.float64), ((v + ey) + f(0.5)).astype(np.float64)
+    ntx, nty = -(-w // tw), -(-h // th)
+    assert len(ranges) == ntx * nty
+    for t in range(ntx * nty):
+        tx, ty = t % ntx, t // ntx
+        xs = np.arange(tx * tw, min((tx + 1) * tw, w))
+        ys = np.arange(ty * th, min((ty + 1) * th, h))
+        members = []
+        for g in range(len(u)):
+            if not valid[g]:
+                continue
+            inx = np.any((ax[g] - 1 < xs) & (xs < bx[g] + 1))
+            iny = np.any((ay[g] - 1 < ys) & (ys < by[g] + 1))
+            if inx and iny:
+                members.append(g)
+        want = [g for _, g in sorted((int(np.float32(z[g]).view(np.uint32)), g) for g in members)]
+        assert ids[ranges[t, 0]:ranges[t, 1]].tolist() == want, (t, tw, th)
+
+
 def test_tile_rect_rule_by_hand():
     # centre 20.3, half-width 3.2: pixels [15, 24] -> tiles 0..1
     tx0, ty0, tx1, ty1 = binning.tile_rects([20.3], [5.0], [3.2], [1.0], [True], 64, 64)
@@ -420,6 +455,64 @@ def test_ambiguity_flags_mark_threshold_cases():
     assert out.flags.sum() < 10
     far = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam), band_alpha=1e-9)
     assert not far.flags[32, 32]
+
+
+def _centred(cam, z):
+    """Mean whose projection is the sample point of pixel (32, 32)."""
+    return [(32.5 - cam.cx) * z / cam.fx, (32.5 - cam.cy) * z / cam.fy, z]
+
+
+def test_ambiguity_flags_mark_the_clamp_band():
+    # a Gaussian centred on pixel (32, 32) has alpha~ = o there; o just above
+    # the 0.99 clamp (3e-5 relative) is inside the 1e-4 band, 3e-3 is not
+    cam = CAM64
+    near = one_gaussian_scene(_centred(cam, 2.0), math.log(0.05), 0.99 * (1 + 3e-5), [1, 1, 1])
+    out = oracle.render(near.arrays(), _eye_view(), cam_tuple(cam))
+    assert out.flags[32, 32] and out.n_blended[32, 32].item() == 1
+    far = one_gaussian_scene(_centred(cam, 2.0), math.log(0.05), 0.99 * (1 + 3e-3), [1, 1, 1])
+    out = oracle.render(far.arrays(), _eye_view(), cam_tuple(cam))
+    assert not out.flags[32, 32]
+    # the same opacity with a narrower band is not flagged either
+    out = oracle.render(near.arrays(), _eye_view(), cam_tuple(cam), band_alpha=1e-6)
+    assert not out.flags[32, 32]
+
+
+def test_ambiguity_flags_mark_the_stop_band():
+    # four Gaussians of opacity 0.9 centred on one pixel: after the fourth,
+    # T = 0.1^4 = 1e-4 up to the float32 rounding of the opacity (about 4e-7
+    # relative), i.e. on the early-termination threshold
+    cam = CAM64
+    zs = 1.0 + 0.1 * np.arange(4)
+    sc = one_gaussian_scene([_centred(cam, z) for z in zs], math.log(0.05), 0.9, [1, 1, 1])
+    o = 1 / (1 + math.exp(-float(sc.opacity_logits[0])))
+    assert abs((1 - o) ** 4 / 1e-4 - 1) < 1e-5
+    out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam))
+    assert out.flags[32, 32]
+    out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam), band_t=1e-9)
+    assert not out.flags[32, 32]
+    # three of them end at T = 1e-3: far from the stop, not flagged
+    sc3 = one_gaussian_scene([_centred(cam, z) for z in zs[:3]], math.log(0.05), 0.9, [1, 1, 1])
+    out = oracle.render(sc3.arrays(), _eye_view(), cam_tuple(cam))
+    assert not out.flags[32, 32] and out.n_blended[32, 32].item() == 3
+
+
+@pytest.mark.parametrize("rel,flagged", [(5e-7, True), (1e-5, False)])
+def test_ambiguity_flags_mark_near_equal_depths(rel, flagged):
+    # two Gaussians over one pixel whose depths differ by `rel` relative: below
+    # the 1e-6 band float32 may order them either way
+    cam = CAM64
+    z = 2.0
+    sc = one_gaussian_scene([_centred(cam, z), _centred(cam, z * (1 + rel))], math.log(0.05),
+                            [0.5, 0.6], [[1, 0, 0], [0, 0, 1]])
+    out = oracle.render(sc.arrays(), _eye_view(), cam_tuple(cam))
+    assert out.n_blended[32, 32].item() == 2
+    assert bool(out.flags[32, 32]) == flagged
+    # a Gaussian that never blends at the pixel (culled by the 1/255 floor)
+    # does not make a near-tie: move the second one far off
+    off = one_gaussian_scene([_centred(cam, z), [1.0, 1.0, z * (1 + rel)]], math.log(0.05),
+                             [0.5, 0.6], [[1, 0, 0], [0, 0, 1]])
+    out = oracle.render(off.arrays(), _eye_view(), cam_tuple(cam))
+    assert not out.flags[32, 32]
 
 
 def test_pose_gradient_is_the_left_perturbation_of_the_viewmat_gradient():
