@@ -377,6 +377,22 @@ int32_t compact_by_mask(const uint8_t* drop, int32_t n,
                         void* scratch, uint64_t scratch_bytes,
                         int32_t* n_kept, void* stream);
 
+/* compact_by_mask without allocation and without a caller scratch, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * result and errors as compact_by_mask, without scratch / scratch_bytes; the
+ * library's own device scratch (64 KB per GPU, a static device array held
+ * until the process ends) limits n to RTGS_COMPACT_STATIC_MAX_ROWS: larger n
+ * returns RTGS_ERR_WORKSPACE.  No memory is allocated or freed; the first
+ * call on a GPU looks up the scratch's address there.  The stream must belong
+ * to the current device (else RTGS_ERR_INVALID_ARG).  Every call on one GPU
+ * shares that scratch: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. */
+#define RTGS_COMPACT_STATIC_MAX_ROWS 16776192   /* (16384 - 1) * 1024 */
+int32_t compact_by_mask_static(const uint8_t* drop, int32_t n,
+                               const rtgs_compact_item* items, int32_t n_items,
+                               int32_t* n_kept, void* stream);
+
 /* The tile rectangle of every Gaussian after a full render_fwd on ws (the
  * same n, width, height, sample_log2 and pair_capacity as that call):
  * rect_out (device int32 [n][4]) = (x0, y0, x1, y1) in tiles, inclusive,

@@ -758,19 +758,14 @@ uint64_t rtgs_compact_scratch_size(int32_t n) {
   return 4 * (nb + 1);
 }
 
-int32_t compact_by_mask(const uint8_t* drop, int32_t n, const rtgs_compact_item* items,
-                        int32_t n_items, void* scratch, uint64_t scratch_bytes, int32_t* n_kept,
-                        void* stream) {
+// Validates a compaction call and fills its kernel arguments (scratch not set).
+static int32_t compact_args(const uint8_t* drop, int32_t n, const rtgs_compact_item* items,
+                            int32_t n_items, int32_t* n_kept, CompactArgs& a) {
   if (n < 0) return fail(RTGS_ERR_INVALID_ARG, "n = %d", n);
   if (n_items < 0 || n_items > kCompactMaxItems || (n_items > 0 && !items))
     return fail(RTGS_ERR_INVALID_ARG, "bad item list (n_items = %d)", n_items);
-  if (!n_kept || !scratch || (n > 0 && !drop))
-    return fail(RTGS_ERR_INVALID_ARG, "null drop mask, count or scratch");
-  if (scratch_bytes < rtgs_compact_scratch_size(n))
-    return fail(RTGS_ERR_WORKSPACE, "compaction scratch %llu < %llu bytes",
-                (unsigned long long)scratch_bytes,
-                (unsigned long long)rtgs_compact_scratch_size(n));
-  CompactArgs a{};
+  if (!n_kept || (n > 0 && !drop))
+    return fail(RTGS_ERR_INVALID_ARG, "null drop mask or count");
   for (int i = 0; i < n_items; ++i) {
     const rtgs_compact_item& it = items[i];
     if ((n > 0 && !it.src) || (it.dst_rows > 0 && !it.dst) || it.row_bytes <= 0 ||
@@ -793,10 +788,57 @@ int32_t compact_by_mask(const uint8_t* drop, int32_t n, const rtgs_compact_item*
   a.n_items = n_items;
   a.n = n;
   a.drop = drop;
-  a.block_keep = static_cast<uint32_t*>(scratch);
   a.n_kept = n_kept;
+  return RTGS_OK;
+}
+
+int32_t compact_by_mask(const uint8_t* drop, int32_t n, const rtgs_compact_item* items,
+                        int32_t n_items, void* scratch, uint64_t scratch_bytes, int32_t* n_kept,
+                        void* stream) {
+  CompactArgs a{};
+  int32_t r = compact_args(drop, n, items, n_items, n_kept, a);
+  if (r) return r;
+  if (!scratch) return fail(RTGS_ERR_INVALID_ARG, "null scratch");
+  if (scratch_bytes < rtgs_compact_scratch_size(n))
+    return fail(RTGS_ERR_WORKSPACE, "compaction scratch %llu < %llu bytes",
+                (unsigned long long)scratch_bytes,
+                (unsigned long long)rtgs_compact_scratch_size(n));
+  a.block_keep = static_cast<uint32_t*>(scratch);
   hipError_t e = launch_compact(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "compact_by_mask launch");
+  return RTGS_OK;
+}
+
+int32_t compact_by_mask_static(const uint8_t* drop, int32_t n, const rtgs_compact_item* items,
+                               int32_t n_items, int32_t* n_kept, void* stream) {
+  CompactArgs a{};
+  int32_t r = compact_args(drop, n, items, n_items, n_kept, a);
+  if (r) return r;
+  if (n > RTGS_COMPACT_STATIC_MAX_ROWS)
+    return fail(RTGS_ERR_WORKSPACE,
+                "compact_by_mask_static: n = %d rows exceeds the static scratch's maximum of "
+                "%d rows (use compact_by_mask with a caller scratch)",
+                n, RTGS_COMPACT_STATIC_MAX_ROWS);
+  static_assert(RTGS_COMPACT_STATIC_MAX_ROWS ==
+                    (int64_t)(kCompactStaticWords - 1) * kCompactBlock,
+                "the header's row limit matches the device scratch");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (st) {
+    int cur = 0, sd = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess) e = hipStreamGetDevice(st, &sd);
+    if (e != hipSuccess) return hip_fail(e, "compact_by_mask_static device query");
+    if (sd != cur)
+      return fail(RTGS_ERR_INVALID_ARG,
+                  "compact_by_mask_static: the stream belongs to device %d, device %d is current",
+                  sd, cur);
+  }
+  uint32_t* ptr = nullptr;
+  hipError_t e = compact_static_scratch(&ptr);
+  if (e != hipSuccess) return hip_fail(e, "compact_by_mask_static scratch address");
+  a.block_keep = ptr;
+  e = launch_compact(a, st);
+  if (e != hipSuccess) return hip_fail(e, "compact_by_mask_static launch");
   return RTGS_OK;
 }
 

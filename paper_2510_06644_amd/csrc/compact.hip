@@ -2,9 +2,20 @@
 // masked for K iterations are then permanently removed (stable compaction of
 // every per-Gaussian array), and the next interval K follows the change ratio
 // of tile-Gaussian intersections over the interval.
+#include <mutex>
+
 #include "rtgs_internal.h"
 
 namespace rtgs {
+
+// Scratch of the allocation-free compaction (compact_by_mask_static): the
+// per-block kept counts, one word per kCompactBlock rows plus one, so at most
+// (kCompactStaticWords - 1) * kCompactBlock rows.  A file-scope device array:
+// every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in; kernels get the device
+// address that hipGetSymbolAddress returns for the current GPU.
+static __device__ __align__(256) uint32_t scratch[kCompactStaticWords];
+
 namespace {
 
 static_assert(sizeof(CompactArgs) <= 4000, "compaction table must fit the kernel arguments");
@@ -128,6 +139,26 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t st) {
   k_compact_scan<<<1, kCompactBlock, 0, st>>>(a, nb);
   k_compact_scatter<<<nb, kCompactBlock, 0, st>>>(a);
   return hipGetLastError();
+}
+
+hipError_t compact_static_scratch(uint32_t** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static uint32_t* ptr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    // once per device, with that device current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_rect_change(const int32_t* a, const int32_t* b, const uint8_t* skip, int n,

@@ -289,6 +289,10 @@ struct CompactArgs {
   int32_t* n_kept;
 };
 hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
+// Words of compact_by_mask_static's device scratch, and its address on the
+// current GPU (taken once per GPU; no allocation).
+constexpr int kCompactStaticWords = 16384;
+hipError_t compact_static_scratch(uint32_t** out);
 hipError_t launch_rect_change(const int32_t* a, const int32_t* b, const uint8_t* skip, int n,
                               int64_t* out, hipStream_t st);
 

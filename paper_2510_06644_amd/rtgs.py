@@ -51,6 +51,7 @@ EXPORTS = (
     "rtgs_query", "rtgs_debug_stage", "rtgs_selftest_wave_sum", "rtgs_profile_enable",
     "rtgs_profile_read", "adam_step", "loss_l1_grad", "pose_update", "compact_by_mask",
     "rtgs_compact_scratch_size", "rtgs_tile_rects", "tile_pair_change", "loss_l1_grad_batched",
+    "compact_by_mask_static",
 )
 
 vp = ctypes.c_void_p
@@ -139,6 +140,8 @@ def lib():
             L.rtgs_compact_scratch_size.restype = u64
             L.compact_by_mask.argtypes = [vp, i32, ctypes.POINTER(CCompactItem), i32, vp, u64,
                                           vp, vp]
+            L.compact_by_mask_static.argtypes = [vp, i32, ctypes.POINTER(CCompactItem), i32, vp,
+                                                 vp]
             L.rtgs_tile_rects.argtypes = [i32, i32, i32, i32, i64, vp, u64, vp, vp]
             L.tile_pair_change.argtypes = [vp, vp, vp, i32, vp, vp]
             L.loss_l1_grad_batched.argtypes = [ctypes.POINTER(CLossItem), i32, f32, f32, vp]
@@ -361,12 +364,10 @@ def loss_l1_grad_batched(items, w_color=1.0, w_depth=0.5, stream=None):
 RTGS_COMPACT_MAX_ITEMS = 24
 
 
-def compact_by_mask(drop, pairs, n_kept, scratch=None, stream=None):
-    """Stable removal of the rows i with drop[i] != 0 (drop: device uint8 [n]):
-    for each (src, dst) pair of contiguous device tensors with n rows, dst[:k]
-    receives the kept rows of src in order (k is written to the device int32
-    n_kept).  dst needs at least the kept rows."""
-    n = drop.numel()
+RTGS_COMPACT_STATIC_MAX_ROWS = 16776192
+
+
+def _compact_items(n, pairs):
     pairs = list(pairs)
     if len(pairs) > RTGS_COMPACT_MAX_ITEMS:
         raise ValueError(f"compact_by_mask: at most {RTGS_COMPACT_MAX_ITEMS} arrays")
@@ -379,12 +380,31 @@ def compact_by_mask(drop, pairs, n_kept, scratch=None, stream=None):
         row = math.prod(src.shape[1:]) * src.element_size()
         _p(src), _p(dst)            # device, contiguous
         arr[k] = CCompactItem(src.data_ptr(), dst.data_ptr(), row, dst.shape[0])
+    return arr, len(pairs)
+
+
+def compact_by_mask(drop, pairs, n_kept, scratch=None, stream=None):
+    """Stable removal of the rows i with drop[i] != 0 (drop: device uint8 [n]):
+    for each (src, dst) pair of contiguous device tensors with n rows, dst[:k]
+    receives the kept rows of src in order (k is written to the device int32
+    n_kept).  dst needs at least the kept rows."""
+    n = drop.numel()
+    arr, k = _compact_items(n, pairs)
     need = int(lib().rtgs_compact_scratch_size(n))
     if scratch is None:
         scratch = torch.empty(max(need, 4), dtype=torch.uint8, device=drop.device)
-    _check(lib().compact_by_mask(_p(drop), n, arr, len(pairs), _p(scratch),
+    _check(lib().compact_by_mask(_p(drop), n, arr, k, _p(scratch),
                                  scratch.numel() * scratch.element_size(), _p(n_kept),
                                  _stream(stream)))
+
+
+def compact_by_mask_static(drop, pairs, n_kept, stream=None):
+    """compact_by_mask with the library's static device scratch: no allocation
+    (n at most RTGS_COMPACT_STATIC_MAX_ROWS; calls on one GPU must not
+    overlap)."""
+    n = drop.numel()
+    arr, k = _compact_items(n, pairs)
+    _check(lib().compact_by_mask_static(_p(drop), n, arr, k, _p(n_kept), _stream(stream)))
 
 
 def rtgs_tile_rects(st, rect_out, stream=None):

@@ -116,3 +116,15 @@ def test_missing_library_and_host_tensors_fail_loudly(monkeypatch):
         rtgs.lib()
     with pytest.raises(ValueError, match="GPU tensors only"):
         rtgs._p(torch.zeros(4))
+
+
+def test_static_compaction_rejects_rows_beyond_its_scratch():
+    # argument checks run on the host before any device call
+    L = rtgs.lib()
+    dummy = ctypes.c_void_p(16)          # never dereferenced: the call fails first
+    n = rtgs.RTGS_COMPACT_STATIC_MAX_ROWS + 1
+    code = L.compact_by_mask_static(dummy, n, None, 0, dummy, None)
+    assert code == rtgs.RTGS_ERR_WORKSPACE
+    assert b"maximum" in L.rtgs_last_error()
+    assert L.compact_by_mask_static(None, 5, None, 0, dummy, None) == rtgs.RTGS_ERR_INVALID_ARG
+    assert L.compact_by_mask_static(dummy, -1, None, 0, dummy, None) == rtgs.RTGS_ERR_INVALID_ARG
