@@ -79,6 +79,8 @@ class Frame:
     started: float = -1.0
     done_event: object = None
     done_time: float = -1.0
+    pose_from: int = -1             # frame whose end pose (and final T) this one starts from
+    version: int = 0                # map version it renders (async mapping)
 
     @property
     def remaining(self):
@@ -95,8 +97,8 @@ class MapJob:
     tracking frames when mapping is asynchronous (ServeConfig.async_mapping):
     the keyframe's result (its pose) is ready when its tracking ends, and its
     map update follows, as in keyframe-based SLAM systems that map in a
-    separate thread.  A newer keyframe of the session replaces a job that has
-    not started yet."""
+    separate thread.  A session's jobs run one at a time in keyframe order;
+    each turns map version v into v + 1."""
     session: int
     index: int
     arrival: float                  # the keyframe's arrival
@@ -153,8 +155,21 @@ class ServeConfig:
     map_every: int = 1
     max_map_batch: int = 16         # map jobs in flight at once (async_mapping)
     # a session's next frame may start before its previous frame's tracking
-    # ends; it starts from the session's latest pose estimate
+    # ends (at most two frames of a session in flight)
     overlap_frames: bool = False
+    # with async_mapping, frame i renders map version V(i): the map after the
+    # jobs of the keyframes k <= i - map_lag, waiting for it if it is not
+    # ready; a fixed version per frame keeps every result a function of the
+    # trace alone, whatever the batching
+    map_lag: int = 8
+
+    @property
+    def pose_lag(self):
+        """Frame i starts from the end pose of frame i - pose_lag (and a
+        downsampled frame takes its pixel mask from that frame's final
+        transmittance): the previous frame, or the one before it when frames
+        overlap."""
+        return 2 if self.overlap_frames else 1
 
 
 # --------------------------------------------------------------------------- engine
@@ -178,20 +193,50 @@ class Engine:
         self.iters = 0
         self.batch_sizes = []
         self.last_key = [-1] * len(self.specs)
-        self.map_pending = {}                  # session -> MapJob not started
+        ns = len(self.specs)
+        self.next_admit = [0] * ns             # next frame index to admit per session
+        self.track_done = [set() for _ in range(ns)]
+        self.jobs_done = [0] * ns              # finished map jobs = published map version
+        self.map_queue = [collections.deque() for _ in range(ns)]   # jobs not started
         self.map_active = []
         self.map_finished = []
-        self.map_superseded = 0
+
+    # ---- dependencies ------------------------------------------------------
+    def version_needed(self, i):
+        """Map version frame i renders: the number of keyframes k <= i - map_lag
+        (their jobs come first); 0 without asynchronous mapping."""
+        c = self.cfg
+        if not c.async_mapping or c.map_iters <= 0:
+            return 0
+        v = i - c.map_lag
+        return v // c.keyframe_every + 1 if v >= 0 else 0
+
+    def _ready(self, f):
+        """Frame f may start: the session's earlier frames have started, the
+        frame it starts from has finished, and its map version is published."""
+        s = f.session
+        if f.index != self.next_admit[s]:
+            return False
+        src = f.index - self.cfg.pose_lag
+        if src >= 0 and src not in self.track_done[s]:
+            return False
+        return self.jobs_done[s] >= self.version_needed(f.index)
+
+    @property
+    def map_pending(self):
+        return sum(len(q) for q in self.map_queue)
 
     # ---- admission -------------------------------------------------------
     def _try_open(self, s):
-        """Make session s resident, evicting idle sessions (no frame admitted
-        or waiting) to host memory if the HBM budget requires it."""
+        """Make session s resident, evicting idle sessions (no frame or map job
+        admitted or waiting) to host memory if the HBM budget requires it."""
         if self.open[s]:
             return True
         need = self.ex.session_bytes(self.specs[s])
         if self.resident + need > self.cfg.hbm_budget:
-            waiting = {f.session for f in self.pending} | {f.session for f in self.active}
+            waiting = ({f.session for f in self.pending} | {f.session for f in self.active}
+                       | {j.session for j in self.map_active}
+                       | {v for v, q in enumerate(self.map_queue) if q})
             for v in range(len(self.specs)):
                 if self.resident + need <= self.cfg.hbm_budget:
                     break
@@ -220,19 +265,22 @@ class Engine:
         if key:
             self.last_key[s] = index
         maps = self.cfg.map_iters if key and not self.cfg.async_mapping else 0
-        self.pending.append(Frame(s, index, t, key, self.cfg.track_iters, maps, j))
+        src = index - self.cfg.pose_lag
+        self.pending.append(Frame(s, index, t, key, self.cfg.track_iters, maps, j,
+                                  pose_from=src if src >= 0 else -1,
+                                  version=self.version_needed(index)))
 
     def _admit(self, now):
-        if self.cfg.async_mapping and self.cfg.mode == "serial" and self.map_active:
+        serial = self.cfg.mode == "serial"
+        if serial and (self.active or self.map_active):
             return                            # one item at a time
-        cap = 1 if self.cfg.mode == "serial" else self.cfg.max_batch
+        cap = 1 if serial else self.cfg.max_batch
         ws = sum(self.ex.step_bytes(self.specs[f.session], f) for f in self.active)
-        busy = {f.session for f in self.active}
         keep = collections.deque()
         while self.pending and len(self.active) < cap:
             f = self.pending.popleft()
-            if f.session in busy and not self.cfg.overlap_frames:
-                keep.append(f)                # a session's frames run in order
+            if not self._ready(f):
+                keep.append(f)
                 continue
             need = self.ex.step_bytes(self.specs[f.session], f)
             if ws + need > self.cfg.ws_budget and self.active:
@@ -244,7 +292,7 @@ class Engine:
             f.started = now
             self.ex.start_frame(f, self.specs[f.session])
             self.active.append(f)
-            busy.add(f.session)
+            self.next_admit[f.session] += 1
             ws += need
         keep.extend(self.pending)
         self.pending = keep
@@ -253,23 +301,24 @@ class Engine:
 
     def _admit_maps(self, now):
         serial = self.cfg.mode == "serial"
-        if serial and (self.active or self.pending or self.map_active):
+        if serial and (self.active or self.map_active):
             return                            # one item at a time, tracking first
         cap = 1 if serial else min(self.cfg.max_batch, self.cfg.max_map_batch)
         ws = sum(self.ex.step_bytes(self.specs[j.session], j) for j in self.map_active)
         busy = {j.session for j in self.map_active}
-        for s in sorted(self.map_pending, key=lambda v: self.map_pending[v].created):
+        heads = [q[0] for q in self.map_queue if q]
+        for j in sorted(heads, key=lambda x: (x.created, x.session)):
             if len(self.map_active) >= cap:
                 break
+            s = j.session
             if s in busy:
                 continue
-            j = self.map_pending[s]
             need = self.ex.step_bytes(self.specs[s], j)
             if ws + need > self.cfg.ws_budget and self.map_active:
                 continue
             if not self._try_open(s):
                 continue
-            del self.map_pending[s]
+            self.map_queue[s].popleft()
             j.started = now
             self.ex.start_map(j, self.specs[s])
             self.map_active.append(j)
@@ -277,6 +326,14 @@ class Engine:
             ws += need
 
     # ---- one engine step ---------------------------------------------------
+    def _finish_frame(self, f, now):
+        self.ex.finish_frame(f, self.specs[f.session])
+        self.finished.append(f)
+        self.track_done[f.session].add(f.index)
+        if self.cfg.async_mapping and f.keyframe and self.cfg.map_iters > 0:
+            self.map_queue[f.session].append(
+                MapJob(f.session, f.index, f.arrival, now, self.cfg.map_iters, f))
+
     def step(self, now):
         if self.cfg.async_mapping:
             return self._step_async(now)
@@ -304,8 +361,7 @@ class Engine:
         still = []
         for f in self.active:
             if f.remaining == 0:
-                self.ex.finish_frame(f, self.specs[f.session])
-                self.finished.append(f)
+                self._finish_frame(f, now)
             else:
                 still.append(f)
         self.active = still
@@ -336,20 +392,16 @@ class Engine:
         for f in self.active:
             if f.remaining > 0:
                 still.append(f)
-                continue
-            self.ex.finish_frame(f, self.specs[f.session])
-            self.finished.append(f)
-            if f.keyframe and self.cfg.map_iters > 0:
-                if f.session in self.map_pending:
-                    self.map_superseded += 1
-                self.map_pending[f.session] = MapJob(f.session, f.index, f.arrival, now,
-                                                     self.cfg.map_iters, f)
+            else:
+                self._finish_frame(f, now)
         self.active = still
         still = []
         for j in self.map_active:
             if j.remaining > 0:
                 still.append(j)
             else:
+                self.ex.finish_map(j, self.specs[j.session])
+                self.jobs_done[j.session] += 1
                 self.map_finished.append(j)
         self.map_active = still
         return True
@@ -375,10 +427,13 @@ class Engine:
             if not self.step(now):
                 if i >= len(trace) and not self.pending and not self.map_pending:
                     break
-                if i < len(trace):
-                    wait = trace[i][0] - (self.clock() - t0)
-                    if wait > 0:
-                        self.ex.idle(wait)
+                if i >= len(trace):
+                    # nothing runs, nothing more arrives, yet work is left
+                    raise RuntimeError(f"serving engine stalled: {len(self.pending)} frames, "
+                                       f"{self.map_pending} map jobs waiting")
+                wait = trace[i][0] - (self.clock() - t0)
+                if wait > 0:
+                    self.ex.idle(wait)
         self.ex.sync()
         for f in self.finished + self.map_finished:
             f.done_time = self.ex.event_time(f.done_event)
@@ -400,6 +455,7 @@ class Engine:
 
         return {
             "frames": len(self.finished),
+            "frames_measured": len(every),
             "p50_ms": pct(every, 50), "p99_ms": pct(every, 99),
             "per_class": {k: {"frames": len(v), "p50_ms": pct(v, 50), "p99_ms": pct(v, 99)}
                           for k, v in sorted(lat.items())},
@@ -409,7 +465,7 @@ class Engine:
             "span_s": span,
             "max_resident_bytes": self.max_resident,
             "async_mapping": self.cfg.async_mapping,
-            "map_jobs": len(self.map_finished), "map_superseded": self.map_superseded,
+            "map_jobs": len(self.map_finished),
             "map_p50_ms": pct(maps, 50), "map_p99_ms": pct(maps, 99),
         }
 
@@ -467,6 +523,9 @@ class FakeExecutor:
     def start_map(self, job, spec):
         pass
 
+    def finish_map(self, job, spec):
+        pass
+
     def run_iteration(self, phase, frames, specs):
         cost = self.launch_s
         for f, sp in zip(frames, specs):
@@ -490,11 +549,20 @@ class FakeExecutor:
 
 
 class GpuExecutor:
-    """Runs sessions on the HIP library with batched launches."""
+    """Runs sessions on the HIP library with batched launches.
+
+    A session's map exists in versions: version 0 at open, and version v + 1
+    written by its v + 1-th keyframe map job (asynchronous mapping) into
+    tensors of its own, so frames that render version v meanwhile see it
+    unchanged.  Without asynchronous mapping the frames' own mapping
+    iterations update the single version in place (a session's frames then
+    run one after another)."""
+
+    KEEP_VERSIONS = 3            # versions a later frame may still render
 
     def __init__(self, device=0, lr_pose=(1e-3, 3e-3), track_noise_seed=0, n_targets=4,
                  capacity_factor=2.0, prune=False, prune_ratio=0.1, prune_cap=0.5,
-                 prune_lam=0.8):
+                 prune_lam=0.8, record_poses=False):
         import torch
 
         from . import rtgs
@@ -510,13 +578,16 @@ class GpuExecutor:
         self.base_wall = None
         self.overflows = 0
         # adaptive pruning (Sec. 4.1) per tracked frame: the frame's first
-        # iteration scores the map and masks up to prune_ratio of the visible
-        # Gaussians, its other iterations render without them, and the frame's
-        # end removes them; never more than prune_cap of the initial map
+        # iteration scores the map (Eq. 7) and masks up to prune_ratio of its
+        # visible Gaussians for the frame's other iterations; a keyframe's
+        # map job removes the Gaussians its keyframe masked, never more than
+        # prune_cap of the initial map in all
         self.prune = prune
         self.prune_ratio = prune_ratio
         self.prune_cap = prune_cap
         self.prune_lam = prune_lam
+        self.record_poses = record_poses
+        self.frame_poses = {}    # (session, frame) -> end pose, with record_poses
 
     # ---- footprint -----------------------------------------------------------
     def session_bytes(self, spec):
@@ -529,6 +600,9 @@ class GpuExecutor:
 
     def step_bytes(self, spec, frame):
         return self.rtgs.rtgs_workspace_size(spec.n, spec.width, spec.height, self._cap(spec))
+
+    def _eye(self):
+        return self.torch.eye(3, 4, dtype=self.torch.float32, device=self.dev).contiguous()
 
     # ---- sessions ------------------------------------------------------------
     def open_session(self, s, spec):
@@ -552,7 +626,7 @@ class GpuExecutor:
             xi = torch.tensor(synth.pose_offset(spec.seed * 31 + k, 0.01, 0.5),
                               dtype=torch.float64, device=self.dev)
             from .pose import apply_left
-            vm = apply_left(xi, torch.eye(3, 4, dtype=torch.float32, device=self.dev))
+            vm = apply_left(xi, self._eye())
             st = r.forward(tuple(params), vm.contiguous(), rc)
             g = torch.Generator(device=self.dev).manual_seed(spec.seed + k)
             targets.append((st.color + 0.01 * torch.randn(st.color.shape, generator=g,
@@ -564,18 +638,11 @@ class GpuExecutor:
         opt = MapAdam(maps, eps=1e-15)
         self.sessions[s] = dict(
             spec=spec, cam=rc, params=maps, opt=opt, targets=targets,
-            viewmat=torch.eye(3, 4, dtype=torch.float32, device=self.dev).contiguous(),
-            m=torch.zeros(6, device=self.dev), v=torch.zeros(6, device=self.dev), t=0,
-            last_T=None,
-            out=self._outs(spec), out_map=self._outs(spec),
-            gpose=torch.zeros(6, device=self.dev),
-            n0=spec.n, removed=0, mask=None, inflight=0, scoring=False,
-            visible=torch.empty(spec.n, dtype=torch.uint8, device=self.dev),
-            mask_count=torch.zeros(1, dtype=torch.int32, device=self.dev),
-            h_count=torch.zeros(1, dtype=torch.int32).pin_memory(),
-            ev_count=torch.cuda.Event(),
-            pmask=torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev),
-            pcount=torch.zeros(1, dtype=torch.int32, device=self.dev))
+            versions={0: maps}, version=0,
+            viewmat=self._eye(),           # end pose of the latest finished frame
+            poses={}, final_T={},          # frame index -> end pose / last final T
+            out_map=self._outs(spec),
+            n0=spec.n, removed=0, inflight=0)
         torch.cuda.synchronize(self.dev)
 
     def _outs(self, spec):
@@ -588,68 +655,52 @@ class GpuExecutor:
                                          device=self.dev))
 
     def close_session(self, s):
-        """Evict: the session's tensors and optimiser state move to host memory."""
+        """Evict an idle session: its latest map version, Adam moments, poses
+        and targets move to host memory (older versions and transmittance
+        images are dropped)."""
         S = self.sessions.get(s)
         if S is None or S.get("offloaded"):
             return
         S["params"] = [p.cpu() for p in S["params"]]
+        S["versions"] = {S["version"]: S["params"]}
         S["opt"].to("cpu").rebind(S["params"])
-        if S["mask"] is not None:
-            self._remove_masked(S)
-        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount", "visible", "mask_count"):
-            S[k] = S[k].cpu()
+        S["viewmat"] = S["viewmat"].cpu()
+        S["poses"] = {k: v.cpu() for k, v in S["poses"].items()}
+        S["final_T"] = {}
         S["targets"] = [(c.cpu(), d.cpu()) for c, d in S["targets"]]
-        S["out"] = {k: v.cpu() for k, v in S["out"].items()}
         S["out_map"] = {k: v.cpu() for k, v in S["out_map"].items()}
-        S["last_T"] = None
         S["offloaded"] = True
 
     def _restore(self, s):
-        torch = self.torch
         S = self.sessions[s]
         S["params"] = [p.to(self.dev) for p in S["params"]]
+        S["versions"] = {S["version"]: S["params"]}
         S["opt"].to(self.dev).rebind(S["params"])
-        for k in ("viewmat", "m", "v", "gpose", "pmask", "pcount", "visible", "mask_count"):
-            S[k] = S[k].to(self.dev)
+        S["viewmat"] = S["viewmat"].to(self.dev)
+        S["poses"] = {k: v.to(self.dev) for k, v in S["poses"].items()}
         S["targets"] = [(c.to(self.dev), d.to(self.dev)) for c, d in S["targets"]]
-        S["out"] = {k: v.to(self.dev) for k, v in S["out"].items()}
         S["out_map"] = {k: v.to(self.dev) for k, v in S["out_map"].items()}
         S["offloaded"] = False
 
     # ---- frames ----------------------------------------------------------------
-    def _remove_masked(self, S):
-        """Permanent removal of the masked Gaussians (map, Adam moments)."""
-        torch, rtgs = self.torch, self.rtgs
-        S["ev_count"].synchronize()             # recorded a frame ago
-        n = S["params"][0].shape[0]
-        k = n - int(S["h_count"].item())
-        mask, S["mask"] = S["mask"], None
-        if k >= n:
-            return
-        opt = S["opt"]
-        srcs = list(S["params"]) + list(opt.exp_avg) + list(opt.exp_avg_sq)
-        outs = [torch.empty((k,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device)
-                for t in srcs]
-        rtgs.compact_by_mask(mask, list(zip(srcs, outs)), S["mask_count"])
-        np_ = len(S["params"])
-        S["params"] = outs[:np_]
-        opt.rebind(S["params"])
-        opt.exp_avg = outs[np_:2 * np_]
-        opt.exp_avg_sq = outs[2 * np_:]
-        S["visible"] = torch.empty(k, dtype=torch.uint8, device=self.dev)
-        S["removed"] += n - k
-
     def start_frame(self, f, spec):
-        """A frame tracks its own pose from the session's latest estimate, with
-        its own Adam state and output buffers (frames of one session may
-        overlap).  Pruning: the first frame of a mask window scores the map."""
+        """A frame tracks its own pose, from the end pose of frame f.pose_from
+        (the identity for a session's first frames), with its own Adam state
+        and output buffers, on map version f.version.  A downsampled frame
+        takes its pixel mask from frame f.pose_from's final transmittance."""
         torch = self.torch
         S = self.sessions[f.session]
+        if f.version not in S["versions"]:
+            raise RuntimeError(f"session {f.session}: map version {f.version} is gone "
+                               f"(have {sorted(S['versions'])})")
         S["inflight"] += 1
-        f.first = self.prune and S["mask"] is None and not S["scoring"]
-        S["scoring"] = S["scoring"] or f.first
+        f.params = S["versions"][f.version]
+        n = f.params[0].shape[0]
+        f.first = self.prune
+        f.gmask = None
+        f.visible = torch.empty(n, dtype=torch.uint8, device=self.dev)
         f.target = S["targets"][f.index % self.n_targets]
-        f.viewmat = S["viewmat"].clone()
+        f.viewmat = (S["poses"][f.pose_from].clone() if f.pose_from >= 0 else self._eye())
         f.m = torch.zeros(6, device=self.dev)
         f.v = torch.zeros(6, device=self.dev)
         f.t = 0
@@ -657,27 +708,72 @@ class GpuExecutor:
         f.out = self._outs(spec)
         f.mask = None
         f.pcount = None
-        if f.log2_ratio > 0 and S["last_T"] is not None:
+        if f.log2_ratio > 0 and f.pose_from in S["final_T"]:
             f.mask = torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev)
             f.pcount = torch.zeros(1, dtype=torch.int32, device=self.dev)
-            self.rtgs.downsample_mask(S["last_T"], f.log2_ratio, f.mask, f.pcount)
+            self.rtgs.downsample_mask(S["final_T"][f.pose_from], f.log2_ratio, f.mask,
+                                      f.pcount)
 
     def finish_frame(self, f, spec):
         S = self.sessions[f.session]
-        S["viewmat"] = f.viewmat                    # the session's latest pose
-        S["last_T"] = f.out["final_T"]
+        S["viewmat"] = f.viewmat
+        S["poses"][f.index] = f.viewmat
+        S["final_T"][f.index] = f.out["final_T"]
+        for d in (S["poses"], S["final_T"]):           # what no later frame reads
+            for k in [k for k in d if k < f.index - 4]:
+                del d[k]
         f.pose_end = f.viewmat                      # a keyframe's tracked pose
+        if self.record_poses:
+            self.frame_poses[(f.session, f.index)] = f.viewmat
         S["inflight"] -= 1
-        if S["mask"] is not None and S["inflight"] == 0:
-            self._remove_masked(S)
+        if not f.keyframe:
+            f.gmask = None                          # only a keyframe's job reads it
 
     def start_map(self, job, spec):
-        """A keyframe's map job renders at the keyframe's tracked pose, into
-        buffers of its own (the session's next frames track meanwhile)."""
+        """A keyframe's map job: version v + 1 starts as a copy of the latest
+        version v (the keyframe rendered v too), without the Gaussians the
+        keyframe masked when pruning, and is trained at the keyframe's tracked
+        pose; frames on version v keep rendering it meanwhile."""
+        torch, rtgs = self.torch, self.rtgs
         S = self.sessions[job.session]
-        job.target = job.frame.target
+        base = S["versions"][S["version"]]
+        f = job.frame
+        opt = S["opt"]
+        n = base[0].shape[0]
+        k = n
+        if self.prune and f.gmask is not None:
+            if f.gmask.numel() != n:
+                raise RuntimeError("keyframe mask and map version disagree")
+            f.ev_count.synchronize()                # recorded frames ago
+            k = n - int(f.h_count.item())
+        if k < n:
+            srcs = list(base) + list(opt.exp_avg) + list(opt.exp_avg_sq)
+            outs = [torch.empty((k,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device)
+                    for t in srcs]
+            cnt = torch.empty(1, dtype=torch.int32, device=self.dev)
+            rtgs.compact_by_mask(f.gmask, list(zip(srcs, outs)), cnt)
+            npar = len(base)
+            new = outs[:npar]
+            opt.exp_avg = outs[npar:2 * npar]
+            opt.exp_avg_sq = outs[2 * npar:]
+            S["removed"] += n - k
+        else:
+            new = [p.clone() for p in base]
+        opt.rebind(new)
+        f.gmask = None
+        job.params = new
+        job.target = f.target
         job.mask = None
-        job.viewmat = job.frame.pose_end
+        job.viewmat = f.pose_end
+
+    def finish_map(self, job, spec):
+        """Publish the job's map as the session's next version."""
+        S = self.sessions[job.session]
+        S["version"] += 1
+        S["versions"][S["version"]] = job.params
+        S["params"] = job.params
+        for v in [v for v in S["versions"] if v <= S["version"] - self.KEEP_VERSIONS]:
+            del S["versions"][v]
 
     # ---- one iteration for a group of frames -----------------------------------
     def run_iteration(self, phase, frames, specs):
@@ -687,16 +783,17 @@ class GpuExecutor:
         for f in frames:
             S = self.sessions[f.session]
             job = isinstance(f, MapJob)
-            o = S["out_map"] if job else getattr(f, "out", S["out"])
-            items.append(dict(scene=tuple(p.detach() for p in S["params"]),
-                              viewmat=getattr(f, "viewmat", S["viewmat"]), cam=S["cam"],
-                              pixel_mask=f.mask, gauss_mask=S["mask"],
-                              visible=S["visible"] if phase == "track" else None,
+            o = S["out_map"] if job else f.out
+            items.append(dict(scene=tuple(p.detach() for p in f.params),
+                              viewmat=f.viewmat, cam=S["cam"],
+                              pixel_mask=f.mask,
+                              gauss_mask=None if job or phase == "map" else f.gmask,
+                              visible=None if job or phase == "map" else f.visible,
                               sample_log2=f.log2_ratio if f.mask is not None else 0,
                               color=o["color"], depth=o["depth"], alpha=o["alpha"],
                               final_T=o["final_T"], last_idx=o["last_idx"]))
             cap += self._cap(S["spec"])
-        ns = [S_["spec"].n for S_ in (self.sessions[f.session] for f in frames)]
+        ns = [f.params[0].shape[0] for f in frames]
         ws_ = [self.sessions[f.session]["spec"].width for f in frames]
         hs_ = [self.sessions[f.session]["spec"].height for f in frames]
         ws = torch.empty(rtgs.rtgs_workspace_size_batched(ns, ws_, hs_, cap),
@@ -706,7 +803,6 @@ class GpuExecutor:
         # launch for the group
         losses = []
         for f, it in zip(frames, items):
-            S = self.sessions[f.session]
             gc = torch.empty_like(it["color"])
             gd = torch.empty_like(it["depth"])
             losses.append((it["color"], it["depth"], f.target[0], f.target[1], gc, gd, f.mask,
@@ -718,47 +814,51 @@ class GpuExecutor:
             flags = rtgs.RTGS_GRAD_POSE
             scored = []
             for f, it in zip(frames, items):
-                S = self.sessions[f.session]
                 it["g_pose6"] = f.gpose
-                if getattr(f, "first", False):
-                    n = S["params"][0].shape[0]
+                if f.first:
+                    n = f.params[0].shape[0]
                     it["g_means"] = torch.empty(n, 3, device=self.dev)
                     it["g_cov3d"] = torch.empty(n, 6, device=self.dev)
                     scored.append((f, it))
                     flags |= rtgs.RTGS_GRAD_SCORE
             rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=flags)
             for f, it in scored:
-                self._mask_lowest(self.sessions[f.session], it)
+                self._mask_lowest(self.sessions[f.session], f, it)
                 f.first = False
             self._pose_step(frames)
         else:
             grads = []
             for f, it in zip(frames, items):
-                S = self.sessions[f.session]
-                g = [torch.empty_like(p) for p in S["params"]]
+                g = [torch.empty_like(p) for p in f.params]
                 it.update(g_means=g[0], g_log_scales=g[1], g_quats=g[2], g_opacity_logits=g[3],
                           g_colors=g[4])
                 grads.append(g)
             rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=rtgs.RTGS_GRAD_MAP)
             # one update launch for the maps of every session of the group
             from .optim import step_many
-            step_many(self.handle, [(self.sessions[f.session]["opt"], g)
-                                    for f, g in zip(frames, grads)])
+            step_many(self.handle, [(getattr(f, "opt", None) or self.sessions[f.session]["opt"],
+                                     g) for f, g in zip(frames, grads)])
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         return ev
 
-    def _mask_lowest(self, S, it):
-        n = S["params"][0].shape[0]
-        budget = max(0.0, self.prune_cap * S["n0"] - S["removed"])
+    def _mask_lowest(self, S, f, it):
+        """The frame's mask (Sec. 4.1, Eq. 7): up to prune_ratio of its
+        visible Gaussians with the lowest importance, within what the 50% cap
+        still allows for the version it renders."""
+        torch = self.torch
+        n = f.params[0].shape[0]
+        budget = max(0.0, self.prune_cap * S["n0"] - (S["n0"] - n))
         ratio = min(self.prune_ratio, budget / max(n, 1), 0.5)
-        mask = self.torch.zeros(n, dtype=self.torch.uint8, device=self.dev)
-        self.rtgs.prune_by_grad(self.handle, it["g_means"], it["g_cov3d"], S["visible"], None,
-                                self.prune_lam, ratio, mask, S["mask_count"])
-        S["h_count"].copy_(S["mask_count"], non_blocking=True)
-        S["ev_count"].record()
-        S["mask"] = mask
-        S["scoring"] = False
+        mask = torch.zeros(n, dtype=torch.uint8, device=self.dev)
+        count = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.rtgs.prune_by_grad(self.handle, it["g_means"], it["g_cov3d"], f.visible, None,
+                                self.prune_lam, ratio, mask, count)
+        f.h_count = torch.zeros(1, dtype=torch.int32).pin_memory()
+        f.h_count.copy_(count, non_blocking=True)
+        f.ev_count = torch.cuda.Event()
+        f.ev_count.record()
+        f.gmask = mask
 
     def _pose_step(self, frames, b1=0.9, b2=0.999, eps=1e-8):
         """Adam on xi = (rho, phi) for every frame of the group, then the
@@ -774,20 +874,21 @@ class GpuExecutor:
         return time.perf_counter()
 
     def warmup(self, specs, iters=2):
-        """One untimed tracking and mapping iteration per open session (first
-        launches, allocator growth)."""
-        torch = self.torch
+        """Untimed tracking and mapping iterations per open session (first
+        launches, allocator growth) on throwaway copies of the map: no session
+        state changes."""
+        from .optim import MapAdam
         for s in list(self.sessions):
-            spec = self.sessions[s]["spec"]
+            S = self.sessions[s]
+            spec = S["spec"]
             for phase in ("track", "map"):
                 f = Frame(s, 0, 0.0, True, 1, 1)
                 self.start_frame(f, spec)
+                f.params = [p.clone() for p in f.params]
+                f.opt = MapAdam(f.params, eps=1e-15)
                 for _ in range(iters):
                     self.run_iteration(phase, [f], [spec])
-            S = self.sessions[s]                     # warm-up frames are not kept
-            S["mask"], S["scoring"], S["inflight"] = None, False, 0
-            S["viewmat"] = torch.eye(3, 4, dtype=torch.float32, device=self.dev).contiguous()
-            S["last_T"] = None
+                S["inflight"] -= 1
         self.sync()
 
     def start_clock(self):

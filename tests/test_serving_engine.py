@@ -88,23 +88,46 @@ def test_downsampling_schedule_follows_keyframes():
 
 def test_async_mapping_runs_keyframe_jobs_beside_tracking():
     """Keyframe mapping as a background job: every frame finishes when its
-    tracking ends; each keyframe's job either runs (20 iterations) or is
-    replaced by the session's next keyframe before it starts; a session has
-    at most one job running; frame latency drops against mapping in line."""
+    tracking ends; every keyframe's job runs (20 iterations), a session's
+    jobs one at a time in keyframe order; frame latency drops against
+    mapping in line."""
     cfg = ServeConfig(async_mapping=True)
     eng, ex, rep = _run(cfg)
     trace = serving.poisson_trace(16, 30.0, 3.0, 3)
     assert len(eng.finished) == len(trace)
     keys = sum(1 for f in eng.finished if f.keyframe)
-    assert rep["map_jobs"] + rep["map_superseded"] == keys
-    assert rep["map_jobs"] > 0
+    assert rep["map_jobs"] == keys > 0
     assert eng.iters == 10 * len(eng.finished) + 20 * rep["map_jobs"]
     for phase, sessions in ex.log:
         assert len(sessions) == len(set(sessions))
+    for s in range(16):
+        idx = [j.index for j in sorted(eng.map_finished, key=lambda j: j.done_time)
+               if j.session == s]
+        assert idx == sorted(idx)
     for j in eng.map_finished:
         assert j.done_time >= j.arrival
     _, _, sync = _run(ServeConfig())
     assert rep["p99_ms"] < sync["p99_ms"]
+
+
+def test_frames_wait_for_their_map_version_and_start_pose():
+    """Frame i starts after frame i - pose_lag has finished and after the
+    jobs of the keyframes k <= i - map_lag (its map version); the version is
+    a function of the index alone."""
+    for overlap in (False, True):
+        cfg = ServeConfig(async_mapping=True, overlap_frames=overlap)
+        eng, ex, rep = _run(cfg, duration=2.0)
+        fin = {(f.session, f.index): f for f in eng.finished}
+        jobs = {(j.session, j.index): j for j in eng.map_finished}
+        lag = cfg.pose_lag
+        assert lag == (2 if overlap else 1)
+        for (s, i), f in fin.items():
+            assert f.version == eng.version_needed(i)
+            assert f.version == (max(0, (i - 8) // 8 + 1) if i >= 8 else 0)
+            if i - lag >= 0:
+                assert fin[(s, i - lag)].done_time <= f.started + 1e-12
+            for k in range(0, i - cfg.map_lag + 1, cfg.keyframe_every):
+                assert jobs[(s, k)].done_time <= f.started + 1e-12
 
 
 def test_async_mapping_serial_runs_one_item_at_a_time():
