@@ -294,42 +294,107 @@ def render_bwd(handle, means, log_scales, quats, opacity_logits, colors, viewmat
                             _p(g_viewmat), _p(g_cov3d), _stream(stream)))
 
 
+def session_struct(it):
+    """One CSession from a dict with the keys of CSession (tensors or None)
+    plus 'scene' (means, log_scales, quats, opacity_logits, colors),
+    'viewmat', 'cam' (Cam), optional 'gauss_mask' and 'sample_log2'.  The
+    struct holds raw device pointers: the tensors must outlive its use."""
+    s = CSession()
+    s.g = _gauss(*it["scene"], it.get("gauss_mask"))
+    s.cam = _cam(it["cam"], it["viewmat"])
+    s.sample_log2 = int(it.get("sample_log2", 0))
+    for name in ("pixel_mask", "color", "depth", "alpha", "final_T", "last_idx", "visible",
+                 "stats",
+                 "dL_dcolor", "dL_ddepth", "dL_dalpha", "g_means", "g_log_scales", "g_quats",
+                 "g_opacity_logits", "g_colors", "g_pose6", "g_viewmat", "g_cov3d"):
+        setattr(s, name, _p(it.get(name)))
+    return s
+
+
 def make_sessions(items):
-    """items: list of dicts with keys of CSession (tensors or None) plus
-    'scene' (means, log_scales, quats, opacity_logits, colors), 'viewmat',
-    'cam' (Cam), optional 'gauss_mask'."""
+    """items: list of dicts as `session_struct` takes; returns the ctypes
+    array and the tensors it points to (keep them alive)."""
     arr = (CSession * len(items))()
     keep = []
     for i, it in enumerate(items):
-        sc = it["scene"]
-        s = arr[i]
-        s.g = _gauss(*sc, it.get("gauss_mask"))
-        s.cam = _cam(it["cam"], it["viewmat"])
-        s.sample_log2 = int(it.get("sample_log2", 0))
-        for name in ("pixel_mask", "color", "depth", "alpha", "final_T", "last_idx", "visible",
-                     "stats",
-                     "dL_dcolor", "dL_ddepth", "dL_dalpha", "g_means", "g_log_scales", "g_quats",
-                     "g_opacity_logits", "g_colors", "g_pose6", "g_viewmat", "g_cov3d"):
-            t = it.get(name)
-            setattr(s, name, _p(t))
-            keep.append(t)
+        arr[i] = session_struct(it)
+        keep.append(it)
     return arr, keep
+
+
+def stream_ptr(stream=None):
+    """The hipStream_t of a torch stream (default: the current one), to pass
+    to the *_c calls below without a lookup per call."""
+    return _stream(stream)
 
 
 def render_fwd_batched(handle, sessions, ws, pair_capacity, flags=RTGS_FWD_SAVE_STATE,
                        stream=None):
     arr, _keep = make_sessions(sessions)
-    _check(lib().render_fwd_batched(handle.ptr, arr, len(sessions), _p(ws),
-                                    ws.numel() * ws.element_size(), int(pair_capacity),
-                                    int(flags), _stream(stream)))
+    render_fwd_batched_c(handle, arr, len(sessions), ws, pair_capacity, flags, _stream(stream))
 
 
 def render_bwd_batched(handle, sessions, ws, pair_capacity,
                        grad_flags=RTGS_GRAD_POSE | RTGS_GRAD_MAP, stream=None):
     arr, _keep = make_sessions(sessions)
-    _check(lib().render_bwd_batched(handle.ptr, arr, len(sessions), _p(ws),
-                                    ws.numel() * ws.element_size(), int(pair_capacity),
-                                    int(grad_flags), _stream(stream)))
+    render_bwd_batched_c(handle, arr, len(sessions), ws, pair_capacity, grad_flags,
+                         _stream(stream))
+
+
+# Calls on prebuilt ctypes arrays (session_struct, CLossItem, CPoseItem,
+# CAdamGroup) and a stream pointer (stream_ptr): for loops that issue the same
+# frames' calls many times, so that marshalling happens once per frame.
+def render_fwd_batched_c(handle, arr, n, ws, pair_capacity, flags, stream):
+    _check(lib().render_fwd_batched(handle.ptr, arr, n, _p(ws), ws.numel() * ws.element_size(),
+                                    int(pair_capacity), int(flags), stream))
+
+
+def render_bwd_batched_c(handle, arr, n, ws, pair_capacity, grad_flags, stream):
+    _check(lib().render_bwd_batched(handle.ptr, arr, n, _p(ws), ws.numel() * ws.element_size(),
+                                    int(pair_capacity), int(grad_flags), stream))
+
+
+def loss_item(c, d, tc, td, gc, gd, mask=None, cnt=None):
+    """A CLossItem for loss_l1_grad_batched_c (validated once)."""
+    _, h, w = c.shape
+    for t, shp in ((c, (3, h, w)), (tc, (3, h, w)), (gc, (3, h, w)), (d, (h, w)),
+                   (td, (h, w)), (gd, (h, w))):
+        _f32(t, shp, "loss image")
+        _p(t)
+    if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != (h, w)):
+        raise ValueError("pixel_mask must be uint8 [H, W]")
+    if mask is not None and cnt is None:
+        raise ValueError("a pixel mask needs its device active-pixel count")
+    return CLossItem(*(t.data_ptr() if t is not None else None
+                       for t in (c, d, tc, td, mask, cnt, gc, gd)), w, h)
+
+
+def loss_l1_grad_batched_c(arr, n, w_color, w_depth, stream):
+    _check(lib().loss_l1_grad_batched(arr, n, float(w_color), float(w_depth), stream))
+
+
+def pose_item(vm, g, m, v, lr_rho, lr_phi, step=1):
+    """A CPoseItem for pose_update_c (validated once; set .step per call)."""
+    _f32(vm, (3, 4), "viewmat")
+    for t in (g, m, v):
+        _f32(t, (6,), "pose vector")
+    return CPoseItem(_p(vm), _p(g), _p(m), _p(v), float(lr_rho), float(lr_phi), int(step))
+
+
+def pose_update_c(arr, n, beta1, beta2, eps, stream):
+    _check(lib().pose_update(arr, n, float(beta1), float(beta2), float(eps), stream))
+
+
+def adam_group(p, g, m, v, lr, step=1):
+    """A CAdamGroup for adam_step_c (validated once; set .step per call)."""
+    for t in (p, g, m, v):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != p.numel():
+            raise ValueError("adam_step: contiguous float32 tensors of one size expected")
+    return CAdamGroup(_p(p), _p(g), _p(m), _p(v), p.numel(), float(lr), int(step))
+
+
+def adam_step_c(handle, arr, n, beta1, beta2, eps, stream):
+    _check(lib().adam_step(handle.ptr, arr, n, float(beta1), float(beta2), float(eps), stream))
 
 
 def prune_by_grad(handle, g_means, g_cov3d, visible, mask_in, lam, max_ratio, mask_out,
@@ -347,18 +412,8 @@ def loss_l1_grad_batched(items, w_color=1.0, w_depth=0.5, stream=None):
     items = list(items)
     arr = (CLossItem * max(len(items), 1))()
     for k, (c, d, tc, td, gc, gd, mask, cnt) in enumerate(items):
-        _, h, w = c.shape
-        for t, shp in ((c, (3, h, w)), (tc, (3, h, w)), (gc, (3, h, w)), (d, (h, w)),
-                       (td, (h, w)), (gd, (h, w))):
-            _f32(t, shp, "loss image")
-        if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != (h, w)):
-            raise ValueError("pixel_mask must be uint8 [H, W]")
-        if mask is not None and cnt is None:
-            raise ValueError("a pixel mask needs its device active-pixel count")
-        arr[k] = CLossItem(*(t.data_ptr() if t is not None else None
-                             for t in (c, d, tc, td, mask, cnt, gc, gd)), w, h)
-    _check(lib().loss_l1_grad_batched(arr, len(items), float(w_color), float(w_depth),
-                                      _stream(stream)))
+        arr[k] = loss_item(c, d, tc, td, gc, gd, mask, cnt)
+    loss_l1_grad_batched_c(arr, len(items), w_color, w_depth, _stream(stream))
 
 
 RTGS_COMPACT_MAX_ITEMS = 24
@@ -432,12 +487,8 @@ def pose_update(items, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     items = list(items)
     arr = (CPoseItem * max(len(items), 1))()
     for k, (vm, g, m, v, lr_rho, lr_phi, step) in enumerate(items):
-        _f32(vm, (3, 4), "viewmat")
-        for t in (g, m, v):
-            _f32(t, (6,), "pose vector")
-        arr[k] = CPoseItem(_p(vm), _p(g), _p(m), _p(v), float(lr_rho), float(lr_phi), int(step))
-    _check(lib().pose_update(arr, len(items), float(beta1), float(beta2), float(eps),
-                             _stream(stream)))
+        arr[k] = pose_item(vm, g, m, v, lr_rho, lr_phi, step)
+    pose_update_c(arr, len(items), beta1, beta2, eps, _stream(stream))
 
 
 def loss_l1_grad(color, depth, target_color, target_depth, dL_dcolor, dL_ddepth,
@@ -461,12 +512,8 @@ def adam_step(handle, groups, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     groups = list(groups)
     arr = (CAdamGroup * max(len(groups), 1))()
     for k, (p, g, m, v, lr, step) in enumerate(groups):
-        for t in (p, g, m, v):
-            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != p.numel():
-                raise ValueError("adam_step: contiguous float32 tensors of one size expected")
-        arr[k] = CAdamGroup(_p(p), _p(g), _p(m), _p(v), p.numel(), float(lr), int(step))
-    _check(lib().adam_step(handle.ptr, arr, len(groups), float(beta1), float(beta2), float(eps),
-                           _stream(stream)))
+        arr[k] = adam_group(p, g, m, v, lr, step)
+    adam_step_c(handle, arr, len(groups), beta1, beta2, eps, _stream(stream))
 
 
 def downsample_mask(final_T, log2_ratio, mask_out, n_active=None, stream=None):

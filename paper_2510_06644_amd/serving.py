@@ -293,6 +293,9 @@ class Engine:
             self.ex.start_frame(f, self.specs[f.session])
             self.active.append(f)
             self.next_admit[f.session] += 1
+            release = getattr(self.ex, "release_versions", None)
+            if release:                       # versions below this one are not rendered again
+                release(f.session, self.version_needed(self.next_admit[f.session]))
             ws += need
         keep.extend(self.pending)
         self.pending = keep
@@ -558,8 +561,6 @@ class GpuExecutor:
     iterations update the single version in place (a session's frames then
     run one after another)."""
 
-    KEEP_VERSIONS = 3            # versions a later frame may still render
-
     def __init__(self, device=0, lr_pose=(1e-3, 3e-3), track_noise_seed=0, n_targets=4,
                  capacity_factor=2.0, prune=False, prune_ratio=0.1, prune_cap=0.5,
                  prune_lam=0.8, record_poses=False):
@@ -588,6 +589,9 @@ class GpuExecutor:
         self.prune_lam = prune_lam
         self.record_poses = record_poses
         self.frame_poses = {}    # (session, frame) -> end pose, with record_poses
+        # every launch goes to the stream current at construction
+        self.stream_obj = torch.cuda.current_stream(self.dev)
+        self.stream = rtgs.stream_ptr(self.stream_obj)
 
     # ---- footprint -----------------------------------------------------------
     def session_bytes(self, spec):
@@ -683,6 +687,38 @@ class GpuExecutor:
         S["offloaded"] = False
 
     # ---- frames ----------------------------------------------------------------
+    def _bind(self, x, S, spec, params, phase):
+        """The ctypes records of a frame or map job, built once: its session
+        record (map version, pose, masks, outputs, upstream and output
+        gradients), loss record, and pose or Adam records.  Each iteration
+        then only copies them into the call's arrays."""
+        torch, rtgs = self.torch, self.rtgs
+        n = params[0].shape[0]
+        o = x.out
+        x.gc = torch.empty_like(o["color"])
+        x.gd = torch.empty_like(o["depth"])
+        it = dict(scene=tuple(p.detach() for p in params), viewmat=x.viewmat, cam=S["cam"],
+                  pixel_mask=x.mask, sample_log2=x.log2_ratio if x.mask is not None else 0,
+                  color=o["color"], depth=o["depth"], alpha=o["alpha"], final_T=o["final_T"],
+                  last_idx=o["last_idx"], visible=x.visible, dL_dcolor=x.gc, dL_ddepth=x.gd)
+        if phase == "track":
+            it["g_pose6"] = x.gpose
+            if x.first:                             # scores the map on its first iteration
+                x.g_means = torch.empty(n, 3, device=self.dev)
+                x.g_cov3d = torch.empty(n, 6, device=self.dev)
+                it.update(g_means=x.g_means, g_cov3d=x.g_cov3d)
+        else:
+            x.grads = [torch.empty_like(p) for p in params]
+            x.g_cov3d = torch.empty(n, 6, device=self.dev)   # read when some job scores
+            it.update(g_means=x.grads[0], g_log_scales=x.grads[1], g_quats=x.grads[2],
+                      g_opacity_logits=x.grads[3], g_colors=x.grads[4], g_cov3d=x.g_cov3d)
+        x.keep = it
+        x.cs = rtgs.session_struct(it)
+        x.cl = rtgs.loss_item(o["color"], o["depth"], x.target[0], x.target[1], x.gc, x.gd,
+                              x.mask, x.pcount if x.mask is not None else None)
+        x.n = n
+        x.phase_bound = phase
+
     def start_frame(self, f, spec):
         """A frame tracks its own pose, from the end pose of frame f.pose_from
         (the identity for a session's first frames), with its own Adam state
@@ -712,7 +748,9 @@ class GpuExecutor:
             f.mask = torch.empty(spec.height, spec.width, dtype=torch.uint8, device=self.dev)
             f.pcount = torch.zeros(1, dtype=torch.int32, device=self.dev)
             self.rtgs.downsample_mask(S["final_T"][f.pose_from], f.log2_ratio, f.mask,
-                                      f.pcount)
+                                      f.pcount, stream=self.stream_obj)
+        self._bind(f, S, spec, f.params, "track")
+        f.cp = self.rtgs.pose_item(f.viewmat, f.gpose, f.m, f.v, self.lr_rho, self.lr_phi)
 
     def finish_frame(self, f, spec):
         S = self.sessions[f.session]
@@ -726,148 +764,157 @@ class GpuExecutor:
         if self.record_poses:
             self.frame_poses[(f.session, f.index)] = f.viewmat
         S["inflight"] -= 1
-        if not f.keyframe:
-            f.gmask = None                          # only a keyframe's job reads it
+        f.gmask = f.cs = f.cl = f.cp = f.keep = f.grads = None
 
     def start_map(self, job, spec):
         """A keyframe's map job: version v + 1 starts as a copy of the latest
-        version v (the keyframe rendered v too), without the Gaussians the
-        keyframe masked when pruning, and is trained at the keyframe's tracked
-        pose; frames on version v keep rendering it meanwhile."""
+        version v and is trained at the keyframe's tracked pose; frames on
+        version v keep rendering it meanwhile.  When pruning, the job's first
+        iteration also scores its map (Eq. 7) and masks up to prune_ratio of
+        the Gaussians it sees; its later iterations render without them, and
+        they are removed (map and Adam moments) when the job ends (Sec. 4.1:
+        mask for K iterations, then remove)."""
         torch, rtgs = self.torch, self.rtgs
         S = self.sessions[job.session]
         base = S["versions"][S["version"]]
-        f = job.frame
+        new = [p.clone() for p in base]
         opt = S["opt"]
-        n = base[0].shape[0]
-        k = n
-        if self.prune and f.gmask is not None:
-            if f.gmask.numel() != n:
-                raise RuntimeError("keyframe mask and map version disagree")
-            f.ev_count.synchronize()                # recorded frames ago
-            k = n - int(f.h_count.item())
-        if k < n:
-            srcs = list(base) + list(opt.exp_avg) + list(opt.exp_avg_sq)
-            outs = [torch.empty((k,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device)
-                    for t in srcs]
-            cnt = torch.empty(1, dtype=torch.int32, device=self.dev)
-            rtgs.compact_by_mask(f.gmask, list(zip(srcs, outs)), cnt)
-            npar = len(base)
-            new = outs[:npar]
-            opt.exp_avg = outs[npar:2 * npar]
-            opt.exp_avg_sq = outs[2 * npar:]
-            S["removed"] += n - k
-        else:
-            new = [p.clone() for p in base]
         opt.rebind(new)
-        f.gmask = None
         job.params = new
-        job.target = f.target
+        job.target = job.frame.target
         job.mask = None
-        job.viewmat = f.pose_end
+        job.pcount = None
+        job.viewmat = job.frame.pose_end
+        job.first = self.prune
+        job.gmask = None
+        job.visible = torch.empty(new[0].shape[0], dtype=torch.uint8, device=self.dev)
+        job.out = S["out_map"]
+        self._bind(job, S, spec, new, "map")
+        job.ca = (rtgs.CAdamGroup * len(new))(*[
+            rtgs.adam_group(p, g, m, v, lr) for p, g, m, v, lr in
+            zip(new, job.grads, opt.exp_avg, opt.exp_avg_sq, opt.lrs)])
+
+    def _remove_masked(self, S, job):
+        """Permanent removal of the Gaussians the job masked (stable
+        compaction of the map and its Adam moments)."""
+        torch, rtgs = self.torch, self.rtgs
+        mask, job.gmask = job.gmask, None
+        n = job.params[0].shape[0]
+        job.ev_count.synchronize()                  # recorded iterations ago
+        k = n - int(job.h_count.item())
+        if k >= n:
+            return
+        opt = S["opt"]
+        srcs = list(job.params) + list(opt.exp_avg) + list(opt.exp_avg_sq)
+        outs = [torch.empty((k,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device)
+                for t in srcs]
+        cnt = torch.empty(1, dtype=torch.int32, device=self.dev)
+        rtgs.compact_by_mask(mask, list(zip(srcs, outs)), cnt, stream=self.stream_obj)
+        npar = len(job.params)
+        job.params = outs[:npar]
+        opt.rebind(job.params)
+        opt.exp_avg = outs[npar:2 * npar]
+        opt.exp_avg_sq = outs[2 * npar:]
+        S["removed"] += n - k
 
     def finish_map(self, job, spec):
         """Publish the job's map as the session's next version."""
         S = self.sessions[job.session]
+        if job.gmask is not None:
+            self._remove_masked(S, job)
         S["version"] += 1
         S["versions"][S["version"]] = job.params
         S["params"] = job.params
-        for v in [v for v in S["versions"] if v <= S["version"] - self.KEEP_VERSIONS]:
+        job.cs = job.cl = job.ca = job.keep = job.grads = None
+
+    def release_versions(self, s, keep_from):
+        """Forget map versions below keep_from (frames that render them hold
+        their own references)."""
+        S = self.sessions[s]
+        for v in [v for v in S["versions"] if v < keep_from and v != S["version"]]:
             del S["versions"][v]
 
     # ---- one iteration for a group of frames -----------------------------------
     def run_iteration(self, phase, frames, specs):
         torch, rtgs = self.torch, self.rtgs
-        items = []
+        st = self.stream
+        k = len(frames)
         cap = 0
-        for f in frames:
-            S = self.sessions[f.session]
-            job = isinstance(f, MapJob)
-            o = S["out_map"] if job else f.out
-            items.append(dict(scene=tuple(p.detach() for p in f.params),
-                              viewmat=f.viewmat, cam=S["cam"],
-                              pixel_mask=f.mask,
-                              gauss_mask=None if job or phase == "map" else f.gmask,
-                              visible=None if job or phase == "map" else f.visible,
-                              sample_log2=f.log2_ratio if f.mask is not None else 0,
-                              color=o["color"], depth=o["depth"], alpha=o["alpha"],
-                              final_T=o["final_T"], last_idx=o["last_idx"]))
-            cap += self._cap(S["spec"])
-        ns = [f.params[0].shape[0] for f in frames]
-        ws_ = [self.sessions[f.session]["spec"].width for f in frames]
-        hs_ = [self.sessions[f.session]["spec"].height for f in frames]
-        ws = torch.empty(rtgs.rtgs_workspace_size_batched(ns, ws_, hs_, cap),
-                         dtype=torch.uint8, device=self.dev)
-        rtgs.render_fwd_batched(self.handle, items, ws, cap)
+        for x in frames:
+            if getattr(x, "phase_bound", None) != phase:     # a frame's in-line mapping
+                self._bind(x, self.sessions[x.session], self.sessions[x.session]["spec"],
+                           x.params, phase)
+            cap += self._cap(self.sessions[x.session]["spec"])
+        arr = (rtgs.CSession * k)(*[x.cs for x in frames])
+        ws = torch.empty(rtgs.rtgs_workspace_size_batched(
+            [x.n for x in frames], [x.out["depth"].shape[1] for x in frames],
+            [x.out["depth"].shape[0] for x in frames], cap), dtype=torch.uint8, device=self.dev)
+        rtgs.render_fwd_batched_c(self.handle, arr, k, ws, cap, rtgs.RTGS_FWD_SAVE_STATE, st)
         # L1 colour + 0.5 L1 depth over the active pixels of each frame, one
         # launch for the group
-        losses = []
-        for f, it in zip(frames, items):
-            gc = torch.empty_like(it["color"])
-            gd = torch.empty_like(it["depth"])
-            losses.append((it["color"], it["depth"], f.target[0], f.target[1], gc, gd, f.mask,
-                           getattr(f, "pcount", None) if f.mask is not None else None))
-            it["dL_dcolor"] = gc
-            it["dL_ddepth"] = gd
-        rtgs.loss_l1_grad_batched(losses)
+        rtgs.loss_l1_grad_batched_c((rtgs.CLossItem * k)(*[x.cl for x in frames]), k, 1.0, 0.5,
+                                    st)
+        scoring = [x for x in frames if x.first]
         if phase == "track":
-            flags = rtgs.RTGS_GRAD_POSE
-            scored = []
-            for f, it in zip(frames, items):
-                it["g_pose6"] = f.gpose
-                if f.first:
-                    n = f.params[0].shape[0]
-                    it["g_means"] = torch.empty(n, 3, device=self.dev)
-                    it["g_cov3d"] = torch.empty(n, 6, device=self.dev)
-                    scored.append((f, it))
-                    flags |= rtgs.RTGS_GRAD_SCORE
-            rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=flags)
-            for f, it in scored:
-                self._mask_lowest(self.sessions[f.session], f, it)
-                f.first = False
-            self._pose_step(frames)
+            flags = rtgs.RTGS_GRAD_POSE | (rtgs.RTGS_GRAD_SCORE if scoring else 0)
+            rtgs.render_bwd_batched_c(self.handle, arr, k, ws, cap, flags, st)
+            for f in frames:
+                f.t += 1
+                f.cp.step = f.t
+            # Adam on xi = (rho, phi) for every frame, then T <- Exp(-step) T
+            rtgs.pose_update_c((rtgs.CPoseItem * k)(*[f.cp for f in frames]), k, 0.9, 0.999,
+                               1e-8, st)
         else:
-            grads = []
-            for f, it in zip(frames, items):
-                g = [torch.empty_like(p) for p in f.params]
-                it.update(g_means=g[0], g_log_scales=g[1], g_quats=g[2], g_opacity_logits=g[3],
-                          g_colors=g[4])
-                grads.append(g)
-            rtgs.render_bwd_batched(self.handle, items, ws, cap, grad_flags=rtgs.RTGS_GRAD_MAP)
+            flags = rtgs.RTGS_GRAD_MAP | (rtgs.RTGS_GRAD_COV3D if scoring else 0)
+            rtgs.render_bwd_batched_c(self.handle, arr, k, ws, cap, flags, st)
             # one update launch for the maps of every session of the group
-            from .optim import step_many
-            step_many(self.handle, [(getattr(f, "opt", None) or self.sessions[f.session]["opt"],
-                                     g) for f, g in zip(frames, grads)])
+            groups = []
+            for x in frames:
+                opt = getattr(x, "opt", None) or self.sessions[x.session]["opt"]
+                if getattr(x, "ca", None) is None:            # in-line mapping of a frame
+                    x.ca = (rtgs.CAdamGroup * len(x.params))(*[
+                        rtgs.adam_group(p, g, m, v, lr) for p, g, m, v, lr in
+                        zip(x.params, x.grads, opt.exp_avg, opt.exp_avg_sq, opt.lrs)])
+                opt.t += 1
+                for grp in x.ca:
+                    grp.step = opt.t
+                    groups.append(grp)
+            rtgs.adam_step_c(self.handle, (rtgs.CAdamGroup * len(groups))(*groups), len(groups),
+                             0.9, 0.999, 1e-15, st)
+        for x in scoring:
+            self._mask_lowest(self.sessions[x.session], x)
+            x.first = False
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         return ev
 
-    def _mask_lowest(self, S, f, it):
-        """The frame's mask (Sec. 4.1, Eq. 7): up to prune_ratio of its
-        visible Gaussians with the lowest importance, within what the 50% cap
-        still allows for the version it renders."""
-        torch = self.torch
-        n = f.params[0].shape[0]
+    def _mask_lowest(self, S, x):
+        """Mask of a frame or map job (Sec. 4.1, Eq. 7): up to prune_ratio of
+        the visible Gaussians with the lowest importance, within what the 50%
+        cap still allows for the map version it renders.  A frame renders its
+        later iterations without them; a job also removes them when it ends."""
+        torch, rtgs = self.torch, self.rtgs
+        n = x.params[0].shape[0]
         budget = max(0.0, self.prune_cap * S["n0"] - (S["n0"] - n))
         ratio = min(self.prune_ratio, budget / max(n, 1), 0.5)
         mask = torch.zeros(n, dtype=torch.uint8, device=self.dev)
-        count = torch.zeros(1, dtype=torch.int32, device=self.dev)
-        self.rtgs.prune_by_grad(self.handle, it["g_means"], it["g_cov3d"], f.visible, None,
-                                self.prune_lam, ratio, mask, count)
-        f.h_count = torch.zeros(1, dtype=torch.int32).pin_memory()
-        f.h_count.copy_(count, non_blocking=True)
-        f.ev_count = torch.cuda.Event()
-        f.ev_count.record()
-        f.gmask = mask
-
-    def _pose_step(self, frames, b1=0.9, b2=0.999, eps=1e-8):
-        """Adam on xi = (rho, phi) for every frame of the group, then the
-        re-linearisation T <- Exp(-step) T: one pose_update launch."""
-        items = []
-        for f in frames:
-            f.t += 1
-            items.append((f.viewmat, f.gpose, f.m, f.v, self.lr_rho, self.lr_phi, f.t))
-        self.rtgs.pose_update(items, b1, b2, eps)
+        g_means = x.grads[0] if x.phase_bound == "map" else x.g_means
+        job = isinstance(x, MapJob)
+        count = torch.zeros(1, dtype=torch.int32, device=self.dev) if job else None
+        rtgs.prune_by_grad(self.handle, g_means, x.g_cov3d, x.visible, None, self.prune_lam,
+                           ratio, mask, count, stream=self.stream_obj)
+        if job:
+            x.h_count = torch.zeros(1, dtype=torch.int32).pin_memory()
+            x.h_count.copy_(count, non_blocking=True)
+            x.ev_count = torch.cuda.Event()
+            x.ev_count.record()
+        x.gmask = mask
+        x.keep["gauss_mask"] = mask
+        x.cs.g.gauss_mask = mask.data_ptr()
+        if not job:                                   # the score outputs were one-off
+            x.cs.g_means = None
+            x.cs.g_cov3d = None
+            x.g_means = x.g_cov3d = None
 
     # ---- clock ----------------------------------------------------------------
     def clock(self):
@@ -886,6 +933,8 @@ class GpuExecutor:
                 self.start_frame(f, spec)
                 f.params = [p.clone() for p in f.params]
                 f.opt = MapAdam(f.params, eps=1e-15)
+                f.phase_bound = None
+                f.first = self.prune and phase == "track"
                 for _ in range(iters):
                     self.run_iteration(phase, [f], [spec])
                 S["inflight"] -= 1
