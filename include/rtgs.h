@@ -62,6 +62,14 @@ extern "C" {
                                      last forward (see render_fwd)            */
 #define RTGS_FWD_STATS        2   /* write per-pixel work counts (sessions'
                                      `stats`; render_fwd_batched only)         */
+#define RTGS_FWD_SAVE_FRAGMENTS 16 /* also save every blended fragment's
+                                     alpha (the per-fragment state of the R&B
+                                     buffer, Sec. 5.2) in the workspace, for a
+                                     backward with RTGS_GRAD_SAVED_FRAGMENTS;
+                                     needs RTGS_FWD_SAVE_STATE and a workspace
+                                     sized with this flag (2 KB more per pair
+                                     of capacity: room for every lane of a
+                                     wave blending every list entry)          */
 
 /* ---- render_bwd flags ---- */
 #define RTGS_GRAD_POSE        1   /* write g_pose6 and/or g_viewmat            */
@@ -69,6 +77,13 @@ extern "C" {
 #define RTGS_GRAD_COV3D       4   /* also write g_cov3d (needs RTGS_GRAD_MAP)  */
 #define RTGS_GRAD_RECOMPUTE_STATE 8 /* final_T/last_idx were not saved: the
                                        backward recomputes them first          */
+#define RTGS_GRAD_SAVED_FRAGMENTS 32 /* the forward saved its fragments
+                                     (RTGS_FWD_SAVE_FRAGMENTS): the backward
+                                     reads each blended fragment's alpha
+                                     instead of re-evaluating Eq. 2, and skips
+                                     list entries no pixel of a wave blended;
+                                     the gradients are bitwise those without
+                                     the flag                                 */
 #define RTGS_GRAD_SCORE      16   /* without RTGS_GRAD_MAP: write g_means and
                                      g_cov3d only, the inputs of the
                                      importance score of Sec. 4.1 (the raster

@@ -7,11 +7,20 @@ world->camera).  The view-matrix gradient treats the entries as independent,
 so any SE(3) parametrisation built in torch (e.g. ``pose.apply_left(xi, T0)``)
 receives its exact gradient through autograd.
 
-Per-pixel state between the passes (final transmittance + last blended list
-position, 8 bytes per pixel, the analogue of the paper's R&B buffer reuse,
-Sec. 5.2): ``state="save"`` keeps it from the forward, ``"recompute"`` makes
-the backward re-run the forward compositing to rebuild it, ``"auto"`` saves
-unless the 8 B/pixel would exceed ``auto_budget`` of the free device memory.
+State between the passes, three policies (the paper's R&B buffer keeps
+per-fragment results for the backward, Sec. 5.2):
+
+* ``state="save"``: per pixel the final transmittance and the last blended
+  list position (8 bytes per pixel); the backward recovers each fragment's
+  transmittance and re-evaluates its alpha (Eq. 2);
+* ``"fragments"``: that, and every blended fragment's alpha as the forward
+  computed it (workspace proportional to the pairs: 2 KB per pair of
+  capacity); the backward reads it instead of re-evaluating, with bitwise the
+  same gradients;
+* ``"recompute"``: nothing per pixel; the backward re-runs the forward
+  compositing to rebuild the per-pixel state;
+* ``"auto"``: save unless 8 B/pixel would exceed ``auto_budget`` of the free
+  device memory.
 """
 import torch
 
@@ -30,12 +39,13 @@ def default_renderer(device=None):
 class RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, viewmat, cam, renderer,
-                gauss_mask, pixel_mask, save_state, need_cov3d):
+                gauss_mask, pixel_mask, state, need_cov3d):
         scene = tuple(t.detach().contiguous() for t in
                       (means, log_scales, quats, opacity_logits, colors))
         vm = viewmat.detach().contiguous()
         st = renderer.forward(scene, vm, cam, gauss_mask=gauss_mask, pixel_mask=pixel_mask,
-                              save_state=save_state)
+                              save_state=state != "recompute",
+                              save_fragments=state == "fragments")
         ctx.scene = scene
         ctx.vm = vm
         ctx.cam = cam
@@ -78,12 +88,10 @@ def render(means, log_scales, quats, opacity_logits, colors, viewmat, cam, rende
     renderer = renderer or default_renderer(means.device.index)
     if state == "auto":
         free, _total = torch.cuda.mem_get_info(means.device)
-        save = 8 * cam.width * cam.height <= auto_budget * free
-    else:
-        if state not in ("save", "recompute"):
-            raise ValueError("state must be 'save', 'recompute' or 'auto'")
-        save = state == "save"
+        state = "save" if 8 * cam.width * cam.height <= auto_budget * free else "recompute"
+    elif state not in ("save", "fragments", "recompute"):
+        raise ValueError("state must be 'save', 'fragments', 'recompute' or 'auto'")
     vm = viewmat.reshape(3, 4)
     c, d, a, vis = RenderFn.apply(means, log_scales, quats, opacity_logits, colors, vm, cam,
-                                  renderer, gauss_mask, pixel_mask, save, need_cov3d)
+                                  renderer, gauss_mask, pixel_mask, state, need_cov3d)
     return c, d, a, vis

@@ -119,7 +119,7 @@ struct rtgs_context {
 
 namespace rtgs {
 
-WsLayout make_layout(const Counts& c, int64_t cap) {
+WsLayout make_layout(const Counts& c, int64_t cap, bool frags) {
   WsLayout L{};
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -149,6 +149,11 @@ WsLayout make_layout(const Counts& c, int64_t cap) {
   L.partial = take(4 * 10 * (uint64_t)cap);
   L.state_t = take(4 * (uint64_t)c.px_total);
   L.state_last = take(4 * (uint64_t)c.px_total);
+  if (frags) {
+    L.fmask = take(8 * 4 * (uint64_t)cap);
+    L.fcount = take(4 * 4 * t);
+    L.fdata = take(8 * 256 * (uint64_t)cap);
+  }
   L.total = off;
   L.n_total = c.n_total;
   L.t_total = c.t_total;
@@ -181,6 +186,11 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.partial = reinterpret_cast<float*>(base + L.partial);
   w.state_t = reinterpret_cast<float*>(base + L.state_t);
   w.state_last = reinterpret_cast<int32_t*>(base + L.state_last);
+  if (L.fdata) {
+    w.fmask = reinterpret_cast<unsigned long long*>(base + L.fmask);
+    w.fcount = reinterpret_cast<uint32_t*>(base + L.fcount);
+    w.fdata = reinterpret_cast<float2*>(base + L.fdata);
+  }
   w.cap = L.cap;
   return w;
 }
@@ -357,7 +367,7 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
 }
 
 int32_t prepare(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws, uint64_t ws_bytes,
-                int64_t cap, WsLayout& L, WsPtrs& w) {
+                int64_t cap, WsLayout& L, WsPtrs& w, bool frags = false) {
   if (!h) return fail(RTGS_ERR_INVALID_ARG, "null handle");
   if (!ss) return fail(RTGS_ERR_INVALID_ARG, "null sessions");
   if (ns < 1 || ns > RTGS_MAX_SESSIONS)
@@ -377,7 +387,7 @@ int32_t prepare(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws, u
   r = geometry(n.data(), wd.data(), ht.data(), ns, g, js.data());
   if (r) return r;
   if (!ws) return fail(RTGS_ERR_INVALID_ARG, "null workspace");
-  L = make_layout(g, cap);
+  L = make_layout(g, cap, frags);
   if (ws_bytes < L.total)
     return fail(RTGS_ERR_WORKSPACE, "workspace %llu bytes < required %llu",
                 (unsigned long long)ws_bytes, (unsigned long long)L.total);
@@ -444,14 +454,13 @@ int32_t rtgs_destroy(rtgs_handle_t h) {
 int32_t rtgs_workspace_size_batched(const int32_t* n, const int32_t* width, const int32_t* height,
                                     int32_t n_sessions, int64_t pair_capacity, int32_t flags,
                                     uint64_t* bytes) {
-  (void)flags;
   if (!n || !width || !height || !bytes) return fail(RTGS_ERR_INVALID_ARG, "null argument");
   int32_t r = check_cap(pair_capacity);
   if (r) return r;
   Counts g;
   r = geometry(n, width, height, n_sessions, g);
   if (r) return r;
-  *bytes = make_layout(g, pair_capacity).total;
+  *bytes = make_layout(g, pair_capacity, (flags & RTGS_FWD_SAVE_FRAGMENTS) != 0).total;
   return RTGS_OK;
 }
 
@@ -464,18 +473,22 @@ int32_t rtgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t pa
   Counts g;
   r = geometry(&n, &width, &height, 1, g, &j);
   if (r) return r;
-  *bytes = make_layout(g, pair_capacity).total;
+  *bytes = make_layout(g, pair_capacity, (flags & RTGS_FWD_SAVE_FRAGMENTS) != 0).total;
   return RTGS_OK;
 }
 
 int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
-  if (flags & ~(RTGS_FWD_SAVE_STATE | RTGS_FWD_STATS | RTGS_FWD_REUSE_LISTS))
+  if (flags & ~(RTGS_FWD_SAVE_STATE | RTGS_FWD_STATS | RTGS_FWD_REUSE_LISTS |
+                RTGS_FWD_SAVE_FRAGMENTS))
     return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d (sample_log2 goes in the sessions)",
                 flags);
+  const bool frags = (flags & RTGS_FWD_SAVE_FRAGMENTS) != 0;
+  if (frags && !(flags & RTGS_FWD_SAVE_STATE))
+    return fail(RTGS_ERR_INVALID_ARG, "RTGS_FWD_SAVE_FRAGMENTS needs RTGS_FWD_SAVE_STATE");
   WsLayout L;
   WsPtrs w;
-  int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w);
+  int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w, frags);
   if (r) return r;
   for (int i = 0; i < ns; ++i) {
     if ((r = check_session(ss[i], i, true, flags))) return r;
@@ -489,7 +502,8 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
   hipError_t e = launch_forward_prep(B, w, h->d_scalars, (flags & RTGS_FWD_REUSE_LISTS) != 0,
                                      st, tm);
-  if (e == hipSuccess) e = launch_raster_fwd(B, w, (flags & RTGS_FWD_STATS) != 0, st, tm);
+  if (e == hipSuccess)
+    e = launch_raster_fwd(B, w, (flags & RTGS_FWD_STATS) != 0, frags, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_fwd launch");
   h->last_stream = st;
   h->used = true;
@@ -499,13 +513,16 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
 int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
   const int32_t known = RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_COV3D |
-                        RTGS_GRAD_RECOMPUTE_STATE | RTGS_GRAD_SCORE;
+                        RTGS_GRAD_RECOMPUTE_STATE | RTGS_GRAD_SCORE | RTGS_GRAD_SAVED_FRAGMENTS;
   if (flags & ~known) return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
   if (!(flags & (RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_SCORE)))
     return fail(RTGS_ERR_INVALID_ARG, "render_bwd needs RTGS_GRAD_POSE, MAP or SCORE");
+  const bool frags = (flags & RTGS_GRAD_SAVED_FRAGMENTS) != 0;
+  if (frags && (flags & RTGS_GRAD_RECOMPUTE_STATE))
+    return fail(RTGS_ERR_INVALID_ARG, "saved fragments come with saved state, not recompute");
   WsLayout L;
   WsPtrs w;
-  int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w);
+  int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w, frags);
   if (r) return r;
   for (int i = 0; i < ns; ++i)
     if ((r = check_session(ss[i], i, false, flags))) return r;
@@ -515,11 +532,11 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   if (r) return r;
   StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
   hipError_t e = hipSuccess;
-  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, false, st, tm);
+  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, false, false, st, tm);
   bool alpha_grad = false;            // some session passes dL/dA
   for (int i = 0; i < ns; ++i) alpha_grad = alpha_grad || ss[i].dL_dalpha != nullptr;
   if (e == hipSuccess)
-    e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, alpha_grad, st, tm);
+    e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, alpha_grad, frags, st, tm);
   if (e == hipSuccess) e = launch_preprocess_bwd(B, w, flags, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_bwd launch");
   h->last_stream = st;

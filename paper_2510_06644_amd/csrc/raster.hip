@@ -137,9 +137,25 @@ __device__ __forceinline__ unsigned long long wave_entries(const unsigned* s_m, 
   return __ballot(hit);
 }
 
+// Saved fragments (the per-fragment state of the paper's R&B buffer): for
+// every list entry a wave evaluates, the 64-bit mask of its lanes that
+// blended it, and for those lanes, in entry order and compacted by lane rank,
+// (alpha, 1 - alpha) with alpha negated where it was clamped to 0.99.  The
+// stream of wave w of a tile with list [start, end) begins at float2 index
+// 64 (4 start + w (end - start)): room for every lane blending every entry.
+__device__ __forceinline__ int64_t frag_base(int start, int end, int wave) {
+  return 64 * (4 * (int64_t)start + (int64_t)wave * (end - start));
+}
+
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // STATS: also count, per pixel, the fragments blended and the list entries
 // visited (the work counts of a frame); off in ordinary renders.
-template <bool STATS>
+// FRAG: also save the fragments' alpha (see frag_base).
+template <bool STATS, bool FRAG>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock];
   __shared__ unsigned s_m[kBlock];
@@ -160,6 +176,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   int last = -1;
   int stop = end;               // list position where the pixel stopped
   int nblend = 0;
+  const int fwave = tid >> 6, flane = tid & 63;
+  uint32_t fcur = 0;            // saved fragments of this wave so far
+  const int64_t fbase = FRAG ? frag_base(start, end, fwave) : 0;
   // the Gaussian id this thread stages next (loaded one batch ahead)
   uint32_t nid = start + tid < end ? W.ids[start + tid] : 0u;
   for (int b0 = start; b0 < end; b0 += kBlock) {
@@ -199,6 +218,16 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         T = blend ? tn : (stop_here ? -T : T);
         last = blend ? b0 + k : last;
         if (STATS) nblend += blend ? 1 : 0;
+        if (FRAG) {
+          const unsigned long long bm = __ballot(blend);
+          if (flane == 0) W.fmask[(int64_t)(b0 + k) * 4 + fwave] = bm;
+          if (blend) {
+            const float4 k4 = s_r1[k];
+            W.fdata[fbase + fcur + lane_rank(bm)] =
+                make_float2(k4.w * f.e > kAlphaMax ? -f.alpha : f.alpha, f.om);
+          }
+          fcur += (uint32_t)__popcll(bm);
+        }
       };
       while (m) {
         if (__ballot(T > 0.f) == 0) break;             // the whole wave has stopped
@@ -212,6 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     }
     __syncthreads();
   }
+  if (FRAG && flane == 0) W.fcount[(int64_t)tile * 4 + fwave] = fcur;
   T = fabsf(T);
   if (!c.inside) return;
   const int64_t hw = (int64_t)S.width * S.height;
@@ -259,12 +289,18 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 // inside each wave, then the four waves in order), so the result is bitwise
 // reproducible and no float atomics are used.  Eight waves per SIMD: the
 // compiler is held to 64 VGPRs.
-template <int NV, bool GA>
+// FRAG: the forward saved its fragments (frag_base): each entry's blending
+// lanes and their (alpha, 1 - alpha) are read instead of re-evaluating alpha,
+// and entries no lane of the wave blended are skipped without arithmetic; the
+// values are those the forward computed, so the gradients are bitwise those
+// of the re-evaluating form.
+template <int NV, bool GA, bool FRAG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
   __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch], s_cn[kBwdBatch];
   __shared__ unsigned s_m[kBwdBatch];
+  __shared__ unsigned long long s_fm[FRAG ? 4 : 1][FRAG ? kBwdBatch : 1];
   // per wave: kStride floats per entry, then one float that takes the
   // reduce-scatter outputs no entry needs; rows padded to 16 bytes so they
   // are cleared with 16-byte stores
@@ -301,6 +337,16 @@ void k_raster_bwd(Batch B, WsPtrs W) {
   // never followed past the list
   const int hi = min(s_hi, end - 1);
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
+  // saved fragments: this wave's last blended position, its stream and cursor
+  int wave_last = last;
+  uint32_t fcur = 0;
+  int64_t fbase = 0;
+  if (FRAG) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, off));
+    fcur = W.fcount[(int64_t)tile * 4 + wave];
+    fbase = frag_base(start, end, wave);
+  }
   // S_j . g: the colour and depth of the fragments behind j, normalised by
   // the transmittance T_{j+1} they start from, dotted with the upstream gradient
   float SG = 0.f;
@@ -326,6 +372,16 @@ void k_raster_bwd(Batch B, WsPtrs W) {
       // the forward staged every entry up to the last blended one of any
       // pixel of the tile, and saved its quadrant mask
       s_m[tid] = W.qmask[b0 + tid];
+      if (FRAG) {
+        // blend masks; a wave reads only entries up to its last blend, all of
+        // which its forward evaluated and wrote
+        const ulonglong2* fm = reinterpret_cast<const ulonglong2*>(W.fmask + (int64_t)(b0 + tid) * 4);
+        const ulonglong2 a = fm[0], b = fm[1];
+        s_fm[0][tid] = a.x;
+        s_fm[1][tid] = a.y;
+        s_fm[2][tid] = b.x;
+        s_fm[3][tid] = b.y;
+      }
     }
     {
       const int nb0 = max(b0 - kBwdBatch, start);
@@ -339,9 +395,28 @@ void k_raster_bwd(Batch B, WsPtrs W) {
       unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
       auto step = [&](int k) {
         const float4 k4 = s_r1[k];
-        const Frag f = frag_alpha(s_r0[k], k4, pxf, pyf);
-        const bool contrib = k <= lrel && !(f.alpha < kAlphaMin);
-        if (__ballot(contrib) == 0) return;            // no lane blended this entry
+        Frag f;
+        bool contrib, clamped;
+        if (FRAG) {
+          if (b0 + k > wave_last) return;                // after every blend of the wave
+          const unsigned long long bm = s_fm[wave][k];
+          if (bm == 0) return;                           // no lane blended this entry
+          fcur -= (uint32_t)__popcll(bm);
+          contrib = ((bm >> lane) & 1ull) != 0;
+          float2 rec = make_float2(0.f, 1.f);
+          if (contrib) rec = W.fdata[fbase + fcur + lane_rank(bm)];
+          const float4 r0 = s_r0[k];
+          f.dx = (r0.x - pxf) + r0.z;
+          f.dy = (r0.y - pyf) + r0.w;
+          f.alpha = fabsf(rec.x);
+          f.om = rec.y;
+          clamped = rec.x < 0.f;
+        } else {
+          f = frag_alpha(s_r0[k], k4, pxf, pyf);
+          contrib = k <= lrel && !(f.alpha < kAlphaMin);
+          if (__ballot(contrib) == 0) return;            // no lane blended this entry
+          clamped = k4.w * f.e > kAlphaMax;
+        }
         // lanes that did not blend it take alpha = 0 and 1 - alpha = 1, so
         // every update below leaves their state unchanged and their
         // gradients exactly zero (selects, not branches)
@@ -361,7 +436,7 @@ void k_raster_bwd(Batch B, WsPtrs W) {
         SG = __builtin_fmaf(al, cg, om * SG);
         Tc = Tj;
         // the clamp alpha = 0.99 has no gradient to o or to the power
-        const bool live = contrib && !(k4.w * f.e > kAlphaMax);
+        const bool live = contrib && !clamped;
         const float ng = live ? -(f.alpha * dla) : 0.f;  // -dL/dpower
         const float pg = ng * f.dx, qg = ng * f.dy;
         // summed over the tile's pixels, these give the 2D gradients once
@@ -454,33 +529,49 @@ void k_raster_bwd(Batch B, WsPtrs W) {
 
 }  // namespace
 
-hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, hipStream_t st,
-                             StageTimer* tm) {
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, bool frags,
+                             hipStream_t st, StageTimer* tm) {
   if (b.t_total <= 0) return hipSuccess;
   const int grid = 8 * ((b.t_total + 7) / 8);
   Scope sc(tm, kStRasterFwd, st);
-  if (stats)
-    k_raster_fwd<true><<<grid, kBlock, 0, st>>>(b, w);
-  else
-    k_raster_fwd<false><<<grid, kBlock, 0, st>>>(b, w);
+  if (stats) {
+    if (frags)
+      k_raster_fwd<true, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_fwd<true, false><<<grid, kBlock, 0, st>>>(b, w);
+  } else {
+    if (frags)
+      k_raster_fwd<false, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_fwd<false, false><<<grid, kBlock, 0, st>>>(b, w);
+  }
   return hipGetLastError();
 }
 
+template <int NV, bool GA>
+static void raster_bwd_frag(const Batch& b, const WsPtrs& w, bool frags, int grid,
+                            hipStream_t st) {
+  if (frags)
+    k_raster_bwd<NV, GA, true><<<grid, kBlock, 0, st>>>(b, w);
+  else
+    k_raster_bwd<NV, GA, false><<<grid, kBlock, 0, st>>>(b, w);
+}
+
 hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, bool alpha_grad,
-                             hipStream_t st, StageTimer* tm) {
+                             bool frags, hipStream_t st, StageTimer* tm) {
   if (b.t_total <= 0) return hipGetLastError();
   const int grid = 8 * ((b.t_total + 7) / 8);
   Scope sc(tm, kStRasterBwd, st);
   if (pose_only) {
     if (alpha_grad)
-      k_raster_bwd<6, true><<<grid, kBlock, 0, st>>>(b, w);
+      raster_bwd_frag<6, true>(b, w, frags, grid, st);
     else
-      k_raster_bwd<6, false><<<grid, kBlock, 0, st>>>(b, w);
+      raster_bwd_frag<6, false>(b, w, frags, grid, st);
   } else {
     if (alpha_grad)
-      k_raster_bwd<10, true><<<grid, kBlock, 0, st>>>(b, w);
+      raster_bwd_frag<10, true>(b, w, frags, grid, st);
     else
-      k_raster_bwd<10, false><<<grid, kBlock, 0, st>>>(b, w);
+      raster_bwd_frag<10, false>(b, w, frags, grid, st);
   }
   return hipGetLastError();
 }

@@ -92,6 +92,10 @@ struct WsLayout {
   uint64_t partial;     // float[cap][10]: per (tile, Gaussian) merged 2D gradient
   uint64_t state_t;     // float[pixels]: recomputed final T
   uint64_t state_last;  // int32[pixels]: recomputed last position
+  // saved fragments (workspace sized with RTGS_FWD_SAVE_FRAGMENTS, else absent)
+  uint64_t fmask;       // uint64[4 cap]: blend mask of each (list entry, wave)
+  uint64_t fcount;      // uint32[4 T]: saved fragments of each (tile, wave)
+  uint64_t fdata;       // float2[256 cap]: (alpha, 1 - alpha) streams per (tile, wave)
   uint64_t total;       // bytes
   int64_t n_total;
   int64_t t_total;
@@ -104,7 +108,7 @@ struct Counts {
   int64_t t_max = 0;
 };
 
-WsLayout make_layout(const Counts& c, int64_t cap);
+WsLayout make_layout(const Counts& c, int64_t cap, bool frags = false);
 
 // What the raster kernels read of one Gaussian, packed into one 64-byte
 // line so that staging a list entry touches a single cache line.
@@ -139,6 +143,9 @@ struct WsPtrs {
   float* partial;
   float* state_t;
   int32_t* state_last;
+  unsigned long long* fmask;   // null without saved fragments
+  uint32_t* fcount;
+  float2* fdata;
   int64_t cap;
 };
 
@@ -185,11 +192,10 @@ struct Scope {
 // ---- launch wrappers (defined in the .hip files) ----
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
                                bool reuse_lists, hipStream_t st, StageTimer* tm);
-hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, hipStream_t st,
-                             StageTimer* tm);
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, bool frags,
+                             hipStream_t st, StageTimer* tm);
 hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, bool alpha_grad,
-                             hipStream_t st,
-                             StageTimer* tm);
+                             bool frags, hipStream_t st, StageTimer* tm);
 hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st,
                                  StageTimer* tm);
 hipError_t launch_prune(const float* g_means, const float* g_cov3d, const uint8_t* visible,

@@ -31,6 +31,7 @@ RTGS_ERR_WORKSPACE = -4
 RTGS_FWD_SAVE_STATE = 1
 RTGS_FWD_STATS = 2
 RTGS_FWD_REUSE_LISTS = 4
+RTGS_FWD_SAVE_FRAGMENTS = 16
 RTGS_PROFILE_STAGES = 16
 STAGES = ("init", "preprocess", "scan", "emit", "sort", "raster_fwd", "adam", "raster_bwd",
           "preprocess_bwd", "pose_reduce", "bin_count", "merge")
@@ -39,6 +40,7 @@ RTGS_GRAD_MAP = 2
 RTGS_GRAD_COV3D = 4
 RTGS_GRAD_RECOMPUTE_STATE = 8
 RTGS_GRAD_SCORE = 16
+RTGS_GRAD_SAVED_FRAGMENTS = 32
 RTGS_STATE_IDLE = 0
 RTGS_STATE_EXECUTING = 1
 RTGS_MAX_SESSIONS = 64
@@ -624,7 +626,8 @@ class Renderer:
 
     # ------------------------------------------------------------------ managed calls
     def forward(self, scene, viewmat, cam: Cam, gauss_mask=None, pixel_mask=None,
-                save_state=True, stream=None, sample_log2=0, reuse_lists_of=None):
+                save_state=True, stream=None, sample_log2=0, reuse_lists_of=None,
+                save_fragments=False):
         """Render one frame; returns a FwdState (outputs + the workspace the
         matching backward needs).  Each forward gets its own workspace from
         torch's caching allocator, so several forwards may await backward.
@@ -632,8 +635,15 @@ class Renderer:
         reuse_lists_of: a FwdState of an earlier full forward of the same
         frame geometry; its tile lists and depth order are reused (projection
         only, no binning or sort) and its workspace is shared, so that
-        state's own backward must already have run."""
+        state's own backward must already have run.
+
+        save_fragments: also save every blended fragment's alpha (the
+        backward then reads it instead of re-evaluating Eq. 2); the workspace
+        grows by 2 KB per pair of capacity."""
         n = scene[0].shape[0]
+        if save_fragments and (not save_state or reuse_lists_of is not None):
+            raise ValueError("save_fragments needs save_state and a full forward")
+        fflag = RTGS_FWD_SAVE_FRAGMENTS if save_fragments else 0
         dev = scene[0].device
         h, w = cam.height, cam.width
         if reuse_lists_of is not None:
@@ -658,9 +668,10 @@ class Renderer:
         est = int(self.ppg * n) + 4 * _tiles(w, h)
         cap = max(self.cap, est, self.min_cap)
         while True:
-            need = rtgs_workspace_size(n, w, h, cap)
+            need = rtgs_workspace_size(n, w, h, cap, fflag)
             ws = torch.empty(need, dtype=torch.uint8, device=dev)
             out = FwdState(ws=ws, cap=cap, cam=cam, n=n, sample_log2=sample_log2,
+                           frags=save_fragments,
                            color=torch.empty(3, h, w, device=dev),
                            depth=torch.empty(h, w, device=dev),
                            alpha=torch.empty(h, w, device=dev),
@@ -671,7 +682,7 @@ class Renderer:
             render_fwd(self.handle, *scene, viewmat, cam, ws, cap, out.color, out.depth,
                        out.alpha, out.final_T, out.last_idx, out.visible, gauss_mask=gauss_mask,
                        pixel_mask=pixel_mask,
-                       flags=(RTGS_FWD_SAVE_STATE if save_state else 0)
+                       flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | fflag
                        | (int(sample_log2) << RTGS_SAMPLE_SHIFT), stream=stream)
             self.cap = max(self.cap, cap)
             if self.check != "every":
@@ -696,6 +707,8 @@ class Renderer:
         flags |= RTGS_GRAD_SCORE if score and not map_grads else 0
         if st.final_T is None:
             flags |= RTGS_GRAD_RECOMPUTE_STATE
+        if st.frags:
+            flags |= RTGS_GRAD_SAVED_FRAGMENTS
         flags |= int(st.sample_log2) << RTGS_SAMPLE_SHIFT
         g = {}
         if map_grads:
@@ -735,6 +748,7 @@ class FwdState:
     visible: torch.Tensor
     sample_log2: int = 0
     pairs: int = -1
+    frags: bool = False
 
     def stage(self):
         """Forward intermediates for tests: dict of numpy arrays."""

@@ -1,7 +1,8 @@
 """The autograd Function (render_fwd / render_bwd as torch.autograd.Function):
 gradients to every map parameter and to a pose parametrised as
-Exp(xi) T0 at xi != 0, against the float64 oracle; saved versus recomputed
-per-pixel state give bitwise-identical gradients."""
+Exp(xi) T0 at xi != 0, against the float64 oracle, with each state policy;
+saved per-pixel state, saved fragments and recomputed state give
+bitwise-identical gradients."""
 import numpy as np
 import pytest
 import torch
@@ -21,8 +22,9 @@ def _loss(c, d, a, gc, gd, ga):
     return (c * gc).sum() + (d * gd).sum() + (a * ga).sum()
 
 
-def test_autograd_matches_oracle_with_pose_off_zero():
-    say("test_autograd_matches_oracle_with_pose_off_zero")
+@pytest.mark.parametrize("state", ["save", "fragments"])
+def test_autograd_matches_oracle_with_pose_off_zero(state):
+    say(f"test_autograd_matches_oracle_with_pose_off_zero state={state}")
     spec = synth.CONFIGS["c0"]
     cam = synth.make_camera(spec.width, spec.height)
     sc = synth.make_scene(spec, cam)
@@ -37,7 +39,7 @@ def test_autograd_matches_oracle_with_pose_off_zero():
     keep = ~ref_f.flags.numpy()
     gc, gd, ga = synth.upstream_grads(cam.width, cam.height, 9)
     gc, gd, ga = gc * keep[None], gd * keep, ga * keep
-    c, d, a, _ = autograd.render(*params, vm, rcam(cam), state="save")
+    c, d, a, _ = autograd.render(*params, vm, rcam(cam), state=state)
     _loss(c, d, a, torch.from_numpy(gc).cuda(), torch.from_numpy(gd).cuda(),
           torch.from_numpy(ga).cuda()).backward()
     torch.cuda.synchronize()
@@ -63,20 +65,21 @@ def test_saved_and_recomputed_state_give_identical_gradients():
     gc, gd, ga = (torch.from_numpy(x).cuda() for x in synth.upstream_grads(128, 128, 10))
     vm = torch.from_numpy(eye_view()).cuda()
     grads = []
-    for state in ("save", "recompute"):
+    for state in ("save", "recompute", "fragments"):
         params = _leaves(sc)
         v = vm.clone().requires_grad_(True)
         c, d, a, _ = autograd.render(*params, v, rcam(cam), state=state)
         _loss(c, d, a, gc, gd, ga).backward()
         grads.append([p.grad.clone() for p in params] + [v.grad.clone()])
     torch.cuda.synchronize()
-    for x, y in zip(*grads):
-        assert torch.equal(x, y)
+    for other in grads[1:]:
+        for x, y in zip(grads[0], other):
+            assert torch.equal(x, y)
 
 
 def test_c3_saved_vs_recompute_at_1200x680_500k():
     """The differentiation workload: 1200x680, 500,000 Gaussians, gradients to
-    the pose and all map parameters.  Both state policies give the same
+    the pose and all map parameters.  The three state policies give the same
     gradients bit for bit; time and peak memory of each are printed."""
     say("test_c3_saved_vs_recompute")
     spec = synth.CONFIGS["c3"]
@@ -87,7 +90,7 @@ def test_c3_saved_vs_recompute_at_1200x680_500k():
     gd = torch.randn(cam.height, cam.width, device="cuda") * 1e-6
     vm = torch.from_numpy(view_c3()).cuda()
     out = {}
-    for state in ("save", "recompute", "save", "recompute"):
+    for state in ("save", "recompute", "fragments", "save", "recompute", "fragments"):
         params = _leaves(sc)
         v = vm.clone().requires_grad_(True)
         torch.cuda.synchronize()
@@ -101,10 +104,11 @@ def test_c3_saved_vs_recompute_at_1200x680_500k():
         torch.cuda.synchronize()
         out[state] = (e0.elapsed_time(e1), torch.cuda.max_memory_allocated() - base,
                       [p.grad for p in params] + [v.grad])
-    for k in ("save", "recompute"):
+    for k in ("save", "recompute", "fragments"):
         say(f"  {k}: {out[k][0]:.3f} ms, peak +{out[k][1] / 2**20:.1f} MiB")
-    for x, y in zip(out["save"][2], out["recompute"][2]):
-        assert torch.equal(x, y)
+    for k in ("recompute", "fragments"):
+        for x, y in zip(out["save"][2], out[k][2]):
+            assert torch.equal(x, y), k
 
 
 def view_c3():
