@@ -333,6 +333,79 @@ def as_written_variant(R, params, view, rc, opt, tc, td, iters=60):
             "pruned": int(n_masked.item()), "active_pixels": int(n_act.item())}
 
 
+def lane_efficiency(work, prev, w, h):
+    """Mean over waves of (mean / max) of the entries each lane walked, for
+    the quadrant assignment and for the assignment sorted by `prev` (the
+    previous forward's per-pixel work); tiles of 16 x 16, waves of 64."""
+    tw, th = (w + 15) // 16, (h + 15) // 16
+    pad = lambda a: np.pad(a.astype(np.int64), ((0, th * 16 - h), (0, tw * 16 - w)))
+    cur = pad(work).reshape(th, 16, tw, 16).transpose(0, 2, 1, 3).reshape(-1, 256)
+    old = pad(prev).reshape(th, 16, tw, 16).transpose(0, 2, 1, 3).reshape(-1, 256)
+    sy, sx = np.divmod(np.arange(256), 16)
+    quad = (sy // 8) * 2 + sx // 8
+    def eff(groups):
+        out = []
+        for q in range(4):
+            vals = np.where(groups == q, cur, -1)
+            mx = vals.max(1)
+            cnt = (groups == q).sum(1)
+            mean = np.where(groups == q, cur, 0).sum(1) / np.maximum(cnt, 1)
+            ok = mx > 0
+            out.append(mean[ok] / mx[ok])
+        return float(np.concatenate(out).mean())
+    key = old * 256 + np.arange(256)[None, :]
+    rank = np.argsort(np.argsort(key, axis=1), axis=1)
+    return {"quadrants": eff(np.broadcast_to(quad, cur.shape)), "by_previous_work": eff(rank // 64)}
+
+
+def lane_balance_run(iters=20):
+    """The mapping iteration (1200x680 / 300k) and the tracking iteration
+    (640x480 / 100k, pose only) with lanes assigned by the previous
+    iteration's work (RTGS_FWD_BALANCE_LANES) against the quadrant
+    assignment: raster kernel times (HIP events) and lane efficiency."""
+    import torch
+    from paper_2510_06644_amd import rtgs, synth
+    out = {}
+    for name in ("c2", "c1"):
+        spec = synth.CONFIGS[name]
+        cam = synth.make_camera(spec.width, spec.height)
+        sc = synth.make_scene(spec, cam)
+        scene = tuple(torch.from_numpy(a).cuda() for a in sc.arrays())
+        rc = rtgs.Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+        R = rtgs.Renderer(0, check="deferred")
+        view = torch.eye(3, 4, dtype=torch.float32, device="cuda").contiguous()
+        tc, td = render_target(R, scene, view, rc, spec.seed)
+        h, w = cam.height, cam.width
+        bufs = [torch.zeros(h, w, dtype=torch.uint16, device="cuda") for _ in range(2)]
+        res = {}
+        for mode in ("quadrants", "balanced", "quadrants", "balanced"):
+            bal = mode == "balanced"
+            rtgs.rtgs_profile_enable(R.handle, ["raster_fwd", "raster_bwd"])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for it in range(iters):
+                kw = dict(balance=True, lane_work=bufs[it % 2] if it else None,
+                          lane_work_out=bufs[(it + 1) % 2]) if bal else {}
+                st = R.forward(scene, view, rc, **kw)
+                gc, gd = l1_grads(st.color, st.depth, tc, td)
+                R.backward(scene, view, rc, st, gc, gd, pose=name == "c1",
+                           map_grads=name == "c2")
+            e1.record()
+            torch.cuda.synchronize()
+            prof = rtgs.rtgs_profile_read(R.handle)
+            rtgs.rtgs_profile_enable(R.handle, [])
+            R.verify()
+            res[mode] = {"ms_per_iter": e0.elapsed_time(e1) / iters,
+                         "raster_fwd_us": 1000 * prof["raster_fwd"][0] / prof["raster_fwd"][1],
+                         "raster_bwd_us": 1000 * prof["raster_bwd"][0] / prof["raster_bwd"][1]}
+        work = bufs[iters % 2].cpu().numpy()
+        prev = bufs[(iters + 1) % 2].cpu().numpy()
+        res["lane_efficiency"] = lane_efficiency(work, prev, w, h)
+        out[f"{w}x{h}_{spec.n // 1000}k_{'mapping' if name == 'c2' else 'tracking'}"] = res
+    return out
+
+
 def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False, mask_prune=False):
     """Tracking at 640x480 with 100k Gaussians: the map frozen, the camera
     starting 2 cm / 1 degree off the pose its target frame was rendered
@@ -607,6 +680,10 @@ def main():
             mapping_step(R2, params2, view2, rc2, opt2, tc2, td2)
         R2.cap = R.cap
         variant = as_written_variant(R2, params2, view2, rc2, opt2, tc2, td2)
+    balance = None
+    if not args.no_variant:
+        log("lanes assigned by previous work")
+        balance = lane_balance_run()
     tracking = tracking_reuse = tracking_prune = None
     if not args.no_tracking:
         log("tracking 640x480 / 100k")
@@ -666,6 +743,7 @@ def main():
         "work": cnt,
         "host_wall_ms_per_step": 1000.0 * wall_ms,
         "as_written": variant,
+        "lane_balance": balance,
         "tracking": tracking,
         "tracking_reuse_lists": tracking_reuse,
         "tracking_mask_prune": tracking_prune,

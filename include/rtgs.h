@@ -70,6 +70,15 @@ extern "C" {
                                      sized with this flag (2 KB more per pair
                                      of capacity: room for every lane of a
                                      wave blending every list entry)          */
+#define RTGS_FWD_BALANCE_LANES 32 /* assign each wave's 64 lanes the samples
+                                     of similar work (the workload scheduling
+                                     unit of Sec. 5.2): a tile's samples are
+                                     sorted by the list entries each walked in
+                                     a previous forward (session lane_work),
+                                     waves take 64 consecutive ranks and cull
+                                     against their samples' bounding box;
+                                     writes this forward's walked entries to
+                                     lane_work_out; render_fwd_batched only   */
 
 /* ---- render_bwd flags ---- */
 #define RTGS_GRAD_POSE        1   /* write g_pose6 and/or g_viewmat            */
@@ -84,6 +93,7 @@ extern "C" {
                                      list entries no pixel of a wave blended;
                                      the gradients are bitwise those without
                                      the flag                                 */
+#define RTGS_GRAD_BALANCED_LANES 64 /* the forward used RTGS_FWD_BALANCE_LANES */
 #define RTGS_GRAD_SCORE      16   /* without RTGS_GRAD_MAP: write g_means and
                                      g_cov3d only, the inputs of the
                                      importance score of Sec. 4.1 (the raster
@@ -167,6 +177,12 @@ typedef struct {
   float* g_pose6;              /* [6] (rho, phi) */
   float* g_viewmat;            /* [12] dL/d(viewmat entries), row-major 3x4 */
   float* g_cov3d;              /* [n][6] (xx, xy, xz, yy, yz, zz) */
+  /* lane scheduling (RTGS_FWD_BALANCE_LANES; ignored without it) */
+  const uint16_t* lane_work;   /* [H][W] lane_work_out of an earlier forward of
+                                  this frame geometry, or NULL (then samples
+                                  keep their index order, rows of 4 per wave) */
+  uint16_t* lane_work_out;     /* [H][W] list entries each sample walked (at
+                                  its block's first pixel), or NULL          */
 } rtgs_session;
 
 /* Last error message of the calling thread (static storage, never NULL). */

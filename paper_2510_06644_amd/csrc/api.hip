@@ -149,6 +149,7 @@ WsLayout make_layout(const Counts& c, int64_t cap, bool frags) {
   L.partial = take(4 * 10 * (uint64_t)cap);
   L.state_t = take(4 * (uint64_t)c.px_total);
   L.state_last = take(4 * (uint64_t)c.px_total);
+  L.lane_perm = take(256 * t);
   if (frags) {
     L.fmask = take(8 * 4 * (uint64_t)cap);
     L.fcount = take(4 * 4 * t);
@@ -186,6 +187,7 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.partial = reinterpret_cast<float*>(base + L.partial);
   w.state_t = reinterpret_cast<float*>(base + L.state_t);
   w.state_last = reinterpret_cast<int32_t*>(base + L.state_last);
+  w.lane_perm = reinterpret_cast<uint8_t*>(base + L.lane_perm);
   if (L.fdata) {
     w.fmask = reinterpret_cast<unsigned long long*>(base + L.fmask);
     w.fcount = reinterpret_cast<uint32_t*>(base + L.fcount);
@@ -312,6 +314,8 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
       d.last_idx = (flags & RTGS_FWD_SAVE_STATE) ? s.last_idx : nullptr;
       d.visible = s.visible;
       d.stats = (flags & RTGS_FWD_STATS) ? s.stats : nullptr;
+      d.lane_work = (flags & RTGS_FWD_BALANCE_LANES) ? s.lane_work : nullptr;
+      d.lane_work_out = (flags & RTGS_FWD_BALANCE_LANES) ? s.lane_work_out : nullptr;
     } else {
       if (flags & RTGS_GRAD_RECOMPUTE_STATE) {
         d.final_T = w.state_t + pbase;
@@ -480,7 +484,7 @@ int32_t rtgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t pa
 int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
   if (flags & ~(RTGS_FWD_SAVE_STATE | RTGS_FWD_STATS | RTGS_FWD_REUSE_LISTS |
-                RTGS_FWD_SAVE_FRAGMENTS))
+                RTGS_FWD_SAVE_FRAGMENTS | RTGS_FWD_BALANCE_LANES))
     return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d (sample_log2 goes in the sessions)",
                 flags);
   const bool frags = (flags & RTGS_FWD_SAVE_FRAGMENTS) != 0;
@@ -503,7 +507,8 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   hipError_t e = launch_forward_prep(B, w, h->d_scalars, (flags & RTGS_FWD_REUSE_LISTS) != 0,
                                      st, tm);
   if (e == hipSuccess)
-    e = launch_raster_fwd(B, w, (flags & RTGS_FWD_STATS) != 0, frags, st, tm);
+    e = launch_raster_fwd(B, w, (flags & RTGS_FWD_STATS) != 0, frags,
+                          (flags & RTGS_FWD_BALANCE_LANES) != 0, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_fwd launch");
   h->last_stream = st;
   h->used = true;
@@ -513,13 +518,17 @@ int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
 int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, void* ws,
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
   const int32_t known = RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_COV3D |
-                        RTGS_GRAD_RECOMPUTE_STATE | RTGS_GRAD_SCORE | RTGS_GRAD_SAVED_FRAGMENTS;
+                        RTGS_GRAD_RECOMPUTE_STATE | RTGS_GRAD_SCORE | RTGS_GRAD_SAVED_FRAGMENTS |
+                        RTGS_GRAD_BALANCED_LANES;
   if (flags & ~known) return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
   if (!(flags & (RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_SCORE)))
     return fail(RTGS_ERR_INVALID_ARG, "render_bwd needs RTGS_GRAD_POSE, MAP or SCORE");
   const bool frags = (flags & RTGS_GRAD_SAVED_FRAGMENTS) != 0;
   if (frags && (flags & RTGS_GRAD_RECOMPUTE_STATE))
     return fail(RTGS_ERR_INVALID_ARG, "saved fragments come with saved state, not recompute");
+  const bool bal = (flags & RTGS_GRAD_BALANCED_LANES) != 0;
+  if (bal && (flags & RTGS_GRAD_RECOMPUTE_STATE))
+    return fail(RTGS_ERR_INVALID_ARG, "balanced lanes come with saved state, not recompute");
   WsLayout L;
   WsPtrs w;
   int32_t r = prepare(h, ss, ns, ws, ws_bytes, cap, L, w, frags);
@@ -532,11 +541,12 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
   if (r) return r;
   StageTimer* tm = h->timer.mask ? &h->timer : nullptr;
   hipError_t e = hipSuccess;
-  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, false, false, st, tm);
+  if (flags & RTGS_GRAD_RECOMPUTE_STATE) e = launch_raster_fwd(B, w, false, false, false, st, tm);
   bool alpha_grad = false;            // some session passes dL/dA
   for (int i = 0; i < ns; ++i) alpha_grad = alpha_grad || ss[i].dL_dalpha != nullptr;
   if (e == hipSuccess)
-    e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, alpha_grad, frags, st, tm);
+    e = launch_raster_bwd(B, w, (flags & RTGS_GRAD_MAP) ? 0 : 1, alpha_grad, frags, bal, st,
+                          tm);
   if (e == hipSuccess) e = launch_preprocess_bwd(B, w, flags, st, tm);
   if (e != hipSuccess) return hip_fail(e, "render_bwd launch");
   h->last_stream = st;

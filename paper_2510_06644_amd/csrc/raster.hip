@@ -51,15 +51,22 @@ struct TileCtx {
   unsigned wbit;
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile) {
+// The sample a thread takes by default: wave w the 8x8 quadrant w.
+__device__ __forceinline__ int quadrant_sample() {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  return ((wave >> 1) * 8 + (lane >> 3)) * 16 + (wave & 1) * 8 + (lane & 7);
+}
+
+// sidx: the thread's sample of the tile, row-major 0..255.
+__device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile, int sidx) {
   TileCtx c;
   c.s = find_session(B.sess, B.n_sessions, tile, [](const SessionDev& x) { return x.tile_base; });
   const SessionDev& S = session_of(B, c.s);
   c.lt = tile - S.tile_base;
   c.tile_x0 = (c.lt % S.tiles_x) << (4 + S.sub_sx);
   c.tile_y0 = (c.lt / S.tiles_x) << (4 + S.sub_sy);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int sx = (wave & 1) * 8 + (lane & 7), sy = (wave >> 1) * 8 + (lane >> 3);
+  const int wave = (int)threadIdx.x >> 6;
+  const int sx = sidx & 15, sy = sidx >> 4;
   c.bx0 = c.tile_x0 + (sx << S.sub_sx);
   c.by0 = c.tile_y0 + (sy << S.sub_sy);
   c.inside = c.bx0 < S.width && c.by0 < S.height;
@@ -129,6 +136,27 @@ __device__ __forceinline__ unsigned quad_mask(float4 r0, float4 r1, float4 ex, i
   return m;
 }
 
+// The same test against four boxes of samples, (x0, y0, x1, y1) inclusive,
+// one per wave (the lanes of a wave assigned by previous work).
+__device__ __forceinline__ unsigned box_mask(float4 r0, float4 r1, float4 ex, int tx0, int ty0,
+                                             int sx, int sy, const int4* boxes) {
+  const float u = r0.x + r0.z, v = r0.y + r0.w;
+  const float t = ex.z * (1.f + 1e-3f) + 1e-3f;
+  const float ia = r1.x > 0.f ? 1.f / r1.x : 0.f, ic = r1.z > 0.f ? 1.f / r1.z : 0.f;
+  unsigned m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int4 bx = boxes[w];
+    const float qx0 = (float)(tx0 + (bx.x << sx)) + 0.5f - u;
+    const float qy0 = (float)(ty0 + (bx.y << sy)) + 0.5f - v;
+    const float qx1 = (float)(tx0 + ((bx.z + 1) << sx) - 1) + 0.5f - u;
+    const float qy1 = (float)(ty0 + ((bx.w + 1) << sy) - 1) + 0.5f - v;
+    const float q = box_min_quad(r1.x, r1.y, r1.z, ia, ic, qx0, qx1, qy0, qy1);
+    m |= (q <= t) ? (1u << w) : 0u;
+  }
+  return m;
+}
+
 // 64-bit ballot of "entry (base + lane) is in this wave's quadrant".
 __device__ __forceinline__ unsigned long long wave_entries(const unsigned* s_m, int base, int cnt,
                                                            unsigned wbit) {
@@ -152,16 +180,62 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long m) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Lanes assigned by previous work (the GPU form of the paper's workload
+// scheduling unit, Sec. 5.2): the tile's 256 samples sorted by the list
+// entries each walked in a previous forward (S.lane_work; ties and missing
+// values by sample index), wave w taking ranks 64 w to 64 w + 63, so each
+// wave's lanes finish together.  Each wave culls against the bounding box of
+// its samples.  Writes the permutation for the backward and the boxes to LDS.
+__device__ __forceinline__ int lane_schedule(const SessionDev& S, const WsPtrs& W, int tile,
+                                             int tile_x0, int tile_y0, uint32_t* s_key,
+                                             uint8_t* s_pix, int4* s_box) {
+  const int tid = threadIdx.x;
+  const int bx = tile_x0 + ((tid & 15) << S.sub_sx), by = tile_y0 + ((tid >> 4) << S.sub_sy);
+  uint32_t work = 0;
+  if (S.lane_work && bx < S.width && by < S.height) work = S.lane_work[by * S.width + bx];
+  const uint32_t key = (work << 8) | (uint32_t)tid;
+  s_key[tid] = key;
+  __syncthreads();
+  int rank = 0;
+  for (int j = 0; j < kBlock; ++j) rank += s_key[j] < key ? 1 : 0;
+  s_pix[rank] = (uint8_t)tid;
+  __syncthreads();
+  const int sidx = s_pix[tid];
+  W.lane_perm[(int64_t)tile * kBlock + tid] = (uint8_t)sidx;
+  int x0 = sidx & 15, x1 = x0, y0 = sidx >> 4, y1 = y0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    x0 = min(x0, __shfl_xor(x0, off));
+    x1 = max(x1, __shfl_xor(x1, off));
+    y0 = min(y0, __shfl_xor(y0, off));
+    y1 = max(y1, __shfl_xor(y1, off));
+  }
+  if ((tid & 63) == 0) s_box[tid >> 6] = make_int4(x0, y0, x1, y1);
+  __syncthreads();
+  return sidx;
+}
+
 // STATS: also count, per pixel, the fragments blended and the list entries
 // visited (the work counts of a frame); off in ordinary renders.
 // FRAG: also save the fragments' alpha (see frag_base).
-template <bool STATS, bool FRAG>
+// BAL: lanes assigned by previous work (lane_schedule); also writes each
+// sample's walked entries to S.lane_work_out for the next forward.
+template <bool STATS, bool FRAG, bool BAL>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock];
   __shared__ unsigned s_m[kBlock];
+  __shared__ uint32_t s_key[BAL ? kBlock : 1];
+  __shared__ uint8_t s_pix[BAL ? kBlock : 1];
+  __shared__ int4 s_box[4];
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
-  const TileCtx c = tile_ctx(B, tile);
+  int sidx = quadrant_sample();
+  if (BAL) {
+    const TileCtx c0 = tile_ctx(B, tile, sidx);
+    sidx = lane_schedule(session_of(B, c0.s), W, tile, c0.tile_x0, c0.tile_y0, s_key, s_pix,
+                         s_box);
+  }
+  const TileCtx c = tile_ctx(B, tile, sidx);
   const SessionDev& S = session_of(B, c.s);
   const int tid = threadIdx.x;
   const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);
@@ -189,8 +263,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
       s_r0[tid] = r.pos;
       s_r1[tid] = conic_log2(r.conic);
       s_r2[tid] = r.col;
-      const unsigned qm = quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx,
-                                    S.sub_sy);
+      const unsigned qm = BAL ? box_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx,
+                                         S.sub_sy, s_box)
+                              : quad_mask(r.pos, r.conic, r.ext, c.tile_x0, c.tile_y0, S.sub_sx,
+                                          S.sub_sy);
       s_m[tid] = qm;
       W.qmask[e] = (uint8_t)qm;     // for the backward, which walks no entry unstaged here
     }
@@ -208,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         const bool hit = T > 0.f && !(f.alpha < kAlphaMin);
         const bool blend = hit && !(tn < kTMin);
         const bool stop_here = hit != blend;              // hit and T would fall below 1e-4
-        if (STATS) stop = stop_here ? b0 + k : stop;
+        if (STATS || BAL) stop = stop_here ? b0 + k : stop;
         const float w = blend ? f.alpha * T : 0.f;       // adds exactly 0 otherwise
         const float4 col = s_r2[k];
         C0 = __builtin_fmaf(w, col.x, C0);
@@ -244,6 +320,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   if (FRAG && flane == 0) W.fcount[(int64_t)tile * 4 + fwave] = fcur;
   T = fabsf(T);
   if (!c.inside) return;
+  if (BAL && S.lane_work_out) {
+    const int walked = active ? min(stop + 1, end) - start : 0;
+    S.lane_work_out[c.by0 * S.width + c.bx0] = (uint16_t)min(walked, 65535);
+  }
   const int64_t hw = (int64_t)S.width * S.height;
   // every pixel of the lane's block: the sample gets its result, the others
   // (masked out) render as background
@@ -294,7 +374,9 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 // and entries no lane of the wave blended are skipped without arithmetic; the
 // values are those the forward computed, so the gradients are bitwise those
 // of the re-evaluating form.
-template <int NV, bool GA, bool FRAG>
+// BAL: the forward assigned lanes by previous work (lane_schedule); the same
+// samples go to the same lanes here (the saved quadrant bits are per wave).
+template <int NV, bool GA, bool FRAG, bool BAL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
@@ -309,7 +391,8 @@ void k_raster_bwd(Batch B, WsPtrs W) {
   __shared__ int s_hi;
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
-  const TileCtx c = tile_ctx(B, tile);
+  const int sidx = BAL ? (int)W.lane_perm[(int64_t)tile * kBlock + threadIdx.x] : quadrant_sample();
+  const TileCtx c = tile_ctx(B, tile, sidx);
   const SessionDev& S = session_of(B, c.s);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ltx = c.lt % S.tiles_x, lty = c.lt / S.tiles_x;
@@ -529,49 +612,65 @@ void k_raster_bwd(Batch B, WsPtrs W) {
 
 }  // namespace
 
-hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, bool frags,
+template <bool STATS>
+static void raster_fwd_variant(const Batch& b, const WsPtrs& w, bool frags, bool bal, int grid,
+                               hipStream_t st) {
+  if (frags) {
+    if (bal)
+      k_raster_fwd<STATS, true, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_fwd<STATS, true, false><<<grid, kBlock, 0, st>>>(b, w);
+  } else {
+    if (bal)
+      k_raster_fwd<STATS, false, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_fwd<STATS, false, false><<<grid, kBlock, 0, st>>>(b, w);
+  }
+}
+
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, bool frags, bool bal,
                              hipStream_t st, StageTimer* tm) {
   if (b.t_total <= 0) return hipSuccess;
   const int grid = 8 * ((b.t_total + 7) / 8);
   Scope sc(tm, kStRasterFwd, st);
-  if (stats) {
-    if (frags)
-      k_raster_fwd<true, true><<<grid, kBlock, 0, st>>>(b, w);
-    else
-      k_raster_fwd<true, false><<<grid, kBlock, 0, st>>>(b, w);
-  } else {
-    if (frags)
-      k_raster_fwd<false, true><<<grid, kBlock, 0, st>>>(b, w);
-    else
-      k_raster_fwd<false, false><<<grid, kBlock, 0, st>>>(b, w);
-  }
+  if (stats)
+    raster_fwd_variant<true>(b, w, frags, bal, grid, st);
+  else
+    raster_fwd_variant<false>(b, w, frags, bal, grid, st);
   return hipGetLastError();
 }
 
 template <int NV, bool GA>
-static void raster_bwd_frag(const Batch& b, const WsPtrs& w, bool frags, int grid,
-                            hipStream_t st) {
-  if (frags)
-    k_raster_bwd<NV, GA, true><<<grid, kBlock, 0, st>>>(b, w);
-  else
-    k_raster_bwd<NV, GA, false><<<grid, kBlock, 0, st>>>(b, w);
+static void raster_bwd_variant(const Batch& b, const WsPtrs& w, bool frags, bool bal, int grid,
+                               hipStream_t st) {
+  if (frags) {
+    if (bal)
+      k_raster_bwd<NV, GA, true, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_bwd<NV, GA, true, false><<<grid, kBlock, 0, st>>>(b, w);
+  } else {
+    if (bal)
+      k_raster_bwd<NV, GA, false, true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_raster_bwd<NV, GA, false, false><<<grid, kBlock, 0, st>>>(b, w);
+  }
 }
 
 hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, bool alpha_grad,
-                             bool frags, hipStream_t st, StageTimer* tm) {
+                             bool frags, bool bal, hipStream_t st, StageTimer* tm) {
   if (b.t_total <= 0) return hipGetLastError();
   const int grid = 8 * ((b.t_total + 7) / 8);
   Scope sc(tm, kStRasterBwd, st);
   if (pose_only) {
     if (alpha_grad)
-      raster_bwd_frag<6, true>(b, w, frags, grid, st);
+      raster_bwd_variant<6, true>(b, w, frags, bal, grid, st);
     else
-      raster_bwd_frag<6, false>(b, w, frags, grid, st);
+      raster_bwd_variant<6, false>(b, w, frags, bal, grid, st);
   } else {
     if (alpha_grad)
-      raster_bwd_frag<10, true>(b, w, frags, grid, st);
+      raster_bwd_variant<10, true>(b, w, frags, bal, grid, st);
     else
-      raster_bwd_frag<10, false>(b, w, frags, grid, st);
+      raster_bwd_variant<10, false>(b, w, frags, bal, grid, st);
   }
   return hipGetLastError();
 }

@@ -40,6 +40,8 @@ struct SessionDev {
   int32_t* last_idx;
   uint8_t* visible;
   int32_t* stats;       // [3][H][W] or null: blended, entries visited, entries to last
+  const uint16_t* lane_work;  // [H][W] entries walked per sample in a previous forward, or null
+  uint16_t* lane_work_out;    // [H][W] this forward's, or null
   // backward
   const float* dl_color;
   const float* dl_depth;
@@ -92,6 +94,7 @@ struct WsLayout {
   uint64_t partial;     // float[cap][10]: per (tile, Gaussian) merged 2D gradient
   uint64_t state_t;     // float[pixels]: recomputed final T
   uint64_t state_last;  // int32[pixels]: recomputed last position
+  uint64_t lane_perm;   // uint8[T][256]: sample of each lane (lanes assigned by previous work)
   // saved fragments (workspace sized with RTGS_FWD_SAVE_FRAGMENTS, else absent)
   uint64_t fmask;       // uint64[4 cap]: blend mask of each (list entry, wave)
   uint64_t fcount;      // uint32[4 T]: saved fragments of each (tile, wave)
@@ -143,6 +146,7 @@ struct WsPtrs {
   float* partial;
   float* state_t;
   int32_t* state_last;
+  uint8_t* lane_perm;
   unsigned long long* fmask;   // null without saved fragments
   uint32_t* fcount;
   float2* fdata;
@@ -192,10 +196,10 @@ struct Scope {
 // ---- launch wrappers (defined in the .hip files) ----
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
                                bool reuse_lists, hipStream_t st, StageTimer* tm);
-hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, bool frags,
+hipError_t launch_raster_fwd(const Batch& b, const WsPtrs& w, bool stats, bool frags, bool bal,
                              hipStream_t st, StageTimer* tm);
 hipError_t launch_raster_bwd(const Batch& b, const WsPtrs& w, int pose_only, bool alpha_grad,
-                             bool frags, hipStream_t st, StageTimer* tm);
+                             bool frags, bool bal, hipStream_t st, StageTimer* tm);
 hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st,
                                  StageTimer* tm);
 hipError_t launch_prune(const float* g_means, const float* g_cov3d, const uint8_t* visible,

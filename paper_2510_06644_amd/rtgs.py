@@ -32,6 +32,7 @@ RTGS_FWD_SAVE_STATE = 1
 RTGS_FWD_STATS = 2
 RTGS_FWD_REUSE_LISTS = 4
 RTGS_FWD_SAVE_FRAGMENTS = 16
+RTGS_FWD_BALANCE_LANES = 32
 RTGS_PROFILE_STAGES = 16
 STAGES = ("init", "preprocess", "scan", "emit", "sort", "raster_fwd", "adam", "raster_bwd",
           "preprocess_bwd", "pose_reduce", "bin_count", "merge")
@@ -41,6 +42,7 @@ RTGS_GRAD_COV3D = 4
 RTGS_GRAD_RECOMPUTE_STATE = 8
 RTGS_GRAD_SCORE = 16
 RTGS_GRAD_SAVED_FRAGMENTS = 32
+RTGS_GRAD_BALANCED_LANES = 64
 RTGS_STATE_IDLE = 0
 RTGS_STATE_EXECUTING = 1
 RTGS_MAX_SESSIONS = 64
@@ -89,7 +91,7 @@ class CSession(ctypes.Structure):
                 ("visible", vp), ("stats", vp), ("dL_dcolor", vp), ("dL_ddepth", vp), ("dL_dalpha", vp),
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
                 ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_viewmat", vp),
-                ("g_cov3d", vp)]
+                ("g_cov3d", vp), ("lane_work", vp), ("lane_work_out", vp)]
 
 
 class CPoseItem(ctypes.Structure):
@@ -308,7 +310,8 @@ def session_struct(it):
     for name in ("pixel_mask", "color", "depth", "alpha", "final_T", "last_idx", "visible",
                  "stats",
                  "dL_dcolor", "dL_ddepth", "dL_dalpha", "g_means", "g_log_scales", "g_quats",
-                 "g_opacity_logits", "g_colors", "g_pose6", "g_viewmat", "g_cov3d"):
+                 "g_opacity_logits", "g_colors", "g_pose6", "g_viewmat", "g_cov3d",
+                 "lane_work", "lane_work_out"):
         setattr(s, name, _p(it.get(name)))
     return s
 
@@ -627,7 +630,7 @@ class Renderer:
     # ------------------------------------------------------------------ managed calls
     def forward(self, scene, viewmat, cam: Cam, gauss_mask=None, pixel_mask=None,
                 save_state=True, stream=None, sample_log2=0, reuse_lists_of=None,
-                save_fragments=False):
+                save_fragments=False, balance=False, lane_work=None, lane_work_out=None):
         """Render one frame; returns a FwdState (outputs + the workspace the
         matching backward needs).  Each forward gets its own workspace from
         torch's caching allocator, so several forwards may await backward.
@@ -639,7 +642,12 @@ class Renderer:
 
         save_fragments: also save every blended fragment's alpha (the
         backward then reads it instead of re-evaluating Eq. 2); the workspace
-        grows by 2 KB per pair of capacity."""
+        grows by 2 KB per pair of capacity.
+
+        balance: assign each wave's lanes the samples of similar previous work
+        (lane_work, uint16 [H, W], the lane_work_out of an earlier balanced
+        forward of this geometry, or None) and write this forward's work to
+        lane_work_out (or None)."""
         n = scene[0].shape[0]
         if save_fragments and (not save_state or reuse_lists_of is not None):
             raise ValueError("save_fragments needs save_state and a full forward")
@@ -679,11 +687,22 @@ class Renderer:
                            last_idx=(torch.empty(h, w, dtype=torch.int32, device=dev)
                                      if save_state else None),
                            visible=torch.empty(n, dtype=torch.uint8, device=dev))
-            render_fwd(self.handle, *scene, viewmat, cam, ws, cap, out.color, out.depth,
-                       out.alpha, out.final_T, out.last_idx, out.visible, gauss_mask=gauss_mask,
-                       pixel_mask=pixel_mask,
-                       flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | fflag
-                       | (int(sample_log2) << RTGS_SAMPLE_SHIFT), stream=stream)
+            if balance:
+                out.balanced = True
+                render_fwd_batched(self.handle, [dict(
+                    scene=scene, viewmat=viewmat, cam=cam, gauss_mask=gauss_mask,
+                    pixel_mask=pixel_mask, sample_log2=sample_log2, color=out.color,
+                    depth=out.depth, alpha=out.alpha, final_T=out.final_T,
+                    last_idx=out.last_idx, visible=out.visible, lane_work=lane_work,
+                    lane_work_out=lane_work_out)], ws, cap,
+                    flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | fflag
+                    | RTGS_FWD_BALANCE_LANES, stream=stream)
+            else:
+                render_fwd(self.handle, *scene, viewmat, cam, ws, cap, out.color, out.depth,
+                           out.alpha, out.final_T, out.last_idx, out.visible,
+                           gauss_mask=gauss_mask, pixel_mask=pixel_mask,
+                           flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | fflag
+                           | (int(sample_log2) << RTGS_SAMPLE_SHIFT), stream=stream)
             self.cap = max(self.cap, cap)
             if self.check != "every":
                 return out
@@ -709,6 +728,8 @@ class Renderer:
             flags |= RTGS_GRAD_RECOMPUTE_STATE
         if st.frags:
             flags |= RTGS_GRAD_SAVED_FRAGMENTS
+        if st.balanced:
+            flags |= RTGS_GRAD_BALANCED_LANES
         flags |= int(st.sample_log2) << RTGS_SAMPLE_SHIFT
         g = {}
         if map_grads:
@@ -749,6 +770,7 @@ class FwdState:
     sample_log2: int = 0
     pairs: int = -1
     frags: bool = False
+    balanced: bool = False
 
     def stage(self):
         """Forward intermediates for tests: dict of numpy arrays."""
