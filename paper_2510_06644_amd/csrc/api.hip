@@ -144,6 +144,7 @@ WsLayout make_layout(const Counts& c, int64_t cap, bool frags) {
   L.tile_start = take(4 * (t + 1));
   L.big_tiles = take(4 * (t + 1));
   L.keys = take(8 * (uint64_t)cap);
+  L.keys_tm = take(8 * (uint64_t)cap);
   L.ids = take(4 * (uint64_t)cap);
   L.qmask = take((uint64_t)cap);
   L.partial = take(4 * 10 * (uint64_t)cap);
@@ -182,6 +183,7 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.tile_start = reinterpret_cast<uint32_t*>(base + L.tile_start);
   w.big_tiles = reinterpret_cast<uint32_t*>(base + L.big_tiles);
   w.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
+  w.keys_tm = reinterpret_cast<unsigned long long*>(base + L.keys_tm);
   w.ids = reinterpret_cast<uint32_t*>(base + L.ids);
   w.qmask = reinterpret_cast<uint8_t*>(base + L.qmask);
   w.partial = reinterpret_cast<float*>(base + L.partial);

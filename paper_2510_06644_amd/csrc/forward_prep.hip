@@ -8,18 +8,20 @@
 //    pixel-space centres split as hi + lo float32 parts, so their float32
 //    compositing matches the float64 definition far below 1e-4;
 //  * binning is a counting sort by tile without global atomics (device-scope
-//    atomics cross the XCDs and serialise): each workgroup takes a chunk of
+//    atomics cross the XCDs and serialise).  Each workgroup takes a chunk of
 //    1024 Gaussians and counts its (tile, Gaussian) pairs per tile in an LDS
-//    histogram; a column scan over chunks turns the counts into per
-//    (chunk, tile) offsets; a second pass over the chunk scatters
-//    (depth bits, id) keys through LDS-atomic cursors.  The same pass writes
-//    each Gaussian's first slot in Gaussian-major pair order, which the
-//    backward uses to merge gradients without atomics.  Then one workgroup
-//    per tile sorts its range in LDS (merge sort of 64-bit keys; long ranges
-//    go to a second kernel with 1024 threads, and ranges beyond its LDS
-//    capacity sort in place in global memory).  No host sync:
-//    the pair total stays on the device and a capacity overflow only drops
-//    pairs.
+//    histogram.  Column sums over the chunks give each tile's list length and
+//    start.  A second pass over the chunk orders its pairs by tile in LDS
+//    and writes them as one contiguous block (chunk-major: every store is
+//    coalesced, where scattering 8-byte keys into the tile ranges made the
+//    memory system merge millions of partial lines).  One workgroup per tile
+//    then gathers the tile's run from every chunk and sorts it in LDS (merge
+//    sort of 64-bit keys; long lists are gathered to global memory and go to
+//    a second kernel with 1024 threads, sorting in place beyond its LDS).
+//    The same pass writes each Gaussian's first slot in Gaussian-major pair
+//    order, which the backward uses to merge gradients without atomics.  No
+//    host sync: the pair total stays on the device, and a capacity overflow
+//    publishes empty tile lists (every list entry is always a real pair).
 #include "rtgs_internal.h"
 
 namespace rtgs {
@@ -279,10 +281,8 @@ __global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   if (threadIdx.x == 0) W.chunk_total[blockIdx.x] = total;
 }
 
-// Column scan of the per-(chunk, tile) counts, in two passes with one thread
-// per (tile, group of chunks): group sums, then each group's exclusive prefix
-// written back in place.  The group of the last chunks also writes the tile's
-// pair count.
+// Column sums of the per-(chunk, tile) counts, one thread per (tile, group
+// of chunks); k_scan_tiles adds the groups.
 constexpr int kScanGroups = 16;
 
 __device__ __forceinline__ void tile_groups(const SessionDev& S, int g, int& c0, int& c1) {
@@ -307,28 +307,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_group_sums(Batch B, WsPtrs W) {
 #pragma unroll 8
   for (int c = c0; c < c1; ++c) sum += h[(int64_t)c * ts];
   W.gsum[(int64_t)g * B.t_total + t] = sum;
-}
-
-__global__ __launch_bounds__(kBlock) void k_tile_group_scan(Batch B, WsPtrs W) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  const int g = blockIdx.y;
-  if (t >= B.t_total) return;
-  const int s = find_session(B.sess, B.n_sessions, t,
-                             [](const SessionDev& x) { return x.tile_base; });
-  const SessionDev& S = session_of(B, s);
-  const int ts = S.tiles_x * S.tiles_y;
-  uint32_t run = 0;
-  for (int q = 0; q < g; ++q) run += W.gsum[(int64_t)q * B.t_total + t];
-  if (g == kScanGroups - 1) W.tile_count[t] = run + W.gsum[(int64_t)g * B.t_total + t];
-  int c0, c1;
-  tile_groups(S, g, c0, c1);
-  uint32_t* h = W.hist + S.hist_base + (t - S.tile_base);
-#pragma unroll 8
-  for (int c = c0; c < c1; ++c) {
-    const uint32_t v = h[(int64_t)c * ts];
-    h[(int64_t)c * ts] = run;
-    run += v;
-  }
 }
 
 // Exclusive scan of n values in[0..n) into out[0..n]; out[n] = total.  Each
@@ -365,13 +343,25 @@ __device__ uint32_t block_scan_1024(const uint32_t* in, uint32_t* out, int n, ui
   return total;
 }
 
-// Tile ranges (scan of the per-tile counts), chunk offsets (scan of the
-// per-chunk totals), and the pair total.
+// Tile ranges (scan of the per-tile counts, each the sum of its chunk
+// groups), chunk offsets (scan of the per-chunk totals), and the pair total.
+// When the pairs exceed the capacity every tile list is published empty (the
+// call's output is invalid and reported, and no list holds a pair that was
+// not stored).
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_total, int c_total,
                                                              unsigned long long* max_pairs) {
   __shared__ uint32_t part[kScanThreads / 64];
+  for (int t = threadIdx.x; t < t_total; t += kScanThreads) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int g = 0; g < kScanGroups; ++g) sum += W.gsum[(int64_t)g * t_total + t];
+    W.tile_count[t] = sum;
+  }
+  __syncthreads();
   const uint32_t total = block_scan_1024(W.tile_count, W.tile_start, t_total, part);
   block_scan_1024(W.chunk_total, W.chunk_off, c_total, part);
+  if ((int64_t)total > W.cap)
+    for (int t = threadIdx.x; t <= t_total; t += kScanThreads) W.tile_start[t] = 0u;
   if (threadIdx.x == 0) {
     W.counters[0] = (long long)total;
     // [0]: largest pair count of any call; [1]: largest count of a call whose
@@ -381,11 +371,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_tot
   }
 }
 
-// Per chunk: each Gaussian's first Gaussian-major slot, then
-// (depth bits << 32 | id) keys scattered into the tile ranges through LDS
-// cursors, pairs dealt evenly over the threads.
+// Per chunk: each Gaussian's first Gaussian-major slot; the chunk's pairs
+// ordered by tile, written as one block at chunk_off (chunk-major layout;
+// inside it, tile t's run starts at the exclusive scan of the chunk's tile
+// counts, which replaces the counts in this chunk's histogram row for the
+// sort's gather).  The pairs are staged in LDS as 16-bit local indices and
+// written with coalesced stores; a chunk with more than kStagePairs pairs
+// writes them directly inside its block.
+constexpr int kStagePairs = 12288;
+
 __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
-  extern __shared__ uint32_t s_cur[];
+  extern __shared__ uint32_t s_dyn[];       // [ts] tile cursors, then [kStagePairs] uint16
   __shared__ uint32_t s_off[kChunk + 1];
   __shared__ int4 s_rect[kChunk];
   __shared__ uint32_t s_zb[kChunk];
@@ -395,9 +391,38 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   const SessionDev& S = session_of(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
-  const uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
-  for (int t = threadIdx.x; t < ts; t += kBinThreads)
-    s_cur[t] = W.tile_start[S.tile_base + t] + h[t];
+  uint32_t* s_cur = s_dyn;
+  uint16_t* s_loc = reinterpret_cast<uint16_t*>(s_dyn + ts);
+  uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
+  // exclusive scan of the chunk's tile counts: each thread a contiguous run of
+  // tiles, the run sums scanned across the waves
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = (ts + kBinThreads - 1) / kBinThreads;
+    const int beg = min((int)threadIdx.x * per, ts), end = min(beg + per, ts);
+    uint32_t sum = 0;
+    for (int t = beg; t < end; ++t) {
+      const uint32_t v = h[t];
+      s_cur[t] = v;
+      sum += v;
+    }
+    uint32_t x = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t run = x - sum;
+    for (int q = 0; q < wave; ++q) run += s_wave[q];
+    for (int t = beg; t < end; ++t) {
+      const uint32_t v = s_cur[t];
+      s_cur[t] = run;
+      h[t] = run;
+      run += v;
+    }
+    __syncthreads();                        // s_wave is reused below
+  }
   stage_rects(S, W, c, s_rect);
   for (int i = threadIdx.x; i < kChunk; i += kBinThreads) {
     const int li = c * kChunk + i;
@@ -410,17 +435,23 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
     const int li = c * kChunk + i;
     if (li < S.n) W.goff[S.gauss_base + li] = base + s_off[i];
   }
-  int cur_i = -1;
-  unsigned long long key = 0;
+  const uint32_t g0 = S.gauss_base + c * kChunk;
+  const bool staged = total <= kStagePairs;
   chunk_pairs(S, s_rect, c, s_off, total, [&](int i, int tile) {
-    if (i != cur_i) {
-      const int gid = S.gauss_base + c * kChunk + i;
-      key = ((unsigned long long)s_zb[i] << 32) | (unsigned)gid;
-      cur_i = i;
-    }
     const uint32_t pos = atomicAdd(&s_cur[tile], 1u);
-    if ((int64_t)pos < W.cap) W.keys[pos] = key;
+    if (staged)
+      s_loc[pos] = (uint16_t)i;
+    else if ((int64_t)base + pos < W.cap)
+      W.keys[base + pos] = ((unsigned long long)s_zb[i] << 32) | (g0 + i);
   });
+  if (staged) {
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < total; k += kBinThreads) {
+      const uint32_t i = s_loc[k];
+      if ((int64_t)base + k < W.cap)
+        W.keys[base + k] = ((unsigned long long)s_zb[i] << 32) | (g0 + i);
+    }
+  }
 }
 
 // Bitonic sorting network on a[0..n) (ascending), all merges in the "flip"
@@ -581,30 +612,124 @@ __device__ void merge_runs_to_ids(const unsigned long long* A, int na,
   }
 }
 
-// One workgroup per tile: lists of up to 1024 keys are sorted here; longer
-// ones are queued for k_sort_big_tiles.
-__global__ __launch_bounds__(kBlock) void k_sort_tiles(WsPtrs W) {
+// The tile's list is the concatenation of its run in every chunk of its
+// session (chunk-major keys, run offsets in the chunks' histogram rows).
+// First each run's source and place in the list (a thread per chunk, a block
+// scan of the run lengths, both kept in LDS for up to kGatherChunks chunks);
+// then the n keys dealt evenly over the threads, each finding the run of its
+// first key by binary search and issuing its loads together.  Sessions with
+// more chunks copy run by run.
+constexpr int kGatherChunks = 1020;    // s_at and s_src fit in one sort buffer
+
+__device__ void gather_tile(const WsPtrs& W, const SessionDev& S, int lt, int n,
+                            unsigned long long* dst, uint32_t* s_part, uint32_t* s_at,
+                            uint32_t* s_src) {
+  const int ts = S.tiles_x * S.tiles_y;
+  const int nc = (S.n + kChunk - 1) / kChunk;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool spread = nc <= kGatherChunks;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nc; c0 += kBlock) {
+    const int c = c0 + (int)threadIdx.x;
+    uint32_t cnt = 0, src = 0;
+    if (c < nc) {
+      const uint32_t* row = W.hist + S.hist_base + (int64_t)c * ts;
+      const uint32_t off = row[lt];
+      const uint32_t nxt = lt + 1 < ts ? row[lt + 1] : W.chunk_total[S.chunk_base + c];
+      cnt = nxt - off;
+      src = W.chunk_off[S.chunk_base + c] + off;
+    }
+    uint32_t x = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_part[wave] = x;
+    __syncthreads();
+    uint32_t at = carry + x - cnt, tot = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      at += q < wave ? s_part[q] : 0u;
+      tot += s_part[q];
+    }
+    if (spread) {
+      if (c < nc) {
+        s_at[c] = at;
+        s_src[c] = src;
+      }
+    } else {
+      for (uint32_t j = 0; j < cnt; ++j) dst[at + j] = W.keys[src + j];
+    }
+    carry += tot;
+    __syncthreads();                        // s_part is reused
+  }
+  if (!spread) return;
+  if (threadIdx.x == 0) s_at[nc] = (uint32_t)n;
+  __syncthreads();
+  const int per = (n + kBlock - 1) / kBlock;
+  const int p0 = min((int)threadIdx.x * per, n), p1 = min(p0 + per, n);
+  if (p0 >= p1) return;
+  int lo = 0, hi = nc - 1;                  // last run with s_at <= p0
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_at[mid] <= (uint32_t)p0) lo = mid; else hi = mid - 1;
+  }
+  int c = lo;
+  for (int q0 = p0; q0 < p1; q0 += 4) {
+    unsigned long long k[4];
+    int qn = min(4, p1 - q0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < qn) {
+        const uint32_t p = (uint32_t)(q0 + j);
+        while (p >= s_at[c + 1]) ++c;       // runs are contiguous in the list
+        k[j] = W.keys[s_src[c] + (p - s_at[c])];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < qn) dst[q0 + j] = k[j];
+  }
+}
+
+// One workgroup per tile (neighbouring tiles on one XCD, whose L2 then holds
+// the chunk rows and runs they share): lists of up to 1024 keys are gathered
+// to LDS and sorted here; longer ones are gathered to the tile-major buffer
+// and queued for k_sort_big_tiles.
+__global__ __launch_bounds__(kBlock) void k_sort_tiles(Batch B, WsPtrs W) {
   __shared__ unsigned long long b0[kSortPerThread * kBlock], b1[kSortPerThread * kBlock];
-  const int t = blockIdx.x;
-  const int64_t cap = W.cap;
-  const int64_t st = min((int64_t)W.tile_start[t], cap);
-  const int64_t en = min((int64_t)W.tile_start[t + 1], cap);
-  const int n = (int)(en - st);
+  __shared__ uint32_t s_part[kBlock / 64];
+  // the gather's run table lives in b0, which the merge sort fills only after
+  // it has read the gathered keys from b1
+  static_assert(2 * kGatherChunks + 1 <= 2 * kSortPerThread * kBlock, "run table fits b0");
+  uint32_t* s_at = reinterpret_cast<uint32_t*>(b0);
+  uint32_t* s_src = s_at + kGatherChunks + 1;
+  const int per = (B.t_total + 7) >> 3;
+  const int t = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+  if (t >= B.t_total) return;
+  const uint32_t st = W.tile_start[t];
+  const int n = (int)(W.tile_start[t + 1] - st);   // all empty after an overflow
   if (n <= 0) return;
+  const int s = find_session(B.sess, B.n_sessions, t,
+                             [](const SessionDev& x) { return x.tile_base; });
+  const SessionDev& S = session_of(B, s);
   if (n > kSortPerThread * kBlock) {
+    gather_tile(W, S, t - S.tile_base, n, W.keys_tm + st, s_part, s_at, s_src);
     if (threadIdx.x == 0) {
       const unsigned long long q = atomicAdd((unsigned long long*)&W.counters[2], 1ull);
       W.big_tiles[q] = (uint32_t)t;
     }
     return;
   }
-  merge_sort_tile<kBlock, kSortPerThread>(W.keys + st, W.ids + st, n, b0, b1);
+  gather_tile(W, S, t - S.tile_base, n, b1, s_part, s_at, s_src);
+  __syncthreads();
+  merge_sort_tile<kBlock, kSortPerThread>(b1, W.ids + st, n, b0, b1);
 }
 
-// Queued long lists: up to 4096 keys by the LDS merge sort with 1024
-// threads; up to 8192 as two such sorts of halves written back as keys, then
-// one merge of the halves from global memory; longer ones by the bitonic
-// network in place in global memory.  One launch whatever the lengths.
+// Queued long lists (gathered to the tile-major buffer): up to 4096 keys by
+// the LDS merge sort with 1024 threads; up to 8192 as two such sorts of
+// halves written back as keys, then one merge of the halves from global
+// memory; longer ones by the bitonic network in place in global memory.  One
+// launch whatever the lengths.
 constexpr int kBigThreads = 1024;
 constexpr int kBigKeys = kSortPerThread * kBigThreads;
 __global__ __launch_bounds__(kBigThreads) void k_sort_big_tiles(WsPtrs W) {
@@ -612,10 +737,9 @@ __global__ __launch_bounds__(kBigThreads) void k_sort_big_tiles(WsPtrs W) {
   const long long count = W.counters[2];
   for (long long q = blockIdx.x; q < count; q += gridDim.x) {
     const int t = (int)W.big_tiles[q];
-    const int64_t st = min((int64_t)W.tile_start[t], W.cap);
-    const int64_t en = min((int64_t)W.tile_start[t + 1], W.cap);
-    const int n = (int)(en - st);
-    unsigned long long* g = W.keys + st;
+    const int64_t st = W.tile_start[t];
+    const int n = (int)(W.tile_start[t + 1] - st);
+    unsigned long long* g = W.keys_tm + st;
     if (n <= kBigKeys) {
       merge_sort_tile<kBigThreads, kSortPerThread>(g, W.ids + st, n, b0, b1);
     } else if (n <= 2 * kBigKeys) {
@@ -651,8 +775,8 @@ __global__ void k_debug_stage(Batch B, WsPtrs W, float* stage, int* rect, int* r
     }
   }
   if (i < B.t_total && ranges) {
-    ranges[2 * i] = (int)min((int64_t)W.tile_start[i], W.cap);
-    ranges[2 * i + 1] = (int)min((int64_t)W.tile_start[i + 1], W.cap);
+    ranges[2 * i] = (int)W.tile_start[i];
+    ranges[2 * i + 1] = (int)W.tile_start[i + 1];
   }
   if (ids) {
     const int64_t total = min((int64_t)W.tile_start[B.t_total], min(W.cap, ids_cap));
@@ -708,16 +832,15 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
     Scope sc(tm, kStScan, st);
     const dim3 grid((b.t_total + kBlock - 1) / kBlock, kScanGroups);
     k_tile_group_sums<<<grid, kBlock, 0, st>>>(b, w);
-    k_tile_group_scan<<<grid, kBlock, 0, st>>>(b, w);
     k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, b.c_total, max_pairs);
   }
   if (b.c_total > 0) {
     Scope sc(tm, kStEmit, st);
-    k_emit<<<b.c_total, kBinThreads, lds, st>>>(b, w);
+    k_emit<<<b.c_total, kBinThreads, lds + sizeof(uint16_t) * kStagePairs, st>>>(b, w);
   }
   if (b.t_total > 0) {
     Scope sc(tm, kStSort, st);
-    k_sort_tiles<<<b.t_total, kBlock, 0, st>>>(w);
+    k_sort_tiles<<<8 * ((b.t_total + 7) / 8), kBlock, 0, st>>>(b, w);
     k_sort_big_tiles<<<b.t_total < 512 ? b.t_total : 512, kBigThreads, 0, st>>>(w);
   }
   return hipGetLastError();

@@ -83,12 +83,14 @@ struct WsLayout {
   uint64_t pose_part;   // double[B][16]: per-block view-matrix gradient partial sums
   uint64_t chunk_total; // uint32[C + 1]: pairs per chunk
   uint64_t chunk_off;   // uint32[C + 1]: exclusive scan of chunk_total
-  uint64_t hist;        // uint32[sum_s C_s T_s]: per (chunk, tile) counts, then offsets
+  uint64_t hist;        // uint32[sum_s C_s T_s]: per (chunk, tile) counts, then each
+                        // chunk's exclusive scan over its tiles (run offsets in the chunk)
   uint64_t gsum;        // uint32[16][T]: per (group of chunks, tile) sums
   uint64_t tile_count;  // uint32[T + 1]
   uint64_t tile_start;  // uint32[T + 1]
   uint64_t big_tiles;   // uint32[T]: tiles whose list is too long for the one-pass sort
-  uint64_t keys;        // uint64[cap]
+  uint64_t keys;        // uint64[cap]: (depth bits << 32 | id), chunk-major
+  uint64_t keys_tm;     // uint64[cap]: the long lists gathered tile-major for their sort
   uint64_t ids;         // uint32[cap]
   uint64_t qmask;       // uint8[cap]: quadrants of its tile each list entry can reach
   uint64_t partial;     // float[cap][10]: per (tile, Gaussian) merged 2D gradient
@@ -141,6 +143,7 @@ struct WsPtrs {
   uint32_t* tile_start;
   uint32_t* big_tiles;
   unsigned long long* keys;
+  unsigned long long* keys_tm;
   uint32_t* ids;
   uint8_t* qmask;
   float* partial;
