@@ -4,8 +4,9 @@
 Headline: mapping iterations per second at 1200x680 with 300,000 Gaussians
 (scales log-normal(-4.5, 0.7), 20% near-transparent), full resolution, no
 pruning.  One step = render_fwd + L1 colour / 0.5 L1 depth loss + render_bwd
-to every Gaussian parameter + an Adam update of the map, i.e. one mapping
-iteration of the SLAM back end; inputs are resident in HBM.
+to every Gaussian parameter + an Adam update of the map (applied inside the
+backward's per-Gaussian pass, bitwise the update of a separate Adam kernel),
+i.e. one mapping iteration of the SLAM back end; inputs are resident in HBM.
 
 Also reported on the same line: the roofline of the dominant kernel (timed
 with HIP events on its own stream inside the timed region), a per-stage
@@ -83,8 +84,10 @@ def counter_record():
 # parameters in, the 64 B raster record, tile rectangle and count out (152 B);
 # the per-chunk histogram reads rectangle and count (20 B); emit 12 B and sort
 # 12 B per pair (key written and read, id written); merge 40 B per pair slot
-# read and 40 B per Gaussian written; preprocessing backward 176 B per
-# Gaussian; Adam 28 B for each of 14 parameters per Gaussian.  Kernel names
+# read and 40 B per Gaussian written; the preprocessing backward with the map's
+# Adam update fused 392 B per Gaussian (rectangle 16 and merged 2D gradient 40
+# read, 14 parameters read and written with both Adam moments, 24 B each);
+# a separate Adam 28 B for each of 14 parameters per Gaussian.  Kernel names
 # per stage as the profiler lists them.
 HBM_STAGES = {
     "preprocess": (lambda n, p: 152 * n, ("k_preprocess",)),
@@ -92,7 +95,7 @@ HBM_STAGES = {
     "emit": (lambda n, p: 12 * p, ("k_emit",)),
     "sort": (lambda n, p: 12 * p, ("k_sort_tiles", "k_sort_big_tiles")),
     "merge": (lambda n, p: 40 * p + 40 * n, ("k_merge",)),
-    "preprocess_bwd": (lambda n, p: 176 * n, ("k_preprocess_bwd",)),
+    "preprocess_bwd": (lambda n, p: 392 * n, ("k_gauss_bwd",)),
     "adam": (lambda n, p: 392 * n, ("k_adam",)),
 }
 VALU_STAGES = {"raster_fwd": ("k_raster_fwd",), "raster_bwd": ("k_raster_bwd",)}
@@ -148,8 +151,9 @@ def per_kernel(stages_ms, cnt, n, rec):
 # 1024 SIMDs x 16 lanes x 2.4 GHz.  Per-unit counts: forward 12 VALU + 1 exp
 # per list entry visited and 10 per blend; backward 12 + 1 exp per entry up to
 # the last blend and 55 + 1 rcp per blended fragment; bytes 152 (projection)
-# + 176 (its backward) + 392 (Adam, 14 parameters) + 40 (merged 2D gradient)
-# per Gaussian, 12 (emit) + 24 (sort) + 40 (merge) per pair, 48 (loss) per pixel.
+# + 40 (merged 2D gradient written) + 392 (its backward with the fused Adam
+# update) per Gaussian, 12 (emit) + 24 (sort) + 40 (merge) per pair, 48 (loss)
+# per pixel.
 SLOT_RATE = 1024 * 16 * 2.4e9
 HBM_BYTES_PER_S = 8e12
 
@@ -158,7 +162,7 @@ def path_roofline(cnt, ms_per_step, bwd_ms, fwd_ms, spec):
     fwd_us = (12 * cnt["visited"] + 10 * cnt["blended"] + 3 * cnt["visited"]) / SLOT_RATE * 1e6
     bwd_us = (12 * cnt["visited_to_last"] + 55 * cnt["blended"]
               + 3 * (cnt["visited_to_last"] + cnt["blended"])) / SLOT_RATE * 1e6
-    hbm_bytes = (760 * spec.n + 76 * cnt["pairs"] + 48 * spec.width * spec.height)
+    hbm_bytes = (584 * spec.n + 76 * cnt["pairs"] + 48 * spec.width * spec.height)
     hbm_us = hbm_bytes / HBM_BYTES_PER_S * 1e6
     t_roof = fwd_us + bwd_us + hbm_us
     return {"model": "sum over stages of max(bytes / 8 TB/s, (VALU ops + 3 per exp or rcp) "
@@ -214,11 +218,19 @@ def l1_grads(color, depth, tc, td, pixel_mask=None, n_active=None):
 
 
 def mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=None, pixel_mask=None,
-                 cov3d=False, sample_log2=0, n_active=None):
+                 cov3d=False, sample_log2=0, n_active=None, fused=True):
+    """One mapping iteration.  The Adam update runs inside the backward's
+    per-Gaussian pass (bitwise the update of a separate adam_step); an
+    iteration whose gradients are wanted (cov3d: the inputs of gradient
+    pruning) takes the backward and the optimizer apart."""
     scene = tuple(p.detach() for p in params)
     st = R.forward(scene, view, rc, gauss_mask=gauss_mask, pixel_mask=pixel_mask,
                    sample_log2=sample_log2)
     gc, gd = l1_grads(st.color, st.depth, tc, td, pixel_mask, n_active)
+    if fused and not cov3d:
+        g = R.backward(scene, view, rc, st, gc, gd, pose=False, gauss_mask=gauss_mask,
+                       pixel_mask=pixel_mask, adam=opt)
+        return st, g
     g = R.backward(scene, view, rc, st, gc, gd, pose=False, map_grads=True, cov3d=cov3d,
                    gauss_mask=gauss_mask, pixel_mask=pixel_mask)
     opt.step(R.handle, [g[k] for k in ("means", "log_scales", "quats", "opacity_logits",
@@ -728,7 +740,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "width": cam.width, "height": cam.height,
                    "gaussians": spec.n, "step": "render_fwd + L1 loss + render_bwd (all map "
-                   "parameters) + Adam", "pixels": "full resolution", "prune": False},
+                   "parameters) + Adam (fused into the backward)", "pixels": "full resolution", "prune": False},
         "roofline": roof,
         "path_roofline": path_roofline(cnt, ms, bwd_ms, fwd_ms, spec),
         "raster_fwd_roofline": {"bound": "alu", "avg_ms": fwd_ms,

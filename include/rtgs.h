@@ -94,6 +94,13 @@ extern "C" {
                                      the gradients are bitwise those without
                                      the flag                                 */
 #define RTGS_GRAD_BALANCED_LANES 64 /* the forward used RTGS_FWD_BALANCE_LANES */
+#define RTGS_GRAD_ADAM      128   /* with RTGS_GRAD_MAP, render_bwd_batched
+                                     only: after each Gaussian's gradients,
+                                     apply its session's Adam update
+                                     (rtgs_session.adam) to its parameters in
+                                     place, in the same pass (Sec. 3.1: the
+                                     mapping update); the five gradient
+                                     outputs may then be NULL                 */
 #define RTGS_GRAD_SCORE      16   /* without RTGS_GRAD_MAP: write g_means and
                                      g_cov3d only, the inputs of the
                                      importance score of Sec. 4.1 (the raster
@@ -146,6 +153,24 @@ typedef struct {
   const float* viewmat;  /* device, 12 floats, row-major [R | t] */
 } rtgs_camera;
 
+/* Adam state of one session's map for RTGS_GRAD_ADAM (a HOST struct; the
+ * arrays are device arrays of the parameters' shapes, updated in place).
+ * Index order: means, log_scales, quats, opacity_logits, colors.  The update
+ * is adam_step's, element for element and bitwise, on the float32 gradients
+ * render_bwd would write: with t = step,
+ *   m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2,
+ *   p <- p - (lr / (1 - beta1^t)) m / (sqrt(v) / sqrt(1 - beta2^t) + eps),
+ * p being the session's map arrays (rtgs_gaussians), which the call writes.
+ * Errors (INVALID_ARG): null moment array with n > 0, step < 1, a beta
+ * outside [0, 1), eps < 0 or not finite, lr not finite. */
+typedef struct {
+  float* exp_avg[5];
+  float* exp_avg_sq[5];
+  float lr[5];
+  int32_t step;                /* >= 1: the count of this update */
+  double beta1, beta2, eps;
+} rtgs_map_adam;
+
 /* One session of a batched call: its own map, camera, masks, outputs and
  * gradients; same meaning as the arguments of render_fwd / render_bwd. */
 typedef struct {
@@ -183,6 +208,9 @@ typedef struct {
                                   keep their index order, rows of 4 per wave) */
   uint16_t* lane_work_out;     /* [H][W] list entries each sample walked (at
                                   its block's first pixel), or NULL          */
+  /* fused map update (RTGS_GRAD_ADAM; ignored without it) */
+  const rtgs_map_adam* adam;   /* HOST pointer, or NULL: no update of this
+                                  session's map                              */
 } rtgs_session;
 
 /* Last error message of the calling thread (static storage, never NULL). */
@@ -493,8 +521,8 @@ int32_t rtgs_debug_stage(const int32_t* n, const int32_t* width,
 
 /* Stage profiler (HIP events on the stream each kernel is launched on).
  * Stages: 0 init, 1 preprocess, 2 scan, 3 emit, 4 sort, 5 raster_fwd,
- * 6 adam, 7 raster_bwd, 8 preprocess_bwd, 9 pose_reduce, 10 bin_count,
- * 11 merge.  After
+ * 6 adam, 7 raster_bwd, 8 preprocess_bwd (with RTGS_GRAD_ADAM also the
+ * map's Adam update), 9 pose_reduce, 10 bin_count, 11 merge.  After
  * rtgs_profile_enable(h, mask) every launch of a stage whose bit is set is
  * bracketed by two events; rtgs_profile_read waits for them and returns per
  * stage the summed milliseconds and the launch count (HOST arrays of

@@ -257,9 +257,23 @@ int32_t check_session(const rtgs_session& s, int idx, bool fwd, int32_t flags) {
       return fail(RTGS_ERR_INVALID_ARG, "session %d: null dL/dcolor or dL/ddepth", idx);
     if (!(flags & RTGS_GRAD_RECOMPUTE_STATE) && (!s.final_T || !s.last_idx))
       return fail(RTGS_ERR_INVALID_ARG, "session %d: saved state missing", idx);
-    if ((flags & RTGS_GRAD_MAP) && g.n > 0 &&
+    if ((flags & RTGS_GRAD_MAP) && !(flags & RTGS_GRAD_ADAM) && g.n > 0 &&
         (!s.g_means || !s.g_log_scales || !s.g_quats || !s.g_opacity_logits || !s.g_colors))
       return fail(RTGS_ERR_INVALID_ARG, "session %d: null map gradient output", idx);
+    if ((flags & RTGS_GRAD_ADAM) && s.adam) {
+      const rtgs_map_adam& a = *s.adam;
+      for (int k = 0; k < 5; ++k) {
+        if (g.n > 0 && (!a.exp_avg[k] || !a.exp_avg_sq[k]))
+          return fail(RTGS_ERR_INVALID_ARG, "session %d: null Adam moment array", idx);
+        if (!std::isfinite(a.lr[k]))
+          return fail(RTGS_ERR_INVALID_ARG, "session %d: Adam lr not finite", idx);
+      }
+      if (a.step < 1) return fail(RTGS_ERR_INVALID_ARG, "session %d: Adam step < 1", idx);
+      if (!(a.beta1 >= 0.0 && a.beta1 < 1.0 && a.beta2 >= 0.0 && a.beta2 < 1.0))
+        return fail(RTGS_ERR_INVALID_ARG, "session %d: Adam betas outside [0, 1)", idx);
+      if (!(a.eps >= 0.0) || !std::isfinite(a.eps))
+        return fail(RTGS_ERR_INVALID_ARG, "session %d: Adam eps must be finite and >= 0", idx);
+    }
     if ((flags & RTGS_GRAD_POSE) && !s.g_pose6 && !s.g_viewmat)
       return fail(RTGS_ERR_INVALID_ARG, "session %d: POSE needs g_pose6 and/or g_viewmat", idx);
     if ((flags & RTGS_GRAD_COV3D) && (!(flags & RTGS_GRAD_MAP) || (g.n > 0 && !s.g_cov3d)))
@@ -339,6 +353,23 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
       } else if (flags & RTGS_GRAD_SCORE) {
         d.g_means = s.g_means;
         d.g_cov3d = s.g_cov3d;
+      }
+      if ((flags & RTGS_GRAD_ADAM) && s.adam) {
+        // the constants adam_step forms, so the two updates agree bitwise
+        const rtgs_map_adam& a = *s.adam;
+        MapAdamDev& m = d.adam;
+        for (int k = 0; k < 5; ++k) {
+          m.m[k] = a.exp_avg[k];
+          m.v[k] = a.exp_avg_sq[k];
+          m.step_size[k] = (float)((double)a.lr[k] / (1.0 - std::pow(a.beta1, (double)a.step)));
+        }
+        m.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(1.0 - std::pow(a.beta2, (double)a.step)));
+        m.beta1 = (float)a.beta1;
+        m.beta2 = (float)a.beta2;
+        m.omb1 = (float)(1.0 - a.beta1);
+        m.omb2 = (float)(1.0 - a.beta2);
+        m.eps = (float)a.eps;
+        m.on = 1;
       }
       d.g_pose6 = (flags & RTGS_GRAD_POSE) ? s.g_pose6 : nullptr;
       d.g_viewmat = (flags & RTGS_GRAD_POSE) ? s.g_viewmat : nullptr;
@@ -521,8 +552,10 @@ int32_t render_bwd_batched(rtgs_handle_t h, const rtgs_session* ss, int32_t ns, 
                            uint64_t ws_bytes, int64_t cap, int32_t flags, void* stream) {
   const int32_t known = RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_COV3D |
                         RTGS_GRAD_RECOMPUTE_STATE | RTGS_GRAD_SCORE | RTGS_GRAD_SAVED_FRAGMENTS |
-                        RTGS_GRAD_BALANCED_LANES;
+                        RTGS_GRAD_BALANCED_LANES | RTGS_GRAD_ADAM;
   if (flags & ~known) return fail(RTGS_ERR_INVALID_ARG, "unknown flags %d", flags);
+  if ((flags & RTGS_GRAD_ADAM) && !(flags & RTGS_GRAD_MAP))
+    return fail(RTGS_ERR_INVALID_ARG, "RTGS_GRAD_ADAM needs RTGS_GRAD_MAP");
   if (!(flags & (RTGS_GRAD_POSE | RTGS_GRAD_MAP | RTGS_GRAD_SCORE)))
     return fail(RTGS_ERR_INVALID_ARG, "render_bwd needs RTGS_GRAD_POSE, MAP or SCORE");
   const bool frags = (flags & RTGS_GRAD_SAVED_FRAGMENTS) != 0;

@@ -20,11 +20,7 @@ static_assert(sizeof(AdamArgs) <= 4000, "Adam launch table must fit the kernel a
 
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v,
                                          const AdamArgs& a, float step, float isb2) {
-  m = __builtin_fmaf(a.omb1, g, a.beta1 * m);
-  v = __builtin_fmaf(a.omb2, g * g, a.beta2 * v);
-  const float eps = a.eps;
-  const float denom = __builtin_fmaf(__builtin_sqrtf(v), isb2, eps);
-  p = p - step * (m / denom);
+  adam_update(p, g, m, v, a.beta1, a.beta2, a.omb1, a.omb2, a.eps, step, isb2);
 }
 
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {

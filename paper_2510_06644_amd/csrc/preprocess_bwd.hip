@@ -2,14 +2,21 @@
 // gradients merged by the raster backward are pushed through the EWA
 // projection to the map parameters, and in tracking summed over Gaussians to
 // the camera-pose gradient dL/dP (the paper's Preprocessing Engine and
-// Merging Tree, Secs. 5.1 and 5.4).
+// Merging Tree, Secs. 5.1 and 5.4).  In mapping the Adam update of the map
+// (Sec. 3.1) can follow in the same pass.
 //
-// One thread per Gaussian in float64 (HBM bound: 40 B of merged 2D gradient
-// per (tile, Gaussian) pair and 56 B of parameters in, up to 80 B out).  The
-// Gaussian's 2D gradient is the fixed-order sum of its pair slots (the
-// tile -> Gaussian merge, the role of the paper's Stage Buffer).  The pose partials are summed per
-// workgroup in LDS, then per session in a fixed order by a second kernel, so
-// the pose reduction adds no float atomics of its own.
+// Two kernels.  The tile -> Gaussian merge (the role of the paper's Stage
+// Buffer): each Gaussian's 2D gradient is the fixed-order sum of its
+// (tile, Gaussian) pair slots, 40 B each; a streaming kernel at full
+// occupancy.  Then one thread per Gaussian in float64 through the
+// projection (56 B of parameters and 40 B of merged gradient in), writing
+// the gradients (56 B) or, fused, applying Adam to the Gaussian's 14
+// parameters right away (parameters and both moments read and written,
+// 280 B), so the gradients never go through memory.  That kernel needs many
+// float64 registers, hence few waves: the merge stays apart, where
+// occupancy hides its loads.  The pose partials are summed per workgroup in
+// LDS, then per session in a fixed order by a third kernel, so the pose
+// reduction adds no float atomics of its own.
 //
 // Chain (all derivatives exact for the forward of forward_prep.hip):
 //   conic (a, b, c) -> Sigma' :  dL/dSigma' = -M G_M M,  G_M = [[ga, gb/2],
@@ -135,12 +142,15 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
   }
 }
 
-__global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPtrs W, int flags) {
+template <int NV, bool ADAM>
+__global__ __launch_bounds__(kGaussPerBlock) void k_gauss_bwd(Batch B, WsPtrs W, int flags) {
   __shared__ double s_red[kGaussPerBlock / 64][12];
   const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
                              [](const SessionDev& x) { return x.block_base; });
   const SessionDev& S = session_of(B, s);
-  const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
+  const int li0 = ((int)blockIdx.x - S.block_base) * kGaussPerBlock;
+  // ---- projection backward, one thread per Gaussian
+  const int li = li0 + (int)threadIdx.x;
   const bool want_map = (flags & RTGS_GRAD_MAP) != 0;
   const bool want_cov = (flags & RTGS_GRAD_COV3D) != 0 && S.g_cov3d != nullptr;
   // score inputs only (dL/dmu, dL/dSigma) on the pose-only raster path
@@ -153,9 +163,11 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
     double gm[3] = {0, 0, 0}, gl[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go_eta = 0;
     double gcol[3] = {0, 0, 0}, gsig[6] = {0, 0, 0, 0, 0, 0};
     if (rect.z >= rect.x) {
+      // the merged 2D gradient: (u, v, a, b, c, o, r, g, b, z), or with the
+      // pose-only merge (u, v, a, b, c, z)
       float g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       const float* m = W.grad2d + (int64_t)gid * 10;
-      if (flags & RTGS_GRAD_MAP) {
+      if (NV == 10) {
         for (int i = 0; i < 10; ++i) g2[i] = m[i];
       } else {
         for (int i = 0; i < 5; ++i) g2[i] = m[i];
@@ -301,6 +313,34 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess_bwd(Batch B, WsPt
       for (int k = 0; k < 3; ++k) S.g_means[3 * li + k] = (float)gm[k];
       for (int k = 0; k < 6; ++k) S.g_cov3d[6 * li + k] = (float)gsig[k];
     }
+    // ---- Adam on the Gaussian's parameters (the update of adam_step, on
+    // the same float32 gradients)
+    if (ADAM && S.adam.on) {
+      const MapAdamDev& A = S.adam;
+      const float g14[14] = {(float)gm[0], (float)gm[1], (float)gm[2], (float)gl[0],
+                             (float)gl[1], (float)gl[2], (float)gq[0], (float)gq[1],
+                             (float)gq[2], (float)gq[3], (float)go_eta, (float)gcol[0],
+                             (float)gcol[1], (float)gcol[2]};
+      float* const par[5] = {const_cast<float*>(S.means), const_cast<float*>(S.log_scales),
+                             const_cast<float*>(S.quats), const_cast<float*>(S.opac),
+                             const_cast<float*>(S.colors)};
+      constexpr int kDim[5] = {3, 3, 4, 1, 3};
+      int at = 0;
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+#pragma unroll
+        for (int k = 0; k < kDim[t]; ++k) {
+          const int64_t e = (int64_t)kDim[t] * li + k;
+          float pv = par[t][e], mv = A.m[t][e], vv = A.v[t][e];
+          adam_update(pv, g14[at + k], mv, vv, A.beta1, A.beta2, A.omb1, A.omb2, A.eps,
+                      A.step_size[t], A.inv_sqrt_bc2);
+          par[t][e] = pv;
+          A.m[t][e] = mv;
+          A.v[t][e] = vv;
+        }
+        at += kDim[t];
+      }
+    }
   }
   // block partial of the pose gradient: wave shuffles, then the 4 waves in LDS
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -375,7 +415,12 @@ hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags
   }
   if (b.b_total > 0) {
     Scope sc(tm, kStPreprocessBwd, st);
-    k_preprocess_bwd<<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+    if (grad_flags & RTGS_GRAD_ADAM)
+      k_gauss_bwd<10, true><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+    else if (grad_flags & RTGS_GRAD_MAP)
+      k_gauss_bwd<10, false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+    else
+      k_gauss_bwd<6, false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
   }
   if ((grad_flags & RTGS_GRAD_POSE) && b.n_sessions > 0) {
     Scope sc(tm, kStPoseReduce, st);

@@ -21,6 +21,17 @@ constexpr double kFovClamp = 1.3;
 constexpr int kChunk = 1024;              // Gaussians per binning chunk (4 per thread)
 constexpr int kMaxTilesPerSession = 12288; // LDS tile histogram of one session (48 KB)
 
+// Adam state of a session's map for an update fused into the backward
+// (constants formed on the host as adam_step forms them).
+struct MapAdamDev {
+  float* m[5];            // first moments: means, log_scales, quats, opacity, colours
+  float* v[5];            // second moments
+  float step_size[5];     // lr / (1 - beta1^t)
+  float inv_sqrt_bc2;     // 1 / sqrt(1 - beta2^t)
+  float beta1, beta2, omb1, omb2, eps;
+  int32_t on;
+};
+
 // Device copy of one session (built on the host from rtgs_session).
 struct SessionDev {
   // map
@@ -54,6 +65,7 @@ struct SessionDev {
   float* g_pose6;
   float* g_viewmat;
   float* g_cov3d;
+  MapAdamDev adam;      // RTGS_GRAD_ADAM: the map's update after its gradients
   // geometry
   int32_t n;
   int32_t width;
@@ -414,6 +426,18 @@ __device__ __forceinline__ int wave_scatter_index(int nv, int row, int s) {
   if (2 * s + 1 < h) return (row >> 1) * h + (row & 1) + 2 * s;
   if (2 * s < h) return (row & 1) ? (row >> 1) * h + 2 * s : -1;
   return -1;
+}
+
+// One Adam element update (t the step count after it):
+//   m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2,
+//   p <- p - (lr / (1 - beta1^t)) m / (sqrt(v) / sqrt(1 - beta2^t) + eps).
+__device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, float beta1,
+                                            float beta2, float omb1, float omb2, float eps,
+                                            float step, float isb2) {
+  m = __builtin_fmaf(omb1, g, beta1 * m);
+  v = __builtin_fmaf(omb2, g * g, beta2 * v);
+  const float denom = __builtin_fmaf(__builtin_sqrtf(v), isb2, eps);
+  p = p - step * (m / denom);
 }
 
 // Activations of Eq. 1's parameters (scales exp(l), opacity sigmoid(eta)),

@@ -40,6 +40,20 @@ class MapAdam:
     def step(self, handle, grads, stream=None):
         step_many(handle, [(self, grads)], stream)
 
+    def fused(self):
+        """The C state of the next update (step t + 1) for a backward that
+        applies it in the same pass (RTGS_GRAD_ADAM); the caller advances t
+        once that backward is enqueued."""
+        a = rtgs.CMapAdam()
+        for k in range(5):
+            a.exp_avg[k] = self.exp_avg[k].data_ptr()
+            a.exp_avg_sq[k] = self.exp_avg_sq[k].data_ptr()
+            a.lr[k] = self.lrs[k]
+        a.step = self.t + 1
+        a.beta1, a.beta2 = self.betas
+        a.eps = self.eps
+        return a
+
     def to(self, device):
         """Move the moments (the parameters are the caller's) to `device`."""
         self.exp_avg = [m.to(device) for m in self.exp_avg]

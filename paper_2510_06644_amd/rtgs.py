@@ -43,6 +43,7 @@ RTGS_GRAD_RECOMPUTE_STATE = 8
 RTGS_GRAD_SCORE = 16
 RTGS_GRAD_SAVED_FRAGMENTS = 32
 RTGS_GRAD_BALANCED_LANES = 64
+RTGS_GRAD_ADAM = 128
 RTGS_STATE_IDLE = 0
 RTGS_STATE_EXECUTING = 1
 RTGS_MAX_SESSIONS = 64
@@ -85,13 +86,19 @@ class CCamera(ctypes.Structure):
                 ("cy", f32), ("viewmat", vp)]
 
 
+class CMapAdam(ctypes.Structure):
+    _fields_ = [("exp_avg", vp * 5), ("exp_avg_sq", vp * 5), ("lr", f32 * 5), ("step", i32),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
 class CSession(ctypes.Structure):
     _fields_ = [("g", CGaussians), ("cam", CCamera), ("pixel_mask", vp), ("sample_log2", i32),
                 ("color", vp), ("depth", vp), ("alpha", vp), ("final_T", vp), ("last_idx", vp),
                 ("visible", vp), ("stats", vp), ("dL_dcolor", vp), ("dL_ddepth", vp), ("dL_dalpha", vp),
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
                 ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_viewmat", vp),
-                ("g_cov3d", vp), ("lane_work", vp), ("lane_work_out", vp)]
+                ("g_cov3d", vp), ("lane_work", vp), ("lane_work_out", vp),
+                ("adam", ctypes.POINTER(CMapAdam))]
 
 
 class CPoseItem(ctypes.Structure):
@@ -301,8 +308,9 @@ def render_bwd(handle, means, log_scales, quats, opacity_logits, colors, viewmat
 def session_struct(it):
     """One CSession from a dict with the keys of CSession (tensors or None)
     plus 'scene' (means, log_scales, quats, opacity_logits, colors),
-    'viewmat', 'cam' (Cam), optional 'gauss_mask' and 'sample_log2'.  The
-    struct holds raw device pointers: the tensors must outlive its use."""
+    'viewmat', 'cam' (Cam), optional 'gauss_mask', 'sample_log2' and 'adam'
+    (a CMapAdam, e.g. MapAdam.fused()).  The struct holds raw pointers: the
+    tensors and the CMapAdam must outlive its use."""
     s = CSession()
     s.g = _gauss(*it["scene"], it.get("gauss_mask"))
     s.cam = _cam(it["cam"], it["viewmat"])
@@ -313,6 +321,8 @@ def session_struct(it):
                  "g_opacity_logits", "g_colors", "g_pose6", "g_viewmat", "g_cov3d",
                  "lane_work", "lane_work_out"):
         setattr(s, name, _p(it.get(name)))
+    if it.get("adam") is not None:
+        s.adam = ctypes.pointer(it["adam"])
     return s
 
 
@@ -716,7 +726,13 @@ class Renderer:
     def backward(self, scene, viewmat, cam: Cam, st: "FwdState", dL_dcolor, dL_ddepth,
                  dL_dalpha=None, pose=True, map_grads=True, cov3d=False, score=False,
                  gauss_mask=None,
-                 pixel_mask=None, stream=None):
+                 pixel_mask=None, stream=None, adam=None):
+        """Gradients of the last forward.  With adam (a MapAdam over the
+        scene tensors) the map is updated in the same pass instead of
+        returning its gradients (RTGS_GRAD_ADAM), and adam's step advances."""
+        if adam is not None:
+            return self._backward_adam(scene, viewmat, cam, st, dL_dcolor, dL_ddepth, dL_dalpha,
+                                       pose, cov3d, gauss_mask, pixel_mask, stream, adam)
         n = st.n
         dev = scene[0].device
         flags = (RTGS_GRAD_POSE if pose else 0) | (RTGS_GRAD_MAP if map_grads else 0)
@@ -752,6 +768,40 @@ class Renderer:
                    g.get("means"), g.get("log_scales"), g.get("quats"), g.get("opacity_logits"),
                    g.get("colors"), g.get("pose"), g.get("cov3d"), gauss_mask=gauss_mask,
                    pixel_mask=pixel_mask, stream=stream, g_viewmat=g.get("viewmat"))
+        return g
+
+    def _backward_adam(self, scene, viewmat, cam, st, dL_dcolor, dL_ddepth, dL_dalpha, pose,
+                       cov3d, gauss_mask, pixel_mask, stream, adam):
+        for p, q in zip(adam.params, scene):
+            if p.data_ptr() != q.data_ptr():
+                raise ValueError("adam must hold the scene tensors being rendered")
+        n = st.n
+        dev = scene[0].device
+        flags = RTGS_GRAD_MAP | RTGS_GRAD_ADAM | (RTGS_GRAD_POSE if pose else 0)
+        flags |= RTGS_GRAD_COV3D if cov3d else 0
+        if st.final_T is None:
+            flags |= RTGS_GRAD_RECOMPUTE_STATE
+        if st.frags:
+            flags |= RTGS_GRAD_SAVED_FRAGMENTS
+        if st.balanced:
+            flags |= RTGS_GRAD_BALANCED_LANES
+        g = {}
+        if cov3d:
+            g["cov3d"] = torch.empty(n, 6, device=dev)
+        if pose:
+            g["pose"] = torch.empty(6, device=dev)
+            g["viewmat"] = torch.empty(3, 4, device=dev)
+        state = adam.fused()
+        item = dict(scene=scene, viewmat=viewmat, cam=cam, gauss_mask=gauss_mask,
+                    pixel_mask=pixel_mask, sample_log2=st.sample_log2, final_T=st.final_T,
+                    last_idx=st.last_idx, dL_dcolor=dL_dcolor.contiguous(),
+                    dL_ddepth=dL_ddepth.contiguous(),
+                    dL_dalpha=None if dL_dalpha is None else dL_dalpha.contiguous(),
+                    g_pose6=g.get("pose"), g_viewmat=g.get("viewmat"), g_cov3d=g.get("cov3d"),
+                    adam=state)
+        arr, _keep = make_sessions([item])
+        render_bwd_batched_c(self.handle, arr, 1, st.ws, st.cap, flags, _stream(stream))
+        adam.t += 1
         return g
 
 

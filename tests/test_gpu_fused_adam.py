@@ -1,0 +1,117 @@
+"""The mapping update fused into the backward (RTGS_GRAD_ADAM): the same
+parameters and Adam moments, bitwise, as render_bwd followed by adam_step,
+over several iterations, with a pixel mask, with the pose gradient asked for
+in the same call, and for a frame whose Gaussians touch many tiles (the
+merge's whole-workgroup path)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2510_06644_amd import optim, rtgs, synth
+from tests.gpu_util import dev_scene, eye_view, rcam, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _l1(R, color, depth, tc, td, mask=None, n_active=None):
+    gc = torch.empty_like(color)
+    gd = torch.empty_like(depth)
+    rtgs.loss_l1_grad(color, depth, tc, td, gc, gd, pixel_mask=mask, n_active=n_active)
+    return gc, gd
+
+
+def _run_pair(sc, cam, iters, pose, mask):
+    R = rtgs.Renderer(0)
+    view = torch.from_numpy(eye_view()).cuda()
+    rc = rcam(cam)
+    target = dev_scene(synth.perturb_scene(sc, 77))
+    st = R.forward(target, view, rc)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    tc = st.color + 0.01 * torch.randn(st.color.shape, generator=g, device="cuda")
+    td = st.depth + 0.01 * torch.randn(st.depth.shape, generator=g, device="cuda")
+    n_active = None
+    if mask is not None:
+        n_active = torch.tensor([int(mask.sum().item())], dtype=torch.int32, device="cuda")
+    sep = [p.clone() for p in dev_scene(sc)]
+    fus = [p.clone() for p in dev_scene(sc)]
+    opt_s, opt_f = optim.MapAdam(sep), optim.MapAdam(fus)
+    for it in range(iters):
+        st_s = R.forward(tuple(sep), view, rc, pixel_mask=mask)
+        gc, gd = _l1(R, st_s.color, st_s.depth, tc, td, mask, n_active)
+        gs = R.backward(tuple(sep), view, rc, st_s, gc, gd, pose=pose, pixel_mask=mask)
+        opt_s.step(R.handle, [gs[k] for k in ("means", "log_scales", "quats", "opacity_logits",
+                                             "colors")])
+        st_f = R.forward(tuple(fus), view, rc, pixel_mask=mask)
+        gc, gd = _l1(R, st_f.color, st_f.depth, tc, td, mask, n_active)
+        gf = R.backward(tuple(fus), view, rc, st_f, gc, gd, pose=pose, pixel_mask=mask,
+                        adam=opt_f)
+        torch.cuda.synchronize()
+        assert opt_f.t == opt_s.t == it + 1
+        for k, (a, b) in enumerate(zip(sep, fus)):
+            assert torch.equal(a, b), f"iteration {it}: parameter {k}"
+            assert torch.equal(opt_s.exp_avg[k], opt_f.exp_avg[k]), f"iteration {it}: m {k}"
+            assert torch.equal(opt_s.exp_avg_sq[k], opt_f.exp_avg_sq[k]), f"iteration {it}: v {k}"
+        if pose:
+            assert torch.equal(gs["pose"], gf["pose"])
+            assert torch.equal(gs["viewmat"], gf["viewmat"])
+        say(f"  iteration {it}: bitwise equal")
+
+
+@pytest.mark.parametrize("pose,masked", [(False, False), (True, False), (False, True)])
+def test_fused_adam_equals_backward_then_adam_step(pose, masked):
+    say(f"test_fused_adam_equals_backward_then_adam_step pose={pose} masked={masked}")
+    spec = synth.CONFIGS["c0"]
+    cam = synth.make_camera(spec.width, spec.height)
+    sc = synth.make_scene(spec, cam)
+    mask = None
+    if masked:
+        rng = np.random.default_rng(3)
+        mask = torch.from_numpy((rng.random((cam.height, cam.width)) < 0.5).astype(np.uint8)).cuda()
+    _run_pair(sc, cam, 3, pose, mask)
+
+
+def test_fused_adam_with_gaussians_over_many_tiles():
+    """Some Gaussians cover most of the frame (the merge sums them with the
+    whole workgroup); the fused update still equals the separate one."""
+    say("test_fused_adam_with_gaussians_over_many_tiles")
+    cam = synth.make_camera(320, 256)
+    rng = np.random.default_rng(22)
+    n = 600
+    z = rng.uniform(2.0, 6.0, n)
+    u = rng.uniform(0, 320, n)
+    v = rng.uniform(0, 256, n)
+    sig_px = rng.uniform(2.0, 6.0, n)
+    logit = rng.uniform(-1.0, 2.0, n)
+    big = np.r_[3, 9, 300]
+    u[big], v[big], sig_px[big], logit[big] = 160, 128, 90.0, -3.0
+    means = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z], 1)
+    log_s = np.log(sig_px * z / cam.fx)[:, None] + rng.uniform(-0.2, 0.2, (n, 3))
+    q = rng.normal(size=(n, 4))
+    sc = synth.Scene(means.astype(np.float32), log_s.astype(np.float32),
+                     (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32),
+                     logit.astype(np.float32), rng.random((n, 3)).astype(np.float32))
+    _run_pair(sc, cam, 2, False, None)
+
+
+def test_fused_adam_rejects_a_foreign_optimizer_and_needs_map_grads():
+    say("test_fused_adam_rejects_a_foreign_optimizer_and_needs_map_grads")
+    spec = synth.CONFIGS["c0"]
+    cam = synth.make_camera(spec.width, spec.height)
+    sc = synth.make_scene(spec, cam)
+    R = rtgs.Renderer(0)
+    view = torch.from_numpy(eye_view()).cuda()
+    scene = dev_scene(sc)
+    st = R.forward(scene, view, rcam(cam))
+    gc, gd = torch.ones_like(st.color), torch.ones_like(st.depth)
+    other = optim.MapAdam([p.clone() for p in scene])
+    with pytest.raises(ValueError):
+        R.backward(scene, view, rcam(cam), st, gc, gd, adam=other)
+    opt = optim.MapAdam(list(scene))
+    item = dict(scene=scene, viewmat=view, cam=rcam(cam), final_T=st.final_T,
+                last_idx=st.last_idx, dL_dcolor=gc, dL_ddepth=gd, adam=opt.fused())
+    arr, _keep = rtgs.make_sessions([item])
+    with pytest.raises(rtgs.RtgsError) as e:
+        rtgs.render_bwd_batched_c(R.handle, arr, 1, st.ws, st.cap,
+                                  rtgs.RTGS_GRAD_POSE | rtgs.RTGS_GRAD_ADAM,
+                                  rtgs.stream_ptr())
+    assert e.value.code == rtgs.RTGS_ERR_INVALID_ARG

@@ -308,6 +308,36 @@ def test_long_tile_lists_take_each_sort_path(renderer, n, span, lo, hi):
     assert rel_err(st.color.cpu().numpy(), ref.color.numpy(), keep) < IMG_TOL
 
 
+def test_chunk_with_more_pairs_than_the_emit_stages(renderer):
+    """Chunks of 1024 Gaussians that each cover about 30 tiles of an 8 x 8
+    tile frame hold about 30k pairs, more than the emit orders by tile in LDS
+    (12288), so they are written straight into their chunk-major block; the
+    lists still equal the definition (tile, then depth, then index)."""
+    say("test_chunk_with_more_pairs_than_the_emit_stages")
+    cam = synth.Camera(128, 128, 102.4, 102.4, 64.0, 64.0)
+    rng = np.random.default_rng(9)
+    n = 2500
+    z = rng.uniform(1, 3, n)
+    u = rng.uniform(20, 108, n)
+    v = rng.uniform(20, 108, n)
+    sig_px = rng.uniform(10.0, 14.0, n)
+    means = np.stack([(u - 64) * z / 102.4, (v - 64) * z / 102.4, z], 1)
+    log_s = np.log(sig_px * z / 102.4)[:, None] + np.zeros((1, 3))
+    sc = synth.Scene(means.astype(np.float32), log_s.astype(np.float32),
+                     np.tile(np.float32([1, 0, 0, 0]), (n, 1)),
+                     np.full(n, 2.0, np.float32), rng.random((n, 3)).astype(np.float32))
+    st = renderer.forward(dev_scene(sc), torch.from_numpy(eye_view()).cuda(), rcam(cam))
+    dbg = st.stage()
+    stg = dbg["stage"]
+    ranges, ids = binning.tile_lists(stg[:, 0], stg[:, 1], stg[:, 7], stg[:, 8], stg[:, 6],
+                                     np.ones(n, bool), 128, 128)
+    per_chunk = len(ids) / ((n + 1023) // 1024)
+    say(f"  pairs {len(ids)}, about {per_chunk:.0f} per chunk")
+    assert per_chunk > 12288
+    assert np.array_equal(dbg["ranges"], ranges)
+    assert np.array_equal(dbg["ids"], ids)
+
+
 @pytest.mark.parametrize("j", [2, 3, 4])
 def test_downsampled_frame_renders_one_sample_per_block(renderer, j):
     """A frame masked to one pixel in 2^j renders with coarse tiles of 16x16
