@@ -90,7 +90,7 @@ def counter_record():
 # a separate Adam 28 B for each of 14 parameters per Gaussian.  Kernel names
 # per stage as the profiler lists them.
 HBM_STAGES = {
-    "preprocess": (lambda n, p: 152 * n, ("k_preprocess",)),
+    "preprocess": (lambda n, p: 152 * n, ("k_preprocess<false>",)),
     "bin_count": (lambda n, p: 20 * n, ("k_chunk_hist",)),
     "emit": (lambda n, p: 12 * p, ("k_emit",)),
     "sort": (lambda n, p: 12 * p, ("k_sort_tiles", "k_sort_big_tiles")),
@@ -98,7 +98,10 @@ HBM_STAGES = {
     "preprocess_bwd": (lambda n, p: 392 * n, ("k_gauss_bwd",)),
     "adam": (lambda n, p: 392 * n, ("k_adam",)),
 }
-VALU_STAGES = {"raster_fwd": ("k_raster_fwd",), "raster_bwd": ("k_raster_bwd",)}
+# the raster variants the headline step launches (the statistics forward of
+# the work counts is another)
+VALU_STAGES = {"raster_fwd": ("k_raster_fwd<false, false, false>",),
+               "raster_bwd": ("k_raster_bwd<10, false, false, false>",)}
 
 
 def _kernel_sum(rec, prefixes, field):
@@ -175,6 +178,101 @@ def path_roofline(cnt, ms_per_step, bwd_ms, fwd_ms, spec):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+CALIB_COPY_BYTES = 128 << 22           # the --calib-copy copy: 128 Mi floats
+
+
+def _short_kernel(name):
+    import re
+    name = name.replace("rtgs::(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", name).strip()
+
+
+def _pmc_per_kernel(db):
+    """{short kernel name: {counter: median per dispatch}} from a rocprofv3
+    results database (rows of one dispatch and counter are summed), plus the
+    median dispatch duration in ns and the dispatch count."""
+    import sqlite3
+    import statistics
+    from collections import defaultdict
+    cur = sqlite3.connect(db).cursor()
+    per = defaultdict(lambda: defaultdict(float))
+    names, dur = {}, {}
+    for disp, kname, cname, val, d in cur.execute(
+            "select dispatch_id, kernel_name, counter_name, value, duration "
+            "from counters_collection"):
+        per[disp][cname] += val
+        names[disp] = kname
+        dur[disp] = d
+    byk = defaultdict(lambda: defaultdict(list))
+    for disp, cs in per.items():
+        k = _short_kernel(names[disp])
+        for c, v in cs.items():
+            byk[k][c].append(v)
+        byk[k]["duration_ns"].append(dur[disp])
+    return {k: {**{c: statistics.median(v) for c, v in cs.items()},
+                "dispatches": len(cs["duration_ns"])} for k, cs in byk.items()}
+
+
+def _copy_counter(db, counter):
+    """The counter of the largest copy dispatch of a run (the calibration
+    copy of --calib-copy is the largest copy this bench makes)."""
+    import sqlite3
+    cur = sqlite3.connect(db).cursor()
+    return max(v for (v,) in cur.execute(
+        "select value from counters_collection where counter_name = ? and "
+        "kernel_name like '%copyBuffer%'", (counter,)))
+
+
+def counter_summary(root):
+    """Markdown summary of four counter runs of this bench (FETCH_SIZE,
+    WRITE_SIZE, two SQ sets) with the record `counter_record` reads: HBM
+    bytes per launch (FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what it
+    reads for the --calib-copy copy of known size) and wave-level VALU
+    instructions, keyed by the hash of the kernel sources."""
+    db = lambda x: os.path.join(root, x, "run_results.db")
+    fetch, write = _pmc_per_kernel(db("fetch")), _pmc_per_kernel(db("write"))
+    sq, sqw = _pmc_per_kernel(db("sq")), _pmc_per_kernel(db("sqw"))
+    cf = _copy_counter(db("fetch"), "FETCH_SIZE") * 1024
+    cw = _copy_counter(db("write"), "WRITE_SIZE") * 1024
+    sf, sw = CALIB_COPY_BYTES / cf, CALIB_COPY_BYTES / cw
+    rec = {"kernel_hash": kernel_hash(),
+           "calibration": {"copy_bytes": CALIB_COPY_BYTES, "fetch_counter_bytes": cf,
+                           "write_counter_bytes": cw, "fetch_scale": sf, "write_scale": sw},
+           "kernels": {}}
+    rows = []
+    for k in sorted(set(fetch) & set(write) & set(sq)):
+        if not k.startswith("k_"):
+            continue
+        f = fetch[k]["FETCH_SIZE"] * 1024 * sf
+        w = write[k]["WRITE_SIZE"] * 1024 * sw
+        q = sq[k]
+        e = {"fetch_bytes": f, "write_bytes": w, "bytes": f + w,
+             "valu_insts": q.get("SQ_INSTS_VALU"), "salu_insts": q.get("SQ_INSTS_SALU"),
+             "lds_insts": q.get("SQ_INSTS_LDS"), "trans_insts": q.get("SQ_INSTS_VALU_TRANS_F32"),
+             "waves": q.get("SQ_WAVES"), "wave_cycles": q.get("SQ_WAVE_CYCLES"),
+             "busy_cycles": q.get("SQ_BUSY_CYCLES"), "cycles": q.get("SQ_CYCLES"),
+             "duration_us": fetch[k]["duration_ns"] / 1000.0}
+        if k in sqw:
+            e.update(wait_any=sqw[k].get("SQ_WAIT_ANY"),
+                     wait_inst_lds=sqw[k].get("SQ_WAIT_INST_LDS"),
+                     lds_bank_conflict=sqw[k].get("SQ_LDS_BANK_CONFLICT"))
+        rec["kernels"][k] = e
+        rows.append((k, e))
+    rows.sort(key=lambda r: -r[1]["duration_us"])
+    out = ["| kernel | us (counter run) | fetch MB | write MB | VALU insts | trans | LDS insts "
+           "| waves | wait_any / wave_cycles |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k, e in rows:
+        wr = (e.get("wait_any") or 0) / e["wave_cycles"] if e.get("wave_cycles") else None
+        out.append(f"| {k} | {e['duration_us']:.1f} | {e['fetch_bytes'] / 1e6:.1f} | "
+                   f"{e['write_bytes'] / 1e6:.1f} | {e['valu_insts'] or 0:.0f} | "
+                   f"{e['trans_insts'] or 0:.0f} | {e['lds_insts'] or 0:.0f} | "
+                   f"{e['waves'] or 0:.0f} | {'' if wr is None else f'{wr:.2f}'} |")
+    cal = (f"Calibration (the {CALIB_COPY_BYTES >> 20} MiB copy of --calib-copy): FETCH_SIZE "
+           f"reads {cf / 2**20:.1f} MiB (scale {sf:.4f}), WRITE_SIZE {cw / 2**20:.1f} MiB "
+           f"(scale {sw:.4f}).")
+    return "\n".join(out + ["", cal, "", "```json", json.dumps(rec, indent=1), "```"])
 
 
 def setup(spec_name="c2", seed_offset=0):
@@ -625,7 +723,14 @@ def main():
                          "(0 disables the serving runs)")
     ap.add_argument("--serve-baseline-seconds", type=float, default=10.0,
                     help="length of the one-item-at-a-time serving traces")
+    ap.add_argument("--counter-record", metavar="DIR",
+                    help="print the counter summary (markdown with the JSON record this "
+                         "bench reads) of the rocprofv3 results under DIR/{fetch,write,sq,"
+                         "sqw}/run_results.db, and exit")
     args = ap.parse_args()
+    if args.counter_record:
+        print(counter_summary(args.counter_record))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this path has no multi-GPU mode "
               f"(--gpus {args.gpus} requested).", file=sys.stderr)
@@ -664,7 +769,7 @@ def main():
     achieved = flops / (bwd_ms * 1e-3) / 1e12
     rec = counter_record()
     khash = kernel_hash()
-    bwd_bytes = _kernel_sum(rec, ("k_raster_bwd",), "bytes")
+    bwd_bytes = _kernel_sum(rec, VALU_STAGES["raster_bwd"], "bytes")
     roof = {"kernel": "raster_bwd", "bound": "alu", "achieved": achieved,
             "peak": PEAK_FP32_PUBLISHED, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED,
             "traffic": bwd_bytes,
