@@ -516,6 +516,55 @@ def lane_balance_run(iters=20):
     return out
 
 
+def state_policy_run(iters=10):
+    """Forward + backward to the map at 1200x680 with 300k and 500k
+    Gaussians under the three state policies of the backward: the saved
+    per-pixel state (final T and last position), the state recomputed by a
+    second forward pass, and the saved fragments (each blended fragment's
+    alpha, the per-fragment state of the paper's R&B buffer): raster times
+    (HIP events), iteration time and workspace bytes."""
+    import torch
+    from paper_2510_06644_amd import rtgs, synth
+    out = {}
+    for name in ("c2", "c3"):
+        spec = synth.CONFIGS[name]
+        cam = synth.make_camera(spec.width, spec.height)
+        sc = synth.make_scene(spec, cam)
+        scene = tuple(torch.from_numpy(a).cuda() for a in sc.arrays())
+        rc = rtgs.Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+        R = rtgs.Renderer(0, check="deferred")
+        view = torch.eye(3, 4, dtype=torch.float32, device="cuda").contiguous()
+        tc, td = render_target(R, scene, view, rc, spec.seed)
+        res = {}
+        for pol in ("saved_state", "recompute", "saved_fragments", "saved_state"):
+            kw = {"save_state": pol != "recompute", "save_fragments": pol == "saved_fragments"}
+            st = R.forward(scene, view, rc, **kw)          # warm-up, sizes the workspace
+            torch.cuda.synchronize()
+            rtgs.rtgs_profile_enable(R.handle, ["raster_fwd", "raster_bwd"])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(iters):
+                st = R.forward(scene, view, rc, **kw)
+                gc, gd = l1_grads(st.color, st.depth, tc, td)
+                R.backward(scene, view, rc, st, gc, gd, pose=False, map_grads=True)
+            e1.record()
+            torch.cuda.synchronize()
+            prof = rtgs.rtgs_profile_read(R.handle)
+            rtgs.rtgs_profile_enable(R.handle, [])
+            R.verify()
+            fwd = prof["raster_fwd"]
+            res[pol] = {"ms_per_iter": e0.elapsed_time(e1) / iters,
+                        "raster_fwd_us_per_launch": 1000 * fwd[0] / fwd[1],
+                        "raster_fwd_launches_per_iter": fwd[1] / iters,
+                        "raster_bwd_us": 1000 * prof["raster_bwd"][0] / prof["raster_bwd"][1],
+                        "workspace_bytes": st.ws.numel() * st.ws.element_size(),
+                        "pair_capacity": st.cap}
+            del st
+            torch.cuda.empty_cache()
+        out[f"{cam.width}x{cam.height}_{spec.n // 1000}k"] = res
+    return out
+
+
 def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False, mask_prune=False):
     """Tracking at 640x480 with 100k Gaussians: the map frozen, the camera
     starting 2 cm / 1 degree off the pose its target frame was rendered
@@ -797,10 +846,12 @@ def main():
             mapping_step(R2, params2, view2, rc2, opt2, tc2, td2)
         R2.cap = R.cap
         variant = as_written_variant(R2, params2, view2, rc2, opt2, tc2, td2)
-    balance = None
+    balance = policies = None
     if not args.no_variant:
         log("lanes assigned by previous work")
         balance = lane_balance_run()
+        log("backward state policies")
+        policies = state_policy_run()
     tracking = tracking_reuse = tracking_prune = None
     if not args.no_tracking:
         log("tracking 640x480 / 100k")
@@ -861,6 +912,7 @@ def main():
         "host_wall_ms_per_step": 1000.0 * wall_ms,
         "as_written": variant,
         "lane_balance": balance,
+        "state_policies": policies,
         "tracking": tracking,
         "tracking_reuse_lists": tracking_reuse,
         "tracking_mask_prune": tracking_prune,
