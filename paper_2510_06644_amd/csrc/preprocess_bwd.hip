@@ -343,6 +343,8 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_gauss_bwd(Batch B, WsPtrs W,
     }
   }
   // block partial of the pose gradient: wave shuffles, then the 4 waves in LDS
+  // (the flag is the launch's, so the whole workgroup leaves together)
+  if (!(flags & RTGS_GRAD_POSE)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = 0; k < 12; ++k) {
     double v = pose[k];

@@ -146,4 +146,16 @@ def full_frame_parity(renderer, sc, cam, view, seed=7, pixel_mask=None, label=""
     e = rel_err(g["pose"], rg.pose.numpy())
     say(f"  {label} pose: {e:.2e}")
     assert e < GRAD_TOL
+    # the map gradients alone (no pose gradient), the launch a mapping
+    # iteration makes
+    gm = renderer.backward(dsc, dview, rcam(cam), st, torch.from_numpy(gc).cuda(),
+                           torch.from_numpy(gd).cuda(), torch.from_numpy(ga).cuda(),
+                           pose=False, pixel_mask=pm)
+    torch.cuda.synchronize()
+    for name in MAP_GRADS:
+        r = getattr(rg, name).numpy()
+        x = gm[name].cpu().numpy()
+        e1, e2, e3 = grad_err(x, r), norm_err(x, r), component_err(x, r)
+        say(f"  {label} {name} (map only): rel {e1:.2e} norm {e2:.2e} (worst component {e3:.2e})")
+        assert e1 < GRAD_TOL and e2 < GRAD_TOL, name
     return st, ref, g, rg

@@ -79,3 +79,13 @@ def test_full_size_sampled_parity(name):
     e = rel_err(g["pose"].cpu().numpy(), rg.pose.numpy())
     say(f"  pose: {e:.2e}")
     assert e < GRAD_TOL
+    # the map gradients alone, in the launch the mapping iteration makes
+    gm = r.backward(dsc, dview, rcam(cam), st,
+                    torch.from_numpy(gc.reshape(3, cam.height, cam.width)).cuda(),
+                    torch.from_numpy(gd.reshape(cam.height, cam.width)).cuda(),
+                    torch.from_numpy(ga.reshape(cam.height, cam.width)).cuda(), pose=False)
+    torch.cuda.synchronize()
+    for name_g in ("means", "log_scales", "quats", "opacity_logits", "colors"):
+        e = grad_err(gm[name_g].cpu().numpy(), getattr(rg, name_g).numpy())
+        say(f"  {name_g} (map only): {e:.2e}")
+        assert e < GRAD_TOL, name_g

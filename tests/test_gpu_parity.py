@@ -129,14 +129,17 @@ def _cov6(m):
     return np.stack([m[:, 0, 0], m[:, 0, 1], m[:, 0, 2], m[:, 1, 1], m[:, 1, 2], m[:, 2, 2]], 1)
 
 
-@pytest.mark.parametrize("posed,alpha_grad", [(False, True), (True, True), (True, False)])
-def test_backward_all_gradients_c0(renderer, posed, alpha_grad):
+@pytest.mark.parametrize("posed,alpha_grad,with_pose", [(False, True, True), (True, True, True),
+                                                        (True, False, True), (False, True, False),
+                                                        (True, True, False)])
+def test_backward_all_gradients_c0(renderer, posed, alpha_grad, with_pose):
     # alpha_grad: with and without an alpha-image gradient (the kernel
-    # leaves that term out when no session passes one)
-    say(f"test_backward c0 posed={posed} alpha_grad={alpha_grad}")
+    # leaves that term out when no session passes one); with_pose: the map
+    # gradients with the pose gradient or alone
+    say(f"test_backward c0 posed={posed} alpha_grad={alpha_grad} with_pose={with_pose}")
     xi = synth.pose_offset(32, 0.05, 3.0) if posed else None
     sc, cam, view = _case("c0", xi)
-    g, ref, keep = _grad_case(renderer, sc, cam, view, alpha_grad=alpha_grad)
+    g, ref, keep = _grad_case(renderer, sc, cam, view, alpha_grad=alpha_grad, pose=with_pose)
     pairs = [("means", ref.means), ("log_scales", ref.log_scales), ("quats", ref.quats),
              ("opacity_logits", ref.opacity_logits), ("colors", ref.colors)]
     for name, r in pairs:
@@ -146,6 +149,8 @@ def test_backward_all_gradients_c0(renderer, posed, alpha_grad):
     e1 = rel_err(g["cov3d"], _cov6(ref.cov3d))
     say(f"  cov3d: rel {e1:.2e}")
     assert e1 < GRAD_TOL
+    if not with_pose:
+        return
     e1, e2 = rel_err(g["pose"], ref.pose.numpy()), norm_err(g["pose"], ref.pose.numpy())
     say(f"  pose: rel {e1:.2e} norm {e2:.2e}  {g['pose']}  {ref.pose.numpy()}")
     assert e1 < GRAD_TOL and e2 < GRAD_TOL
