@@ -278,7 +278,8 @@ int32_t render_fwd(rtgs_handle_t h, const rtgs_gaussians* g,
  * input of the importance score.  dL_dalpha may be NULL.
  * The arguments g, cam, pixel_mask, ws and pair_capacity must be those of the
  * render_fwd whose results are being differentiated.
- * Errors: as render_fwd. */
+ * Errors: as render_fwd; RTGS_GRAD_ADAM is INVALID_ARG here (the fused
+ * update takes render_bwd_batched, whose sessions carry the Adam state). */
 int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g,
                    const rtgs_camera* cam, const uint8_t* pixel_mask,
                    void* ws, uint64_t ws_bytes, int64_t pair_capacity,

@@ -614,6 +614,8 @@ int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g, const rtgs_camera* 
                    float* g_colors, float* g_pose6, float* g_viewmat, float* g_cov3d,
                    void* stream) {
   if (!g || !cam) return fail(RTGS_ERR_INVALID_ARG, "null gaussians or camera");
+  if (grad_flags & RTGS_GRAD_ADAM)
+    return fail(RTGS_ERR_INVALID_ARG, "RTGS_GRAD_ADAM takes render_bwd_batched (its Adam state)");
   rtgs_session s = single(g, cam, pixel_mask);
   s.sample_log2 = (grad_flags >> RTGS_SAMPLE_SHIFT) & 0xf;
   grad_flags &= ~(0xf << RTGS_SAMPLE_SHIFT);

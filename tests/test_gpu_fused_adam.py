@@ -115,3 +115,10 @@ def test_fused_adam_rejects_a_foreign_optimizer_and_needs_map_grads():
                                   rtgs.RTGS_GRAD_POSE | rtgs.RTGS_GRAD_ADAM,
                                   rtgs.stream_ptr())
     assert e.value.code == rtgs.RTGS_ERR_INVALID_ARG
+    # the single-session call has no Adam state to take
+    with pytest.raises(rtgs.RtgsError) as e:
+        rtgs.render_bwd(R.handle, *scene, view, rcam(cam), st.ws, st.cap, st.final_T,
+                        st.last_idx, gc, gd, None,
+                        rtgs.RTGS_GRAD_MAP | rtgs.RTGS_GRAD_ADAM, None, None, None, None,
+                        None, None, None)
+    assert e.value.code == rtgs.RTGS_ERR_INVALID_ARG
