@@ -90,18 +90,18 @@ def counter_record():
 # a separate Adam 28 B for each of 14 parameters per Gaussian.  Kernel names
 # per stage as the profiler lists them.
 HBM_STAGES = {
-    "preprocess": (lambda n, p: 152 * n, ("k_preprocess<false>",)),
-    "bin_count": (lambda n, p: 20 * n, ("k_chunk_hist",)),
-    "emit": (lambda n, p: 12 * p, ("k_emit",)),
-    "sort": (lambda n, p: 12 * p, ("k_sort_tiles", "k_sort_big_tiles")),
+    "preprocess": (lambda n, p: 152 * n, ("k_preprocess<false, true>",)),
+    "bin_count": (lambda n, p: 20 * n, ("k_chunk_hist<true>",)),
+    "emit": (lambda n, p: 12 * p, ("k_emit<true>",)),
+    "sort": (lambda n, p: 12 * p, ("k_sort_tiles<true>", "k_sort_big_tiles")),
     "merge": (lambda n, p: 40 * p + 40 * n, ("k_merge",)),
-    "preprocess_bwd": (lambda n, p: 392 * n, ("k_gauss_bwd",)),
+    "preprocess_bwd": (lambda n, p: 392 * n, ("k_gauss_bwd<10, true, true>",)),
     "adam": (lambda n, p: 392 * n, ("k_adam",)),
 }
 # the raster variants the headline step launches (the statistics forward of
 # the work counts is another)
-VALU_STAGES = {"raster_fwd": ("k_raster_fwd<false, false, false>",),
-               "raster_bwd": ("k_raster_bwd<10, false, false, false>",)}
+VALU_STAGES = {"raster_fwd": ("k_raster_fwd<false, false, false, true>",),
+               "raster_bwd": ("k_raster_bwd<10, false, false, false, true>",)}
 
 
 def _kernel_sum(rec, prefixes, field):
@@ -317,14 +317,20 @@ def l1_grads(color, depth, tc, td, pixel_mask=None, n_active=None):
 
 def mapping_step(R, params, view, rc, opt, tc, td, gauss_mask=None, pixel_mask=None,
                  cov3d=False, sample_log2=0, n_active=None, fused=True):
-    """One mapping iteration.  The Adam update runs inside the backward's
-    per-Gaussian pass (bitwise the update of a separate adam_step); an
-    iteration whose gradients are wanted (cov3d: the inputs of gradient
-    pruning) takes the backward and the optimizer apart."""
+    """One mapping iteration.  Fused: the forward writes the loss gradients
+    as it writes the image, and the Adam update runs inside the backward's
+    per-Gaussian pass (both bitwise the results of the separate loss and
+    adam_step passes); an iteration whose gradients are wanted (cov3d: the
+    inputs of gradient pruning) takes the backward and the optimizer apart."""
     scene = tuple(p.detach() for p in params)
-    st = R.forward(scene, view, rc, gauss_mask=gauss_mask, pixel_mask=pixel_mask,
-                   sample_log2=sample_log2)
-    gc, gd = l1_grads(st.color, st.depth, tc, td, pixel_mask, n_active)
+    if fused:
+        st = R.forward(scene, view, rc, gauss_mask=gauss_mask, pixel_mask=pixel_mask,
+                       sample_log2=sample_log2, l1=(tc, td, n_active))
+        gc, gd = st.dL_dcolor, st.dL_ddepth
+    else:
+        st = R.forward(scene, view, rc, gauss_mask=gauss_mask, pixel_mask=pixel_mask,
+                       sample_log2=sample_log2)
+        gc, gd = l1_grads(st.color, st.depth, tc, td, pixel_mask, n_active)
     if fused and not cov3d:
         g = R.backward(scene, view, rc, st, gc, gd, pose=False, gauss_mask=gauss_mask,
                        pixel_mask=pixel_mask, adam=opt)
@@ -895,8 +901,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": spec.name, "width": cam.width, "height": cam.height,
-                   "gaussians": spec.n, "step": "render_fwd + L1 loss + render_bwd (all map "
-                   "parameters) + Adam (fused into the backward)", "pixels": "full resolution", "prune": False},
+                   "gaussians": spec.n, "step": "render_fwd + L1 loss (fused into the forward) + render_bwd "
+                   "(all map parameters) + Adam (fused into the backward)", "pixels": "full resolution", "prune": False},
         "roofline": roof,
         "path_roofline": path_roofline(cnt, ms, bwd_ms, fwd_ms, spec),
         "raster_fwd_roofline": {"bound": "alu", "avg_ms": fwd_ms,

@@ -171,6 +171,23 @@ typedef struct {
   double beta1, beta2, eps;
 } rtgs_map_adam;
 
+/* The loss gradient of a frame, formed by the forward that renders it (a
+ * HOST struct of device arrays; see rtgs_session.l1).  The outputs are those
+ * of loss_l1_grad(color, depth, target_color, target_depth, the session's
+ * pixel_mask, n_active_dev, width, height, w_color, w_depth, dL_dcolor,
+ * dL_ddepth) called on the forward's colour and depth, bitwise, for every
+ * pixel of the frame.  Errors (INVALID_ARG): a null array, a pixel mask
+ * without n_active_dev, weights not finite. */
+typedef struct {
+  const float* target_color;   /* [3][H][W] */
+  const float* target_depth;   /* [H][W] */
+  const int32_t* n_active_dev; /* device int32 (values below 1 count as 1), or
+                                  NULL: W * H; required with a pixel mask */
+  float w_color, w_depth;
+  float* dL_dcolor;            /* [3][H][W], written */
+  float* dL_ddepth;            /* [H][W], written */
+} rtgs_l1_loss;
+
 /* One session of a batched call: its own map, camera, masks, outputs and
  * gradients; same meaning as the arguments of render_fwd / render_bwd. */
 typedef struct {
@@ -211,6 +228,8 @@ typedef struct {
   /* fused map update (RTGS_GRAD_ADAM; ignored without it) */
   const rtgs_map_adam* adam;   /* HOST pointer, or NULL: no update of this
                                   session's map                              */
+  /* loss gradient formed by render_fwd_batched (Eq. 6; NULL: none) */
+  const rtgs_l1_loss* l1;      /* HOST pointer, or NULL                      */
 } rtgs_session;
 
 /* Last error message of the calling thread (static storage, never NULL). */
@@ -293,7 +312,11 @@ int32_t render_bwd(rtgs_handle_t h, const rtgs_gaussians* g,
 /* Batched forward / backward over n_sessions (<= RTGS_MAX_SESSIONS): one
  * launch per stage for all sessions, one tile space and one sort.  `sessions`
  * is a HOST array; each entry has the meaning of the single-session
- * arguments.  Per-session results equal those of single-session calls. */
+ * arguments.  Per-session results equal those of single-session calls.  A
+ * forward session with a non-NULL l1 also gets the gradient of the loss of
+ * Eq. 6 with respect to its colour and depth (rtgs_l1_loss), written by the
+ * rasterizer as it writes the image, so that no separate loss pass reads the
+ * image back. */
 int32_t render_fwd_batched(rtgs_handle_t h, const rtgs_session* sessions,
                            int32_t n_sessions, void* ws, uint64_t ws_bytes,
                            int64_t pair_capacity, int32_t flags, void* stream);

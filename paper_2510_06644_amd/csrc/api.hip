@@ -252,6 +252,16 @@ int32_t check_session(const rtgs_session& s, int idx, bool fwd, int32_t flags) {
       return fail(RTGS_ERR_INVALID_ARG, "session %d: null colour/depth/alpha output", idx);
     if ((flags & RTGS_FWD_SAVE_STATE) && (!s.final_T || !s.last_idx))
       return fail(RTGS_ERR_INVALID_ARG, "session %d: SAVE_STATE needs final_T and last_idx", idx);
+    if (s.l1) {
+      const rtgs_l1_loss& l = *s.l1;
+      if (!l.target_color || !l.target_depth || !l.dL_dcolor || !l.dL_ddepth)
+        return fail(RTGS_ERR_INVALID_ARG, "session %d: null loss array", idx);
+      if (s.pixel_mask && !l.n_active_dev)
+        return fail(RTGS_ERR_INVALID_ARG, "session %d: loss with a pixel mask needs n_active_dev",
+                    idx);
+      if (!std::isfinite(l.w_color) || !std::isfinite(l.w_depth))
+        return fail(RTGS_ERR_INVALID_ARG, "session %d: loss weights not finite", idx);
+    }
   } else {
     if (!s.dL_dcolor || !s.dL_ddepth)
       return fail(RTGS_ERR_INVALID_ARG, "session %d: null dL/dcolor or dL/ddepth", idx);
@@ -332,6 +342,15 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
       d.stats = (flags & RTGS_FWD_STATS) ? s.stats : nullptr;
       d.lane_work = (flags & RTGS_FWD_BALANCE_LANES) ? s.lane_work : nullptr;
       d.lane_work_out = (flags & RTGS_FWD_BALANCE_LANES) ? s.lane_work_out : nullptr;
+      if (s.l1) {
+        d.l1_tcolor = s.l1->target_color;
+        d.l1_tdepth = s.l1->target_depth;
+        d.l1_n_active = s.l1->n_active_dev;
+        d.l1_dcolor = s.l1->dL_dcolor;
+        d.l1_ddepth = s.l1->dL_ddepth;
+        d.l1_w_color = s.l1->w_color;
+        d.l1_w_depth = s.l1->w_depth;
+      }
     } else {
       if (flags & RTGS_GRAD_RECOMPUTE_STATE) {
         d.final_T = w.state_t + pbase;

@@ -103,11 +103,11 @@ __device__ __forceinline__ void split(double x, float& hi, float& lo) {
 // REUSE: the tile lists (and with them each Gaussian's tile rectangle, pair
 // count and slots) stay those of the workspace's last full forward; only the
 // raster records are recomputed for the current pose.
-template <bool REUSE>
+template <bool REUSE, bool ONE>
 __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W) {
-  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
-                             [](const SessionDev& x) { return x.block_base; });
-  const SessionDev& S = session_of(B, s);
+  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                                         [](const SessionDev& x) { return x.block_base; });
+  const SessionDev& S = batch_session<ONE>(B, s);
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
   // the call's counters start at zero (the binning passes run after this kernel)
   if (!REUSE && blockIdx.x == 0 && threadIdx.x < 8) W.counters[threadIdx.x] = 0;
@@ -260,14 +260,15 @@ __device__ __forceinline__ void chunk_pairs(const SessionDev& S, const int4* s_r
 
 // Per chunk of kChunk Gaussians: pair counts per tile of the session (LDS
 // histogram), and the chunk's pair total.
+template <bool ONE>
 __global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_hist[];
   __shared__ uint32_t s_off[kChunk + 1];
   __shared__ int4 s_rect[kChunk];
   __shared__ uint32_t s_wave[kBinThreads / 64];
-  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
-                             [](const SessionDev& x) { return x.chunk_base; });
-  const SessionDev& S = session_of(B, s);
+  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                                         [](const SessionDev& x) { return x.chunk_base; });
+  const SessionDev& S = batch_session<ONE>(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
   for (int t = threadIdx.x; t < ts; t += kBinThreads) s_hist[t] = 0u;
@@ -292,13 +293,14 @@ __device__ __forceinline__ void tile_groups(const SessionDev& S, int g, int& c0,
   c1 = min(nc, c0 + per);
 }
 
+template <bool ONE>
 __global__ __launch_bounds__(kBlock) void k_tile_group_sums(Batch B, WsPtrs W) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int g = blockIdx.y;
   if (t >= B.t_total) return;
-  const int s = find_session(B.sess, B.n_sessions, t,
-                             [](const SessionDev& x) { return x.tile_base; });
-  const SessionDev& S = session_of(B, s);
+  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, t,
+                                         [](const SessionDev& x) { return x.tile_base; });
+  const SessionDev& S = batch_session<ONE>(B, s);
   const int ts = S.tiles_x * S.tiles_y;
   int c0, c1;
   tile_groups(S, g, c0, c1);
@@ -343,23 +345,105 @@ __device__ uint32_t block_scan_1024(const uint32_t* in, uint32_t* out, int n, ui
   return total;
 }
 
+// Exclusive scan across the block of the values v[0..P) that each thread
+// holds for positions P tid .. P tid + P - 1; v becomes the exclusive
+// prefixes, and the block total is returned.  Same two-barrier structure as
+// block_scan_1024.
+template <int P>
+__device__ uint32_t block_scan_regs(uint32_t (&v)[P], uint32_t* part) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < P; ++i) sum += v[i];
+  uint32_t x = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) part[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int q = 0; q < kScanThreads / 64; ++q) {
+    const uint32_t w = part[q];
+    before += q < wave ? w : 0u;
+    total += w;
+  }
+  uint32_t run = before + x - sum;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const uint32_t w = v[i];
+    v[i] = run;
+    run += w;
+  }
+  __syncthreads();                        // part is reused by the next call
+  return total;
+}
+
 // Tile ranges (scan of the per-tile counts, each the sum of its chunk
 // groups), chunk offsets (scan of the per-chunk totals), and the pair total.
-// When the pairs exceed the capacity every tile list is published empty (the
-// call's output is invalid and reported, and no list holds a pair that was
-// not stored).
+// Up to kScanPer tiles and chunks per thread the counts are loaded together
+// with coalesced loads into LDS, scanned in registers (each thread a
+// contiguous run) and stored coalesced from LDS: one round trip to memory.
+// Larger batches scan through global memory.  When the pairs exceed the
+// capacity every tile list is published empty (the call's output is invalid
+// and reported, and no list holds a pair that was not stored).
+constexpr int kScanPer = 4;
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_total, int c_total,
                                                              unsigned long long* max_pairs) {
   __shared__ uint32_t part[kScanThreads / 64];
-  for (int t = threadIdx.x; t < t_total; t += kScanThreads) {
-    uint32_t sum = 0;
+  __shared__ uint32_t s_t[kScanPer * kScanThreads], s_c[kScanPer * kScanThreads];
+  const int tid = threadIdx.x;
+  uint32_t total;
+  if (t_total <= kScanPer * kScanThreads && c_total <= kScanPer * kScanThreads) {
 #pragma unroll
-    for (int g = 0; g < kScanGroups; ++g) sum += W.gsum[(int64_t)g * t_total + t];
-    W.tile_count[t] = sum;
+    for (int k = 0; k < kScanPer; ++k) {
+      const int t = k * kScanThreads + tid;
+      uint32_t sum = 0;
+      if (t < t_total) {
+#pragma unroll
+        for (int g = 0; g < kScanGroups; ++g) sum += W.gsum[(int64_t)g * t_total + t];
+      }
+      s_t[t] = sum;
+      s_c[t] = t < c_total ? W.chunk_total[t] : 0u;
+    }
+    __syncthreads();
+    uint32_t tv[kScanPer], cv[kScanPer];
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      tv[i] = s_t[tid * kScanPer + i];
+      cv[i] = s_c[tid * kScanPer + i];
+    }
+    total = block_scan_regs<kScanPer>(tv, part);        // its barriers order the LDS reuse
+    const uint32_t ctot = block_scan_regs<kScanPer>(cv, part);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      s_t[tid * kScanPer + i] = tv[i];
+      s_c[tid * kScanPer + i] = cv[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int t = k * kScanThreads + tid;
+      if (t < t_total) W.tile_start[t] = s_t[t];
+      if (t < c_total) W.chunk_off[t] = s_c[t];
+    }
+    if (tid == 0) {
+      W.tile_start[t_total] = total;
+      W.chunk_off[c_total] = ctot;
+    }
+    __syncthreads();                      // tile_start complete before an overflow clears it
+  } else {
+    for (int t = tid; t < t_total; t += kScanThreads) {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int g = 0; g < kScanGroups; ++g) sum += W.gsum[(int64_t)g * t_total + t];
+      W.tile_count[t] = sum;
+    }
+    __syncthreads();
+    total = block_scan_1024(W.tile_count, W.tile_start, t_total, part);
+    block_scan_1024(W.chunk_total, W.chunk_off, c_total, part);
   }
-  __syncthreads();
-  const uint32_t total = block_scan_1024(W.tile_count, W.tile_start, t_total, part);
-  block_scan_1024(W.chunk_total, W.chunk_off, c_total, part);
   if ((int64_t)total > W.cap)
     for (int t = threadIdx.x; t <= t_total; t += kScanThreads) W.tile_start[t] = 0u;
   if (threadIdx.x == 0) {
@@ -380,15 +464,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(WsPtrs W, int t_tot
 // writes them directly inside its block.
 constexpr int kStagePairs = 12288;
 
+template <bool ONE>
 __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   extern __shared__ uint32_t s_dyn[];       // [ts] tile cursors, then [kStagePairs] uint16
   __shared__ uint32_t s_off[kChunk + 1];
   __shared__ int4 s_rect[kChunk];
   __shared__ uint32_t s_zb[kChunk];
   __shared__ uint32_t s_wave[kBinThreads / 64];
-  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
-                             [](const SessionDev& x) { return x.chunk_base; });
-  const SessionDev& S = session_of(B, s);
+  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                                         [](const SessionDev& x) { return x.chunk_base; });
+  const SessionDev& S = batch_session<ONE>(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
   uint32_t* s_cur = s_dyn;
@@ -695,6 +780,7 @@ __device__ void gather_tile(const WsPtrs& W, const SessionDev& S, int lt, int n,
 // the chunk rows and runs they share): lists of up to 1024 keys are gathered
 // to LDS and sorted here; longer ones are gathered to the tile-major buffer
 // and queued for k_sort_big_tiles.
+template <bool ONE>
 __global__ __launch_bounds__(kBlock) void k_sort_tiles(Batch B, WsPtrs W) {
   __shared__ unsigned long long b0[kSortPerThread * kBlock], b1[kSortPerThread * kBlock];
   __shared__ uint32_t s_part[kBlock / 64];
@@ -709,9 +795,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_tiles(Batch B, WsPtrs W) {
   const uint32_t st = W.tile_start[t];
   const int n = (int)(W.tile_start[t + 1] - st);   // all empty after an overflow
   if (n <= 0) return;
-  const int s = find_session(B.sess, B.n_sessions, t,
-                             [](const SessionDev& x) { return x.tile_base; });
-  const SessionDev& S = session_of(B, s);
+  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, t,
+                                         [](const SessionDev& x) { return x.tile_base; });
+  const SessionDev& S = batch_session<ONE>(B, s);
   if (n > kSortPerThread * kBlock) {
     gather_tile(W, S, t - S.tile_base, n, W.keys_tm + st, s_part, s_at, s_src);
     if (threadIdx.x == 0) {
@@ -807,10 +893,14 @@ __global__ void k_wave_sum_test(const float* in, float* out, int n_waves) {
 
 hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long long* max_pairs,
                                bool reuse_lists, hipStream_t st, StageTimer* tm) {
+  const bool one = b.n_sessions == 1;
   if (reuse_lists) {
     if (b.b_total > 0) {
       Scope sc(tm, kStPreprocess, st);
-      k_preprocess<true><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+      if (one)
+        k_preprocess<true, true><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+      else
+        k_preprocess<true, false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
     }
     return hipGetLastError();
   }
@@ -822,25 +912,41 @@ hipError_t launch_forward_prep(const Batch& b, const WsPtrs& w, unsigned long lo
   }
   if (b.b_total > 0) {
     Scope sc(tm, kStPreprocess, st);
-    k_preprocess<false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+    if (one)
+      k_preprocess<false, true><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
+    else
+      k_preprocess<false, false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w);
   }
   if (b.c_total > 0) {
     Scope sc(tm, kStBinCount, st);
-    k_chunk_hist<<<b.c_total, kBinThreads, lds, st>>>(b, w);
+    if (one)
+      k_chunk_hist<true><<<b.c_total, kBinThreads, lds, st>>>(b, w);
+    else
+      k_chunk_hist<false><<<b.c_total, kBinThreads, lds, st>>>(b, w);
   }
   {
     Scope sc(tm, kStScan, st);
     const dim3 grid((b.t_total + kBlock - 1) / kBlock, kScanGroups);
-    k_tile_group_sums<<<grid, kBlock, 0, st>>>(b, w);
+    if (one)
+      k_tile_group_sums<true><<<grid, kBlock, 0, st>>>(b, w);
+    else
+      k_tile_group_sums<false><<<grid, kBlock, 0, st>>>(b, w);
     k_scan_tiles<<<1, kScanThreads, 0, st>>>(w, b.t_total, b.c_total, max_pairs);
   }
   if (b.c_total > 0) {
     Scope sc(tm, kStEmit, st);
-    k_emit<<<b.c_total, kBinThreads, lds + sizeof(uint16_t) * kStagePairs, st>>>(b, w);
+    const size_t lds_emit = lds + sizeof(uint16_t) * kStagePairs;
+    if (one)
+      k_emit<true><<<b.c_total, kBinThreads, lds_emit, st>>>(b, w);
+    else
+      k_emit<false><<<b.c_total, kBinThreads, lds_emit, st>>>(b, w);
   }
   if (b.t_total > 0) {
     Scope sc(tm, kStSort, st);
-    k_sort_tiles<<<8 * ((b.t_total + 7) / 8), kBlock, 0, st>>>(b, w);
+    if (one)
+      k_sort_tiles<true><<<8 * ((b.t_total + 7) / 8), kBlock, 0, st>>>(b, w);
+    else
+      k_sort_tiles<false><<<8 * ((b.t_total + 7) / 8), kBlock, 0, st>>>(b, w);
     k_sort_big_tiles<<<b.t_total < 512 ? b.t_total : 512, kBigThreads, 0, st>>>(w);
   }
   return hipGetLastError();

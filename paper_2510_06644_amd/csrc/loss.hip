@@ -11,8 +11,6 @@ namespace {
 
 static_assert(sizeof(LossBatchArgs) <= 4000, "loss table must fit the kernel arguments");
 
-__device__ __forceinline__ float sgn(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
-
 __device__ __forceinline__ void l1_grad_pixel(const LossArgs& a, int64_t p) {
   const int64_t hw = (int64_t)a.w * a.h;
   if (p >= hw) return;
@@ -22,9 +20,9 @@ __device__ __forceinline__ void l1_grad_pixel(const LossArgs& a, int64_t p) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int64_t q = c * hw + p;
-    a.g_color[q] = m * sc * sgn(a.color[q] - a.t_color[q]);
+    a.g_color[q] = m * sc * sign_of(a.color[q] - a.t_color[q]);
   }
-  a.g_depth[p] = m * sd * sgn(a.depth[p] - a.t_depth[p]);
+  a.g_depth[p] = m * sd * sign_of(a.depth[p] - a.t_depth[p]);
 }
 
 __global__ __launch_bounds__(256) void k_l1_grad(LossArgs a) {

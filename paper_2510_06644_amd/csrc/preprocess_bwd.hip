@@ -142,12 +142,12 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
   }
 }
 
-template <int NV, bool ADAM>
+template <int NV, bool ADAM, bool ONE>
 __global__ __launch_bounds__(kGaussPerBlock) void k_gauss_bwd(Batch B, WsPtrs W, int flags) {
   __shared__ double s_red[kGaussPerBlock / 64][12];
-  const int s = find_session(B.sess, B.n_sessions, (int)blockIdx.x,
-                             [](const SessionDev& x) { return x.block_base; });
-  const SessionDev& S = session_of(B, s);
+  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+                                       [](const SessionDev& x) { return x.block_base; });
+  const SessionDev& S = batch_session<ONE>(B, s);
   const int li0 = ((int)blockIdx.x - S.block_base) * kGaussPerBlock;
   // ---- projection backward, one thread per Gaussian
   const int li = li0 + (int)threadIdx.x;
@@ -314,31 +314,68 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_gauss_bwd(Batch B, WsPtrs W,
       for (int k = 0; k < 6; ++k) S.g_cov3d[6 * li + k] = (float)gsig[k];
     }
     // ---- Adam on the Gaussian's parameters (the update of adam_step, on
-    // the same float32 gradients)
+    // the same float32 gradients).  The constants, then every parameter and
+    // moment, are read before the first store: the stores may alias them, so
+    // read element by element each would wait for the previous one's store.
     if (ADAM && S.adam.on) {
       const MapAdamDev& A = S.adam;
+      const float beta1 = A.beta1, beta2 = A.beta2, omb1 = A.omb1, omb2 = A.omb2, eps = A.eps;
+      const float isb2 = A.inv_sqrt_bc2;
+      float step[5];
+      float* par[5] = {const_cast<float*>(S.means), const_cast<float*>(S.log_scales),
+                       const_cast<float*>(S.quats), const_cast<float*>(S.opac),
+                       const_cast<float*>(S.colors)};
+      float *pm[5], *pv2[5];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        step[t] = A.step_size[t];
+        pm[t] = A.m[t];
+        pv2[t] = A.v[t];
+      }
       const float g14[14] = {(float)gm[0], (float)gm[1], (float)gm[2], (float)gl[0],
                              (float)gl[1], (float)gl[2], (float)gq[0], (float)gq[1],
                              (float)gq[2], (float)gq[3], (float)go_eta, (float)gcol[0],
                              (float)gcol[1], (float)gcol[2]};
-      float* const par[5] = {const_cast<float*>(S.means), const_cast<float*>(S.log_scales),
-                             const_cast<float*>(S.quats), const_cast<float*>(S.opac),
-                             const_cast<float*>(S.colors)};
       constexpr int kDim[5] = {3, 3, 4, 1, 3};
-      int at = 0;
+      float P[14], Mo[14], Vo[14];
+      {
+        int at = 0;
 #pragma unroll
-      for (int t = 0; t < 5; ++t) {
+        for (int t = 0; t < 5; ++t) {
 #pragma unroll
-        for (int k = 0; k < kDim[t]; ++k) {
-          const int64_t e = (int64_t)kDim[t] * li + k;
-          float pv = par[t][e], mv = A.m[t][e], vv = A.v[t][e];
-          adam_update(pv, g14[at + k], mv, vv, A.beta1, A.beta2, A.omb1, A.omb2, A.eps,
-                      A.step_size[t], A.inv_sqrt_bc2);
-          par[t][e] = pv;
-          A.m[t][e] = mv;
-          A.v[t][e] = vv;
+          for (int k = 0; k < kDim[t]; ++k) {
+            const int64_t e = (int64_t)kDim[t] * li + k;
+            P[at + k] = par[t][e];
+            Mo[at + k] = pm[t][e];
+            Vo[at + k] = pv2[t][e];
+          }
+          at += kDim[t];
         }
-        at += kDim[t];
+      }
+      {
+        int at = 0;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+#pragma unroll
+          for (int k = 0; k < kDim[t]; ++k)
+            adam_update(P[at + k], g14[at + k], Mo[at + k], Vo[at + k], beta1, beta2, omb1, omb2,
+                        eps, step[t], isb2);
+          at += kDim[t];
+        }
+      }
+      {
+        int at = 0;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+#pragma unroll
+          for (int k = 0; k < kDim[t]; ++k) {
+            const int64_t e = (int64_t)kDim[t] * li + k;
+            par[t][e] = P[at + k];
+            pm[t][e] = Mo[at + k];
+            pv2[t][e] = Vo[at + k];
+          }
+          at += kDim[t];
+        }
       }
     }
   }
@@ -405,6 +442,14 @@ __global__ __launch_bounds__(256) void k_pose_reduce(Batch B, WsPtrs W) {
 
 }  // namespace
 
+template <int NV, bool ADAM>
+static void gauss_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st) {
+  if (b.n_sessions == 1)
+    k_gauss_bwd<NV, ADAM, true><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+  else
+    k_gauss_bwd<NV, ADAM, false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+}
+
 hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags, hipStream_t st,
                                  StageTimer* tm) {
   if (b.n_total > 0) {
@@ -418,11 +463,11 @@ hipError_t launch_preprocess_bwd(const Batch& b, const WsPtrs& w, int grad_flags
   if (b.b_total > 0) {
     Scope sc(tm, kStPreprocessBwd, st);
     if (grad_flags & RTGS_GRAD_ADAM)
-      k_gauss_bwd<10, true><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+      gauss_bwd<10, true>(b, w, grad_flags, st);
     else if (grad_flags & RTGS_GRAD_MAP)
-      k_gauss_bwd<10, false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+      gauss_bwd<10, false>(b, w, grad_flags, st);
     else
-      k_gauss_bwd<6, false><<<b.b_total, kGaussPerBlock, 0, st>>>(b, w, grad_flags);
+      gauss_bwd<6, false>(b, w, grad_flags, st);
   }
   if ((grad_flags & RTGS_GRAD_POSE) && b.n_sessions > 0) {
     Scope sc(tm, kStPoseReduce, st);

@@ -58,10 +58,13 @@ __device__ __forceinline__ int quadrant_sample() {
 }
 
 // sidx: the thread's sample of the tile, row-major 0..255.
+template <bool ONE>
 __device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile, int sidx) {
   TileCtx c;
-  c.s = find_session(B.sess, B.n_sessions, tile, [](const SessionDev& x) { return x.tile_base; });
-  const SessionDev& S = session_of(B, c.s);
+  c.s = ONE ? 0
+            : find_session(B.sess, B.n_sessions, tile,
+                           [](const SessionDev& x) { return x.tile_base; });
+  const SessionDev& S = batch_session<ONE>(B, c.s);
   c.lt = tile - S.tile_base;
   c.tile_x0 = (c.lt % S.tiles_x) << (4 + S.sub_sx);
   c.tile_y0 = (c.lt / S.tiles_x) << (4 + S.sub_sy);
@@ -220,7 +223,7 @@ __device__ __forceinline__ int lane_schedule(const SessionDev& S, const WsPtrs& 
 // FRAG: also save the fragments' alpha (see frag_base).
 // BAL: lanes assigned by previous work (lane_schedule); also writes each
 // sample's walked entries to S.lane_work_out for the next forward.
-template <bool STATS, bool FRAG, bool BAL>
+template <bool STATS, bool FRAG, bool BAL, bool ONE>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock];
   __shared__ unsigned s_m[kBlock];
@@ -231,12 +234,12 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
   if (tile >= B.t_total) return;
   int sidx = quadrant_sample();
   if (BAL) {
-    const TileCtx c0 = tile_ctx(B, tile, sidx);
-    sidx = lane_schedule(session_of(B, c0.s), W, tile, c0.tile_x0, c0.tile_y0, s_key, s_pix,
-                         s_box);
+    const TileCtx c0 = tile_ctx<ONE>(B, tile, sidx);
+    sidx = lane_schedule(batch_session<ONE>(B, c0.s), W, tile, c0.tile_x0, c0.tile_y0, s_key,
+                         s_pix, s_box);
   }
-  const TileCtx c = tile_ctx(B, tile, sidx);
-  const SessionDev& S = session_of(B, c.s);
+  const TileCtx c = tile_ctx<ONE>(B, tile, sidx);
+  const SessionDev& S = batch_session<ONE>(B, c.s);
   const int tid = threadIdx.x;
   const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);
   const float pxf = (float)c.px + 0.5f, pyf = (float)c.py + 0.5f;
@@ -325,6 +328,14 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     S.lane_work_out[c.by0 * S.width + c.bx0] = (uint16_t)min(walked, 65535);
   }
   const int64_t hw = (int64_t)S.width * S.height;
+  // loss gradient (Eq. 6, L1 colour and depth, means over the active pixels):
+  // the arithmetic of the separate loss pass on the values written here
+  float l1_sc = 0.f, l1_sd = 0.f;
+  if (S.l1_dcolor) {
+    const float n = S.l1_n_active ? fmaxf((float)*S.l1_n_active, 1.f) : (float)hw;
+    l1_sc = S.l1_w_color / (3.f * n);
+    l1_sd = S.l1_w_depth / n;
+  }
   // every pixel of the lane's block: the sample gets its result, the others
   // (masked out) render as background
   const int x1 = min(S.width, c.bx0 + (1 << S.sub_sx));
@@ -337,6 +348,14 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         S.color[p] = me ? C0 : 0.f;
         S.color[hw + p] = me ? C1 : 0.f;
         S.color[2 * hw + p] = me ? C2 : 0.f;
+      }
+      if (S.l1_dcolor) {
+        const float m = S.pmask ? (S.pmask[p] ? 1.f : 0.f) : 1.f;
+        const float v[4] = {me ? C0 : 0.f, me ? C1 : 0.f, me ? C2 : 0.f, me ? D : 0.f};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          S.l1_dcolor[k * hw + p] = m * l1_sc * sign_of(v[k] - S.l1_tcolor[k * hw + p]);
+        S.l1_ddepth[p] = m * l1_sd * sign_of(v[3] - S.l1_tdepth[p]);
       }
       if (S.depth) S.depth[p] = me ? D : 0.f;
       if (S.alpha) S.alpha[p] = me ? 1.f - T : 0.f;
@@ -376,7 +395,7 @@ __device__ __forceinline__ int64_t pair_slot(const WsPtrs& W, uint32_t g, int tx
 // of the re-evaluating form.
 // BAL: the forward assigned lanes by previous work (lane_schedule); the same
 // samples go to the same lanes here (the saved quadrant bits are per wave).
-template <int NV, bool GA, bool FRAG, bool BAL>
+template <int NV, bool GA, bool FRAG, bool BAL, bool ONE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_raster_bwd(Batch B, WsPtrs W) {
   constexpr int kStride = NV + 1;          // odd stride: conflict-free epilogue reads
@@ -392,8 +411,8 @@ void k_raster_bwd(Batch B, WsPtrs W) {
   const int tile = tile_of_block(B.t_total);
   if (tile >= B.t_total) return;
   const int sidx = BAL ? (int)W.lane_perm[(int64_t)tile * kBlock + threadIdx.x] : quadrant_sample();
-  const TileCtx c = tile_ctx(B, tile, sidx);
-  const SessionDev& S = session_of(B, c.s);
+  const TileCtx c = tile_ctx<ONE>(B, tile, sidx);
+  const SessionDev& S = batch_session<ONE>(B, c.s);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ltx = c.lt % S.tiles_x, lty = c.lt / S.tiles_x;
   const bool active = c.has && (S.pmask == nullptr || S.pmask[c.pix] != 0);
@@ -617,14 +636,16 @@ static void raster_fwd_variant(const Batch& b, const WsPtrs& w, bool frags, bool
                                hipStream_t st) {
   if (frags) {
     if (bal)
-      k_raster_fwd<STATS, true, true><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_fwd<STATS, true, true, false><<<grid, kBlock, 0, st>>>(b, w);
     else
-      k_raster_fwd<STATS, true, false><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_fwd<STATS, true, false, false><<<grid, kBlock, 0, st>>>(b, w);
   } else {
     if (bal)
-      k_raster_fwd<STATS, false, true><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_fwd<STATS, false, true, false><<<grid, kBlock, 0, st>>>(b, w);
+    else if (b.n_sessions == 1)
+      k_raster_fwd<STATS, false, false, true><<<grid, kBlock, 0, st>>>(b, w);
     else
-      k_raster_fwd<STATS, false, false><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_fwd<STATS, false, false, false><<<grid, kBlock, 0, st>>>(b, w);
   }
 }
 
@@ -645,14 +666,16 @@ static void raster_bwd_variant(const Batch& b, const WsPtrs& w, bool frags, bool
                                hipStream_t st) {
   if (frags) {
     if (bal)
-      k_raster_bwd<NV, GA, true, true><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_bwd<NV, GA, true, true, false><<<grid, kBlock, 0, st>>>(b, w);
     else
-      k_raster_bwd<NV, GA, true, false><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_bwd<NV, GA, true, false, false><<<grid, kBlock, 0, st>>>(b, w);
   } else {
     if (bal)
-      k_raster_bwd<NV, GA, false, true><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_bwd<NV, GA, false, true, false><<<grid, kBlock, 0, st>>>(b, w);
+    else if (b.n_sessions == 1)
+      k_raster_bwd<NV, GA, false, false, true><<<grid, kBlock, 0, st>>>(b, w);
     else
-      k_raster_bwd<NV, GA, false, false><<<grid, kBlock, 0, st>>>(b, w);
+      k_raster_bwd<NV, GA, false, false, false><<<grid, kBlock, 0, st>>>(b, w);
   }
 }
 

@@ -53,6 +53,13 @@ struct SessionDev {
   int32_t* stats;       // [3][H][W] or null: blended, entries visited, entries to last
   const uint16_t* lane_work;  // [H][W] entries walked per sample in a previous forward, or null
   uint16_t* lane_work_out;    // [H][W] this forward's, or null
+  // loss gradient written by the forward (l1_dcolor null: none)
+  const float* l1_tcolor;
+  const float* l1_tdepth;
+  const int32_t* l1_n_active;
+  float* l1_dcolor;
+  float* l1_ddepth;
+  float l1_w_color, l1_w_depth;
   // backward
   const float* dl_color;
   const float* dl_depth;
@@ -335,9 +342,26 @@ __device__ __forceinline__ int find_session(const SessionDev* s, int n, int key,
   return lo;
 }
 
+// Sign of the L1 loss derivative: 1, -1, or 0 where the residual is 0.
+__device__ __forceinline__ float sign_of(float x) {
+  return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f);
+}
+
 // Session s of a batch.
 __device__ __forceinline__ const SessionDev& session_of(const Batch& B, int s) {
   return B.n_sessions == 1 ? B.one : B.sess[s];
+}
+
+// Session s of a batch, for kernels instantiated per batch kind.  ONE (the
+// host launches it only for a batch of one session): the session is read
+// from the launch arguments, and the compiler then reads its fields with
+// scalar loads, which it may issue early and keep, since no store of the
+// kernel can reach the arguments.  Otherwise session_of, whose reference may
+// point either there or into the device table, so that each field becomes a
+// vector load that waits behind every earlier store.
+template <bool ONE>
+__device__ __forceinline__ const SessionDev& batch_session(const Batch& B, int s) {
+  return ONE ? B.one : session_of(B, s);
 }
 
 // DPP control words (GFX9 encoding).

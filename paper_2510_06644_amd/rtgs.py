@@ -91,6 +91,11 @@ class CMapAdam(ctypes.Structure):
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
+class CL1Loss(ctypes.Structure):
+    _fields_ = [("target_color", vp), ("target_depth", vp), ("n_active_dev", vp),
+                ("w_color", f32), ("w_depth", f32), ("dL_dcolor", vp), ("dL_ddepth", vp)]
+
+
 class CSession(ctypes.Structure):
     _fields_ = [("g", CGaussians), ("cam", CCamera), ("pixel_mask", vp), ("sample_log2", i32),
                 ("color", vp), ("depth", vp), ("alpha", vp), ("final_T", vp), ("last_idx", vp),
@@ -98,7 +103,7 @@ class CSession(ctypes.Structure):
                 ("g_means", vp), ("g_log_scales", vp), ("g_quats", vp),
                 ("g_opacity_logits", vp), ("g_colors", vp), ("g_pose6", vp), ("g_viewmat", vp),
                 ("g_cov3d", vp), ("lane_work", vp), ("lane_work_out", vp),
-                ("adam", ctypes.POINTER(CMapAdam))]
+                ("adam", ctypes.POINTER(CMapAdam)), ("l1", ctypes.POINTER(CL1Loss))]
 
 
 class CPoseItem(ctypes.Structure):
@@ -308,9 +313,10 @@ def render_bwd(handle, means, log_scales, quats, opacity_logits, colors, viewmat
 def session_struct(it):
     """One CSession from a dict with the keys of CSession (tensors or None)
     plus 'scene' (means, log_scales, quats, opacity_logits, colors),
-    'viewmat', 'cam' (Cam), optional 'gauss_mask', 'sample_log2' and 'adam'
-    (a CMapAdam, e.g. MapAdam.fused()).  The struct holds raw pointers: the
-    tensors and the CMapAdam must outlive its use."""
+    'viewmat', 'cam' (Cam), optional 'gauss_mask', 'sample_log2', 'adam'
+    (a CMapAdam, e.g. MapAdam.fused()) and 'l1' (a CL1Loss, l1_loss()).  The
+    struct holds raw pointers: the tensors and the CMapAdam / CL1Loss must
+    outlive its use."""
     s = CSession()
     s.g = _gauss(*it["scene"], it.get("gauss_mask"))
     s.cam = _cam(it["cam"], it["viewmat"])
@@ -323,7 +329,22 @@ def session_struct(it):
         setattr(s, name, _p(it.get(name)))
     if it.get("adam") is not None:
         s.adam = ctypes.pointer(it["adam"])
+    if it.get("l1") is not None:
+        s.l1 = ctypes.pointer(it["l1"])
     return s
+
+
+def l1_loss(target_color, target_depth, dL_dcolor, dL_ddepth, n_active=None, w_color=1.0,
+            w_depth=0.5):
+    """A CL1Loss: the forward of a session carrying it also writes the
+    gradients loss_l1_grad would (same arguments, the forward's own colour,
+    depth and pixel mask).  The tensors must outlive its use."""
+    _, h, w = target_color.shape
+    for t, shp in ((target_color, (3, h, w)), (dL_dcolor, (3, h, w)), (target_depth, (h, w)),
+                   (dL_ddepth, (h, w))):
+        _f32(t, shp)
+    return CL1Loss(_p(target_color), _p(target_depth), _p(n_active), float(w_color),
+                   float(w_depth), _p(dL_dcolor), _p(dL_ddepth))
 
 
 def make_sessions(items):
@@ -640,7 +661,8 @@ class Renderer:
     # ------------------------------------------------------------------ managed calls
     def forward(self, scene, viewmat, cam: Cam, gauss_mask=None, pixel_mask=None,
                 save_state=True, stream=None, sample_log2=0, reuse_lists_of=None,
-                save_fragments=False, balance=False, lane_work=None, lane_work_out=None):
+                save_fragments=False, balance=False, lane_work=None, lane_work_out=None,
+                l1=None):
         """Render one frame; returns a FwdState (outputs + the workspace the
         matching backward needs).  Each forward gets its own workspace from
         torch's caching allocator, so several forwards may await backward.
@@ -657,7 +679,11 @@ class Renderer:
         balance: assign each wave's lanes the samples of similar previous work
         (lane_work, uint16 [H, W], the lane_work_out of an earlier balanced
         forward of this geometry, or None) and write this forward's work to
-        lane_work_out (or None)."""
+        lane_work_out (or None).
+
+        l1: (target_color, target_depth, n_active or None[, w_color, w_depth])
+        to have the forward also write the loss gradients (FwdState.dL_dcolor,
+        .dL_ddepth) that loss_l1_grad would compute from its image."""
         n = scene[0].shape[0]
         if save_fragments and (not save_state or reuse_lists_of is not None):
             raise ValueError("save_fragments needs save_state and a full forward")
@@ -665,6 +691,8 @@ class Renderer:
         dev = scene[0].device
         h, w = cam.height, cam.width
         if reuse_lists_of is not None:
+            if l1 is not None:
+                raise ValueError("l1 takes a forward that bins (no reuse_lists_of)")
             ref = reuse_lists_of
             if (ref.n, ref.cam.width, ref.cam.height, ref.sample_log2) != (n, w, h, sample_log2):
                 raise ValueError("reuse_lists_of: different frame geometry")
@@ -683,6 +711,11 @@ class Renderer:
                        flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | RTGS_FWD_REUSE_LISTS
                        | (int(sample_log2) << RTGS_SAMPLE_SHIFT), stream=stream)
             return out
+        l1s = None
+        if l1 is not None:
+            tc, td, cnt, *wts = l1
+            gc, gd = torch.empty(3, h, w, device=dev), torch.empty(h, w, device=dev)
+            l1s = l1_loss(tc, td, gc, gd, cnt, *wts)
         est = int(self.ppg * n) + 4 * _tiles(w, h)
         cap = max(self.cap, est, self.min_cap)
         while True:
@@ -697,16 +730,18 @@ class Renderer:
                            last_idx=(torch.empty(h, w, dtype=torch.int32, device=dev)
                                      if save_state else None),
                            visible=torch.empty(n, dtype=torch.uint8, device=dev))
-            if balance:
-                out.balanced = True
+            if l1s is not None:
+                out.dL_dcolor, out.dL_ddepth = gc, gd
+            if balance or l1s is not None:
+                out.balanced = balance
                 render_fwd_batched(self.handle, [dict(
                     scene=scene, viewmat=viewmat, cam=cam, gauss_mask=gauss_mask,
                     pixel_mask=pixel_mask, sample_log2=sample_log2, color=out.color,
                     depth=out.depth, alpha=out.alpha, final_T=out.final_T,
                     last_idx=out.last_idx, visible=out.visible, lane_work=lane_work,
-                    lane_work_out=lane_work_out)], ws, cap,
+                    lane_work_out=lane_work_out, l1=l1s)], ws, cap,
                     flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | fflag
-                    | RTGS_FWD_BALANCE_LANES, stream=stream)
+                    | (RTGS_FWD_BALANCE_LANES if balance else 0), stream=stream)
             else:
                 render_fwd(self.handle, *scene, viewmat, cam, ws, cap, out.color, out.depth,
                            out.alpha, out.final_T, out.last_idx, out.visible,
@@ -821,6 +856,8 @@ class FwdState:
     pairs: int = -1
     frags: bool = False
     balanced: bool = False
+    dL_dcolor: torch.Tensor | None = None   # loss gradients written by the forward (l1=)
+    dL_ddepth: torch.Tensor | None = None
 
     def stage(self):
         """Forward intermediates for tests: dict of numpy arrays."""
