@@ -18,7 +18,7 @@ constexpr float kTMin = 1e-4f;              // early-termination transmittance
 constexpr double kNearZ = 0.2;
 constexpr double kDilation = 0.3;
 constexpr double kFovClamp = 1.3;
-constexpr int kChunk = 1024;              // Gaussians per binning chunk (4 per thread)
+constexpr int kChunk = 1024;              // Gaussians per binning chunk (1 per thread)
 constexpr int kMaxTilesPerSession = 12288; // LDS tile histogram of one session (48 KB)
 
 // Adam state of a session's map for an update fused into the backward
