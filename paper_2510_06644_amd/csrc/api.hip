@@ -134,6 +134,7 @@ WsLayout make_layout(const Counts& c, int64_t cap, bool frags) {
   L.rect = take(16 * n);
   L.cnt = take(4 * n);
   L.goff = take(4 * n);
+  L.zkey = take(4 * n);
   L.grad2d = take(40 * n);
   L.pose_part = take(128 * (uint64_t)c.b_total);
   L.chunk_total = take(4 * (uint64_t)(c.c_total + 1));
@@ -173,6 +174,7 @@ WsPtrs ws_ptrs(void* ws, const WsLayout& L) {
   w.rect = reinterpret_cast<int4*>(base + L.rect);
   w.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
   w.goff = reinterpret_cast<uint32_t*>(base + L.goff);
+  w.zkey = reinterpret_cast<uint32_t*>(base + L.zkey);
   w.grad2d = reinterpret_cast<float*>(base + L.grad2d);
   w.pose_part = reinterpret_cast<double*>(base + L.pose_part);
   w.chunk_total = reinterpret_cast<uint32_t*>(base + L.chunk_total);

@@ -163,6 +163,9 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
     return;
   }
   W.rect[gid] = rect;
+  // the depth bits of the Gaussian's sort key, read by the emit from this
+  // dense array rather than from the 64-byte records
+  W.zkey[gid] = __float_as_uint((float)P.z);
   const bool vis = rect.z >= rect.x;
   if (S.visible) S.visible[li] = vis ? 1 : 0;
   W.cnt[gid] = vis ? (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1)) : 0u;
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   stage_rects(S, W, c, s_rect);
   for (int i = threadIdx.x; i < kChunk; i += kBinThreads) {
     const int li = c * kChunk + i;
-    s_zb[i] = li < S.n ? __float_as_uint(W.rec[S.gauss_base + li].col.w) : 0u;
+    s_zb[i] = li < S.n ? W.zkey[S.gauss_base + li] : 0u;
   }
   const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
   const uint32_t base = W.chunk_off[blockIdx.x];

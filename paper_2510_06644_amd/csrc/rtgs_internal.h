@@ -98,6 +98,7 @@ struct WsLayout {
   uint64_t rect;        // int4[N]: tile rectangle
   uint64_t cnt;         // uint32[N]: tiles touched
   uint64_t goff;        // uint32[N]: first slot of the Gaussian's pairs, Gaussian-major
+  uint64_t zkey;        // uint32[N]: depth bits of the Gaussian's sort key (projection)
   uint64_t grad2d;      // float[N][10]: merged dL/d(u, v, a, b, c, o, r, g, b, z)
   uint64_t pose_part;   // double[B][16]: per-block view-matrix gradient partial sums
   uint64_t chunk_total; // uint32[C + 1]: pairs per chunk
@@ -152,6 +153,7 @@ struct WsPtrs {
   int4* rect;
   uint32_t* cnt;
   uint32_t* goff;
+  uint32_t* zkey;
   float* grad2d;
   double* pose_part;
   uint32_t* chunk_total;
