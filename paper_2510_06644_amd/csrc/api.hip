@@ -405,9 +405,13 @@ int32_t upload_table(rtgs_handle_t h, const rtgs_session* ss, int ns, const WsPt
     if (ts > tmax) tmax = ts;
     pbase += (int64_t)s.cam.width * s.cam.height;
   }
-  // one session travels in the launch arguments (Batch::one); a table is
-  // uploaded only for several
-  if (ns > 1) {
+  // one session travels in the launch arguments (Batch::one); the table is
+  // uploaded for several, and for the raster variants that read it whatever
+  // the count (saved fragments, lanes by previous work)
+  const bool table = ns > 1 ||
+                     (fwd ? (flags & (RTGS_FWD_SAVE_FRAGMENTS | RTGS_FWD_BALANCE_LANES)) != 0
+                          : (flags & (RTGS_GRAD_SAVED_FRAGMENTS | RTGS_GRAD_BALANCED_LANES)) != 0);
+  if (table) {
     e = hipMemcpyAsync(w.table, t, sizeof(SessionDev) * ns, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(session table)");
   }

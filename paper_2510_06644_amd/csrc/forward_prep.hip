@@ -105,7 +105,7 @@ __device__ __forceinline__ void split(double x, float& hi, float& lo) {
 // raster records are recomputed for the current pose.
 template <bool REUSE, bool ONE>
 __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W) {
-  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+  const int s = ONE ? 0 : find_session(session_table(B), B.n_sessions, (int)blockIdx.x,
                                          [](const SessionDev& x) { return x.block_base; });
   const SessionDev& S = batch_session<ONE>(B, s);
   const int li = ((int)blockIdx.x - S.block_base) * kGaussPerBlock + (int)threadIdx.x;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   __shared__ uint32_t s_off[kChunk + 1];
   __shared__ int4 s_rect[kChunk];
   __shared__ uint32_t s_wave[kBinThreads / 64];
-  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+  const int s = ONE ? 0 : find_session(session_table(B), B.n_sessions, (int)blockIdx.x,
                                          [](const SessionDev& x) { return x.chunk_base; });
   const SessionDev& S = batch_session<ONE>(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_group_sums(Batch B, WsPtrs W) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int g = blockIdx.y;
   if (t >= B.t_total) return;
-  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, t,
+  const int s = ONE ? 0 : find_session(session_table(B), B.n_sessions, t,
                                          [](const SessionDev& x) { return x.tile_base; });
   const SessionDev& S = batch_session<ONE>(B, s);
   const int ts = S.tiles_x * S.tiles_y;
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   __shared__ int4 s_rect[kChunk];
   __shared__ uint32_t s_zb[kChunk];
   __shared__ uint32_t s_wave[kBinThreads / 64];
-  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+  const int s = ONE ? 0 : find_session(session_table(B), B.n_sessions, (int)blockIdx.x,
                                          [](const SessionDev& x) { return x.chunk_base; });
   const SessionDev& S = batch_session<ONE>(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
@@ -798,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_tiles(Batch B, WsPtrs W) {
   const uint32_t st = W.tile_start[t];
   const int n = (int)(W.tile_start[t + 1] - st);   // all empty after an overflow
   if (n <= 0) return;
-  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, t,
+  const int s = ONE ? 0 : find_session(session_table(B), B.n_sessions, t,
                                          [](const SessionDev& x) { return x.tile_base; });
   const SessionDev& S = batch_session<ONE>(B, s);
   if (n > kSortPerThread * kBlock) {

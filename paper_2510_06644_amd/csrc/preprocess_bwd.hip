@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_merge(Batch B, WsPtrs W) {
 template <int NV, bool ADAM, bool ONE>
 __global__ __launch_bounds__(kGaussPerBlock) void k_gauss_bwd(Batch B, WsPtrs W, int flags) {
   __shared__ double s_red[kGaussPerBlock / 64][12];
-  const int s = ONE ? 0 : find_session(B.sess, B.n_sessions, (int)blockIdx.x,
+  const int s = ONE ? 0 : find_session(session_table(B), B.n_sessions, (int)blockIdx.x,
                                        [](const SessionDev& x) { return x.block_base; });
   const SessionDev& S = batch_session<ONE>(B, s);
   const int li0 = ((int)blockIdx.x - S.block_base) * kGaussPerBlock;

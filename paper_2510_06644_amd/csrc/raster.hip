@@ -62,7 +62,7 @@ template <bool ONE>
 __device__ __forceinline__ TileCtx tile_ctx(const Batch& B, int tile, int sidx) {
   TileCtx c;
   c.s = ONE ? 0
-            : find_session(B.sess, B.n_sessions, tile,
+            : find_session(session_table(B), B.n_sessions, tile,
                            [](const SessionDev& x) { return x.tile_base; });
   const SessionDev& S = batch_session<ONE>(B, c.s);
   c.lt = tile - S.tile_base;

@@ -354,16 +354,25 @@ __device__ __forceinline__ const SessionDev& session_of(const Batch& B, int s) {
   return B.n_sessions == 1 ? B.one : B.sess[s];
 }
 
+// The device session table seen through the constant address space: the
+// kernels never write it, and read through such a pointer its uniform fields
+// become scalar loads (through session_of's reference, which may point into
+// the launch arguments or the table, each is a vector load that waits behind
+// every earlier store).  Valid when the host uploaded the table (see
+// batch_session).
+__device__ __forceinline__ const SessionDev* session_table(const Batch& B) {
+  typedef const __attribute__((address_space(4))) SessionDev ConstSession;
+  return (const SessionDev*)(ConstSession*)B.sess;
+}
+
 // Session s of a batch, for kernels instantiated per batch kind.  ONE (the
 // host launches it only for a batch of one session): the session is read
-// from the launch arguments, and the compiler then reads its fields with
-// scalar loads, which it may issue early and keep, since no store of the
-// kernel can reach the arguments.  Otherwise session_of, whose reference may
-// point either there or into the device table, so that each field becomes a
-// vector load that waits behind every earlier store.
+// from the launch arguments.  Otherwise from the table, which the host then
+// uploads (also for one session).  Either way its fields are read with scalar
+// loads.
 template <bool ONE>
 __device__ __forceinline__ const SessionDev& batch_session(const Batch& B, int s) {
-  return ONE ? B.one : session_of(B, s);
+  return ONE ? B.one : session_table(B)[s];
 }
 
 // DPP control words (GFX9 encoding).
