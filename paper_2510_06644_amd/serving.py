@@ -30,6 +30,7 @@ a GPU).
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import heapq
 import math
@@ -563,7 +564,7 @@ class GpuExecutor:
 
     def __init__(self, device=0, lr_pose=(1e-3, 3e-3), track_noise_seed=0, n_targets=4,
                  capacity_factor=2.0, prune=False, prune_ratio=0.1, prune_cap=0.5,
-                 prune_lam=0.8, record_poses=False):
+                 prune_lam=0.8, record_poses=False, fused=True):
         import torch
 
         from . import rtgs
@@ -583,6 +584,10 @@ class GpuExecutor:
         # visible Gaussians for the frame's other iterations; a keyframe's
         # map job removes the Gaussians its keyframe masked, never more than
         # prune_cap of the initial map in all
+        # fused: the forward writes the loss gradient and map jobs update their
+        # maps inside the backward; otherwise a loss pass and adam_step (the
+        # same results, bit for bit)
+        self.fused = fused
         self.prune = prune
         self.prune_ratio = prune_ratio
         self.prune_cap = prune_cap
@@ -712,10 +717,17 @@ class GpuExecutor:
             x.g_cov3d = torch.empty(n, 6, device=self.dev)   # read when some job scores
             it.update(g_means=x.grads[0], g_log_scales=x.grads[1], g_quats=x.grads[2],
                       g_opacity_logits=x.grads[3], g_colors=x.grads[4], g_cov3d=x.g_cov3d)
+        # L1 colour + 0.5 L1 depth over the active pixels, its gradient written
+        # by the forward as it writes the image (or by a loss pass)
+        if self.fused:
+            x.l1c = rtgs.l1_loss(x.target[0], x.target[1], x.gc, x.gd,
+                                 x.pcount if x.mask is not None else None, 1.0, 0.5)
+            it["l1"] = x.l1c
+        else:
+            x.cl = rtgs.loss_item(o["color"], o["depth"], x.target[0], x.target[1], x.gc, x.gd,
+                                  x.mask, x.pcount if x.mask is not None else None)
         x.keep = it
         x.cs = rtgs.session_struct(it)
-        x.cl = rtgs.loss_item(o["color"], o["depth"], x.target[0], x.target[1], x.gc, x.gd,
-                              x.mask, x.pcount if x.mask is not None else None)
         x.n = n
         x.phase_bound = phase
 
@@ -764,7 +776,7 @@ class GpuExecutor:
         if self.record_poses:
             self.frame_poses[(f.session, f.index)] = f.viewmat
         S["inflight"] -= 1
-        f.gmask = f.cs = f.cl = f.cp = f.keep = f.grads = None
+        f.gmask = f.cs = f.l1c = f.cl = f.cp = f.keep = f.grads = None
 
     def start_map(self, job, spec):
         """A keyframe's map job: version v + 1 starts as a copy of the latest
@@ -790,9 +802,20 @@ class GpuExecutor:
         job.visible = torch.empty(new[0].shape[0], dtype=torch.uint8, device=self.dev)
         job.out = S["out_map"]
         self._bind(job, S, spec, new, "map")
-        job.ca = (rtgs.CAdamGroup * len(new))(*[
-            rtgs.adam_group(p, g, m, v, lr) for p, g, m, v, lr in
-            zip(new, job.grads, opt.exp_avg, opt.exp_avg_sq, opt.lrs)])
+        if not self.fused:
+            job.ca = (rtgs.CAdamGroup * len(new))(*[
+                rtgs.adam_group(p, g, m, v, lr) for p, g, m, v, lr in
+                zip(new, job.grads, opt.exp_avg, opt.exp_avg_sq, opt.lrs)])
+            return
+        # the job's Adam update runs inside its backward (RTGS_GRAD_ADAM,
+        # bitwise the update of adam_step), so its map gradients need not be
+        # written, except dL/dmu while the job scores its map (dL/dSigma stays:
+        # a launch in which another job scores asks every session for it)
+        job.cadam = opt.fused()
+        job.cs.adam = ctypes.pointer(job.cadam)
+        job.cs.g_log_scales = job.cs.g_quats = job.cs.g_opacity_logits = job.cs.g_colors = None
+        if not job.first:
+            job.cs.g_means = None
 
     def _remove_masked(self, S, job):
         """Permanent removal of the Gaussians the job masked (stable
@@ -825,7 +848,7 @@ class GpuExecutor:
         S["version"] += 1
         S["versions"][S["version"]] = job.params
         S["params"] = job.params
-        job.cs = job.cl = job.ca = job.keep = job.grads = None
+        job.cs = job.l1c = job.cl = job.ca = job.cadam = job.keep = job.grads = None
 
     def release_versions(self, s, keep_from):
         """Forget map versions below keep_from (frames that render them hold
@@ -849,11 +872,11 @@ class GpuExecutor:
         ws = torch.empty(rtgs.rtgs_workspace_size_batched(
             [x.n for x in frames], [x.out["depth"].shape[1] for x in frames],
             [x.out["depth"].shape[0] for x in frames], cap), dtype=torch.uint8, device=self.dev)
+        # the forward also writes each frame's loss gradient (its session's l1)
         rtgs.render_fwd_batched_c(self.handle, arr, k, ws, cap, rtgs.RTGS_FWD_SAVE_STATE, st)
-        # L1 colour + 0.5 L1 depth over the active pixels of each frame, one
-        # launch for the group
-        rtgs.loss_l1_grad_batched_c((rtgs.CLossItem * k)(*[x.cl for x in frames]), k, 1.0, 0.5,
-                                    st)
+        if not self.fused:                  # one loss launch for the group
+            rtgs.loss_l1_grad_batched_c((rtgs.CLossItem * k)(*[x.cl for x in frames]), k, 1.0,
+                                        0.5, st)
         scoring = [x for x in frames if x.first]
         if phase == "track":
             flags = rtgs.RTGS_GRAD_POSE | (rtgs.RTGS_GRAD_SCORE if scoring else 0)
@@ -865,11 +888,20 @@ class GpuExecutor:
             rtgs.pose_update_c((rtgs.CPoseItem * k)(*[f.cp for f in frames]), k, 0.9, 0.999,
                                1e-8, st)
         else:
-            flags = rtgs.RTGS_GRAD_MAP | (rtgs.RTGS_GRAD_COV3D if scoring else 0)
+            # map jobs update their maps inside the backward; frames that map
+            # in line take one adam_step launch for every session of the group
+            fused = [x for x in frames if getattr(x, "cadam", None) is not None]
+            flags = (rtgs.RTGS_GRAD_MAP | (rtgs.RTGS_GRAD_COV3D if scoring else 0)
+                     | (rtgs.RTGS_GRAD_ADAM if fused else 0))
+            for x in fused:                          # read by the call through x.cs.adam
+                x.cadam.step = self.sessions[x.session]["opt"].t + 1
             rtgs.render_bwd_batched_c(self.handle, arr, k, ws, cap, flags, st)
-            # one update launch for the maps of every session of the group
+            for x in fused:
+                self.sessions[x.session]["opt"].t += 1
             groups = []
             for x in frames:
+                if getattr(x, "cadam", None) is not None:
+                    continue
                 opt = getattr(x, "opt", None) or self.sessions[x.session]["opt"]
                 if getattr(x, "ca", None) is None:            # in-line mapping of a frame
                     x.ca = (rtgs.CAdamGroup * len(x.params))(*[
@@ -879,8 +911,9 @@ class GpuExecutor:
                 for grp in x.ca:
                     grp.step = opt.t
                     groups.append(grp)
-            rtgs.adam_step_c(self.handle, (rtgs.CAdamGroup * len(groups))(*groups), len(groups),
-                             0.9, 0.999, 1e-15, st)
+            if groups:
+                rtgs.adam_step_c(self.handle, (rtgs.CAdamGroup * len(groups))(*groups),
+                                 len(groups), 0.9, 0.999, 1e-15, st)
         for x in scoring:
             self._mask_lowest(self.sessions[x.session], x)
             x.first = False
@@ -915,6 +948,8 @@ class GpuExecutor:
             x.cs.g_means = None
             x.cs.g_cov3d = None
             x.g_means = x.g_cov3d = None
+        elif getattr(x, "cadam", None) is not None:   # a fused job needs dL/dmu no more
+            x.cs.g_means = None
 
     # ---- clock ----------------------------------------------------------------
     def clock(self):

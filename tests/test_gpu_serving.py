@@ -182,3 +182,37 @@ def test_served_algorithm_is_the_same_alone_and_in_the_mix():
         for x, y in zip(A["opt"].exp_avg + A["opt"].exp_avg_sq,
                         B["opt"].exp_avg + B["opt"].exp_avg_sq):
             assert torch.equal(x, y)
+
+
+def test_served_algorithm_with_fused_launches_equals_unfused():
+    """The executor's fused form (the forward writes the loss gradient, map
+    jobs update their maps inside the backward) serves the same algorithm as
+    its unfused form (a loss pass, the backward's gradients, adam_step): every
+    frame's end pose and every session's final map and Adam moments bitwise
+    equal, with pruning, downsampling and background keyframe mapping."""
+    say("test_served_algorithm_with_fused_launches_equals_unfused")
+    specs = [SessionSpec(320, 240, 20_000, "c0", 60 + k) for k in range(3)]
+    trace = serving.poisson_trace(len(specs), 60.0, 0.4, 19)
+    out = {}
+    for fused in (False, True):
+        ex = GpuExecutor(0, n_targets=2, prune=True, prune_ratio=0.2, record_poses=True,
+                         fused=fused)
+        eng = Engine(specs, ex, ServeConfig(mode="batched", **SERVED))
+        rep = eng.run(trace)
+        ex.verify()
+        assert ex.overflows == 0 and rep["frames"] == len(trace)
+        say(f"  fused={fused}: {rep['frames']} frames, {rep['map_jobs']} map jobs")
+        out[fused] = ex
+    a, b = out[False], out[True]
+    assert a.frame_poses.keys() == b.frame_poses.keys()
+    for k in a.frame_poses:
+        assert torch.equal(a.frame_poses[k], b.frame_poses[k]), k
+    for s in range(len(specs)):
+        A, B = a.sessions[s], b.sessions[s]
+        assert A["version"] == B["version"] > 0
+        assert A["removed"] == B["removed"] > 0
+        for x, y in zip(A["params"], B["params"]):
+            assert torch.equal(x, y)
+        for x, y in zip(A["opt"].exp_avg + A["opt"].exp_avg_sq,
+                        B["opt"].exp_avg + B["opt"].exp_avg_sq):
+            assert torch.equal(x, y)
