@@ -574,8 +574,9 @@ def state_policy_run(iters=10):
 def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False, mask_prune=False):
     """Tracking at 640x480 with 100k Gaussians: the map frozen, the camera
     starting 2 cm / 1 degree off the pose its target frame was rendered
-    from; each iteration is render_fwd, the loss gradient, render_bwd to the
-    pose only and pose_update (Adam on xi, then T <- Exp(-step) T).
+    from; each iteration is render_fwd (which also writes the loss gradient),
+    render_bwd to the pose only and pose_update (Adam on xi, then
+    T <- Exp(-step) T).
     reuse_lists: iterations after the first reuse its tile lists and depth
     order (projection only; Sec. 3, Observation 6).
     mask_prune: the mask-prune schedule of Sec. 4.1 (prune.MaskPruneTracker:
@@ -614,11 +615,12 @@ def tracking_run(iters=40, lr_rho=1e-3, lr_phi=1e-3, reuse_lists=False, mask_pru
                 rtgs.pose_update([(view, g, m, v, lr_rho, lr_phi, it)])
             return
         for it in range(1, n + 1):
-            st = R.forward(scene, view, rc, reuse_lists_of=first)
+            # the forward also writes the loss gradient (as the mapping step's)
+            st = R.forward(scene, view, rc, reuse_lists_of=first, l1=(tc, td, None))
             if reuse_lists and first is None:
                 first = st
-            gc, gd = l1_grads(st.color, st.depth, tc, td)
-            g = R.backward(scene, view, rc, st, gc, gd, pose=True, map_grads=False)
+            g = R.backward(scene, view, rc, st, st.dL_dcolor, st.dL_ddepth, pose=True,
+                           map_grads=False)
             rtgs.pose_update([(view, g["pose"], m, v, lr_rho, lr_phi, it)])
 
     run(start.clone(), 3)                      # warm-up (first launches)

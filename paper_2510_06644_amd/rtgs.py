@@ -690,9 +690,12 @@ class Renderer:
         fflag = RTGS_FWD_SAVE_FRAGMENTS if save_fragments else 0
         dev = scene[0].device
         h, w = cam.height, cam.width
+        l1s = None
+        if l1 is not None:
+            tc, td, cnt, *wts = l1
+            gc, gd = torch.empty(3, h, w, device=dev), torch.empty(h, w, device=dev)
+            l1s = l1_loss(tc, td, gc, gd, cnt, *wts)
         if reuse_lists_of is not None:
-            if l1 is not None:
-                raise ValueError("l1 takes a forward that bins (no reuse_lists_of)")
             ref = reuse_lists_of
             if (ref.n, ref.cam.width, ref.cam.height, ref.sample_log2) != (n, w, h, sample_log2):
                 raise ValueError("reuse_lists_of: different frame geometry")
@@ -705,17 +708,22 @@ class Renderer:
                                      if save_state else None),
                            visible=torch.empty(n, dtype=torch.uint8, device=dev),
                            pairs=ref.pairs)
+            if l1s is not None:
+                out.dL_dcolor, out.dL_ddepth = gc, gd
+                render_fwd_batched(self.handle, [dict(
+                    scene=scene, viewmat=viewmat, cam=cam, gauss_mask=gauss_mask,
+                    pixel_mask=pixel_mask, sample_log2=sample_log2, color=out.color,
+                    depth=out.depth, alpha=out.alpha, final_T=out.final_T,
+                    last_idx=out.last_idx, visible=out.visible, l1=l1s)], ref.ws, ref.cap,
+                    flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | RTGS_FWD_REUSE_LISTS,
+                    stream=stream)
+                return out
             render_fwd(self.handle, *scene, viewmat, cam, ref.ws, ref.cap, out.color, out.depth,
                        out.alpha, out.final_T, out.last_idx, out.visible, gauss_mask=gauss_mask,
                        pixel_mask=pixel_mask,
                        flags=(RTGS_FWD_SAVE_STATE if save_state else 0) | RTGS_FWD_REUSE_LISTS
                        | (int(sample_log2) << RTGS_SAMPLE_SHIFT), stream=stream)
             return out
-        l1s = None
-        if l1 is not None:
-            tc, td, cnt, *wts = l1
-            gc, gd = torch.empty(3, h, w, device=dev), torch.empty(h, w, device=dev)
-            l1s = l1_loss(tc, td, gc, gd, cnt, *wts)
         est = int(self.ppg * n) + 4 * _tiles(w, h)
         cap = max(self.cap, est, self.min_cap)
         while True:

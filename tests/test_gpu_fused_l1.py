@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2510_06644_amd import optim, rtgs, synth
+from paper_2510_06644_amd import optim, pose, rtgs, synth
 from tests.gpu_util import dev_scene, eye_view, rcam, say
 
 pytestmark = pytest.mark.gpu
@@ -180,6 +180,23 @@ def test_forward_loss_gradient_argument_checks():
     with pytest.raises(rtgs.RtgsError) as e:
         rtgs.render_fwd_batched(R.handle, [out], ws, cap, flags=0)
     assert e.value.code == rtgs.RTGS_ERR_INVALID_ARG
-    with pytest.raises(ValueError):                   # no loss on a reused-list forward
-        ref = R.forward(scene, view, rcam(cam))
-        R.forward(scene, view, rcam(cam), reuse_lists_of=ref, l1=(tc, td, None))
+
+
+def test_forward_loss_gradient_on_reused_lists():
+    """A forward on the tile lists of an earlier one (another pose) also
+    writes the loss gradient of its own image."""
+    say("test_forward_loss_gradient_on_reused_lists")
+    spec = synth.CONFIGS["c0"]
+    cam = synth.make_camera(spec.width, spec.height)
+    scene = dev_scene(synth.make_scene(spec, cam))
+    R = rtgs.Renderer(0)
+    ref = R.forward(scene, torch.from_numpy(eye_view()).cuda(), rcam(cam))
+    xi = torch.tensor(synth.pose_offset(3, 0.01, 0.5), dtype=torch.float32, device="cuda")
+    view = pose.apply_left(xi, torch.from_numpy(eye_view()).cuda()).contiguous()
+    plain = R.forward(scene, view, rcam(cam), reuse_lists_of=ref)
+    tc, td = _targets(cam.height, cam.width, 7, plain.color, plain.depth)
+    st = R.forward(scene, view, rcam(cam), reuse_lists_of=ref, l1=(tc, td, None))
+    torch.cuda.synchronize()
+    for k in ("color", "depth", "final_T", "last_idx"):
+        assert torch.equal(getattr(st, k), getattr(plain, k)), k
+    _check_session(st.color, st.depth, tc, td, st.dL_dcolor, st.dL_ddepth, None, None)
