@@ -617,8 +617,17 @@ __device__ __forceinline__ int pow2_at_least(int n, int lo) {
   return p;
 }
 
+// LDS position of key e of a sort buffer: one spare key after every eight, so
+// that the threads' runs of K = 4 keys (32 bytes apart) fall on different
+// banks instead of the same few (at most 2-way conflicts for 64-bit accesses).
+__device__ __forceinline__ int sp(int e) { return e + (e >> 3); }
+
+// Keys a sort buffer of n keys holds with the spare ones.
+constexpr int sort_buf_keys(int n) { return n + n / 8; }
+
 // KEYS_OUT: write the sorted keys back to keys_out instead of their ids.
-template <int NT, int K, bool KEYS_OUT = false>
+// PAD_IN: `keys` is a sort buffer in LDS (positions by sp), else plain memory.
+template <int NT, int K, bool KEYS_OUT = false, bool PAD_IN = false>
 __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, int n,
                                 unsigned long long* buf0, unsigned long long* buf1,
                                 unsigned long long* keys_out = nullptr) {
@@ -628,10 +637,13 @@ __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, i
   if (act) {
     unsigned long long k[K];
 #pragma unroll
-    for (int s = 0; s < K; ++s) k[s] = K * t + s < n ? keys[K * t + s] : kKeyPad;
+    for (int s = 0; s < K; ++s) {
+      const int e = K * t + s;
+      k[s] = e < n ? keys[PAD_IN ? sp(e) : e] : kKeyPad;
+    }
     sort_network(k);
 #pragma unroll
-    for (int s = 0; s < K; ++s) buf0[K * t + s] = k[s];
+    for (int s = 0; s < K; ++s) buf0[sp(K * t + s)] = k[s];
   }
   __syncthreads();
   unsigned long long* src = buf0;
@@ -641,27 +653,27 @@ __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, i
       const int pos = K * t;
       const int base = pos & ~(2 * L - 1);
       const int r = pos - base;
-      const unsigned long long* A = src + base;
-      const unsigned long long* Bv = src + base + L;
+      const int a0 = base, b0 = base + L;     // the two runs being merged
       // number of A keys among the first r outputs (ties: A first)
       int lo = r > L ? r - L : 0, hi = r < L ? r : L;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (A[mid] <= Bv[r - 1 - mid]) lo = mid + 1;
+        if (src[sp(a0 + mid)] <= src[sp(b0 + r - 1 - mid)]) lo = mid + 1;
         else hi = mid;
       }
       int i = lo, j = r - lo;
-      unsigned long long x = i < L ? A[i] : kKeyPad, y = j < L ? Bv[j] : kKeyPad;
+      unsigned long long x = i < L ? src[sp(a0 + i)] : kKeyPad;
+      unsigned long long y = j < L ? src[sp(b0 + j)] : kKeyPad;
 #pragma unroll
       for (int s = 0; s < K; ++s) {
         const bool take_a = j >= L || (i < L && x <= y);
-        dst[pos + s] = take_a ? x : y;
+        dst[sp(pos + s)] = take_a ? x : y;
         if (take_a) {
           ++i;
-          x = i < L ? A[i] : kKeyPad;
+          x = i < L ? src[sp(a0 + i)] : kKeyPad;
         } else {
           ++j;
-          y = j < L ? Bv[j] : kKeyPad;
+          y = j < L ? src[sp(b0 + j)] : kKeyPad;
         }
       }
     }
@@ -672,9 +684,9 @@ __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, i
   }
   for (int i = t; i < n; i += NT) {
     if (KEYS_OUT)
-      keys_out[i] = src[i];
+      keys_out[i] = src[sp(i)];
     else
-      ids[i] = (uint32_t)src[i];
+      ids[i] = (uint32_t)src[sp(i)];
   }
 }
 
@@ -709,6 +721,7 @@ __device__ void merge_runs_to_ids(const unsigned long long* A, int na,
 // more chunks copy run by run.
 constexpr int kGatherChunks = 1020;    // s_at and s_src fit in one sort buffer
 
+template <bool PAD>
 __device__ void gather_tile(const WsPtrs& W, const SessionDev& S, int lt, int n,
                             unsigned long long* dst, uint32_t* s_part, uint32_t* s_at,
                             uint32_t* s_src) {
@@ -745,7 +758,7 @@ __device__ void gather_tile(const WsPtrs& W, const SessionDev& S, int lt, int n,
         s_src[c] = src;
       }
     } else {
-      for (uint32_t j = 0; j < cnt; ++j) dst[at + j] = W.keys[src + j];
+      for (uint32_t j = 0; j < cnt; ++j) dst[PAD ? sp(at + j) : at + j] = W.keys[src + j];
     }
     carry += tot;
     __syncthreads();                        // s_part is reused
@@ -775,7 +788,7 @@ __device__ void gather_tile(const WsPtrs& W, const SessionDev& S, int lt, int n,
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (j < qn) dst[q0 + j] = k[j];
+      if (j < qn) dst[PAD ? sp(q0 + j) : q0 + j] = k[j];
   }
 }
 
@@ -785,7 +798,8 @@ __device__ void gather_tile(const WsPtrs& W, const SessionDev& S, int lt, int n,
 // and queued for k_sort_big_tiles.
 template <bool ONE>
 __global__ __launch_bounds__(kBlock) void k_sort_tiles(Batch B, WsPtrs W) {
-  __shared__ unsigned long long b0[kSortPerThread * kBlock], b1[kSortPerThread * kBlock];
+  __shared__ unsigned long long b0[sort_buf_keys(kSortPerThread * kBlock)];
+  __shared__ unsigned long long b1[sort_buf_keys(kSortPerThread * kBlock)];
   __shared__ uint32_t s_part[kBlock / 64];
   // the gather's run table lives in b0, which the merge sort fills only after
   // it has read the gathered keys from b1
@@ -802,16 +816,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_tiles(Batch B, WsPtrs W) {
                                          [](const SessionDev& x) { return x.tile_base; });
   const SessionDev& S = batch_session<ONE>(B, s);
   if (n > kSortPerThread * kBlock) {
-    gather_tile(W, S, t - S.tile_base, n, W.keys_tm + st, s_part, s_at, s_src);
+    gather_tile<false>(W, S, t - S.tile_base, n, W.keys_tm + st, s_part, s_at, s_src);
     if (threadIdx.x == 0) {
       const unsigned long long q = atomicAdd((unsigned long long*)&W.counters[2], 1ull);
       W.big_tiles[q] = (uint32_t)t;
     }
     return;
   }
-  gather_tile(W, S, t - S.tile_base, n, b1, s_part, s_at, s_src);
+  gather_tile<true>(W, S, t - S.tile_base, n, b1, s_part, s_at, s_src);
   __syncthreads();
-  merge_sort_tile<kBlock, kSortPerThread>(b1, W.ids + st, n, b0, b1);
+  merge_sort_tile<kBlock, kSortPerThread, false, true>(b1, W.ids + st, n, b0, b1);
 }
 
 // Queued long lists (gathered to the tile-major buffer): up to 4096 keys by
@@ -822,7 +836,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_tiles(Batch B, WsPtrs W) {
 constexpr int kBigThreads = 1024;
 constexpr int kBigKeys = kSortPerThread * kBigThreads;
 __global__ __launch_bounds__(kBigThreads) void k_sort_big_tiles(WsPtrs W) {
-  __shared__ unsigned long long b0[kBigKeys], b1[kBigKeys];
+  __shared__ unsigned long long b0[sort_buf_keys(kBigKeys)], b1[sort_buf_keys(kBigKeys)];
   const long long count = W.counters[2];
   for (long long q = blockIdx.x; q < count; q += gridDim.x) {
     const int t = (int)W.big_tiles[q];
