@@ -176,28 +176,42 @@ __global__ __launch_bounds__(kGaussPerBlock) void k_preprocess(Batch B, WsPtrs W
 constexpr int kBinThreads = 1024;
 static_assert(kChunk % kBinThreads == 0, "whole rounds per chunk");
 
-// The chunk's tile rectangles in LDS (one coalesced load per Gaussian), so the
-// pair walk below never waits on a dependent global load.  Visible after the
-// barrier in chunk_offsets.
-__device__ __forceinline__ void stage_rects(const SessionDev& S, const WsPtrs& W, int c,
-                                            int4* s_rect) {
-  for (int i = threadIdx.x; i < kChunk; i += kBinThreads) {
-    const int li = c * kChunk + i;
-    s_rect[i] = li < S.n ? W.rect[S.gauss_base + li] : make_int4(0, 0, -1, -1);
+// The tile rectangles and pair counts of this thread's Gaussians of chunk c
+// (local index i = j * kBinThreads + thread for round j), loaded together at
+// the start of a binning pass so that their latencies overlap.
+constexpr int kChunkRounds = kChunk / kBinThreads;
+struct ChunkIn {
+  int4 rect[kChunkRounds];
+  uint32_t cnt[kChunkRounds];
+};
+
+__device__ __forceinline__ ChunkIn load_chunk(const SessionDev& S, const WsPtrs& W, int c) {
+  ChunkIn in;
+#pragma unroll
+  for (int j = 0; j < kChunkRounds; ++j) {
+    const int li = c * kChunk + j * kBinThreads + (int)threadIdx.x;
+    in.rect[j] = li < S.n ? W.rect[S.gauss_base + li] : make_int4(0, 0, -1, -1);
+    in.cnt[j] = li < S.n ? W.cnt[S.gauss_base + li] : 0u;
   }
+  return in;
+}
+
+// The chunk's tile rectangles in LDS, so the pair walk below never waits on
+// a dependent global load.  Visible after the barrier in chunk_offsets.
+__device__ __forceinline__ void stage_rects(const ChunkIn& in, int4* s_rect) {
+#pragma unroll
+  for (int j = 0; j < kChunkRounds; ++j) s_rect[j * kBinThreads + threadIdx.x] = in.rect[j];
 }
 
 // In-chunk exclusive offsets of the Gaussians' tile counts, in local index
 // order, into s_off[0..kChunk]; s_off[kChunk] = the chunk's pair total, which
-// is returned.  Local index i = j * kBinThreads + thread for round j.
-__device__ uint32_t chunk_offsets(const SessionDev& S, const WsPtrs& W, int c, uint32_t* s_off,
-                                  uint32_t* s_wave) {
+// is returned.
+__device__ uint32_t chunk_offsets(const ChunkIn& in, uint32_t* s_off, uint32_t* s_wave) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t carry = 0;
-  for (int j = 0; j < kChunk / kBinThreads; ++j) {
+  for (int j = 0; j < kChunkRounds; ++j) {
     const int i = j * kBinThreads + (int)threadIdx.x;
-    const int li = c * kChunk + i;
-    const uint32_t n = li < S.n ? W.cnt[S.gauss_base + li] : 0u;
+    const uint32_t n = in.cnt[j];
     uint32_t x = n;
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(x, off, 64);
@@ -274,9 +288,10 @@ __global__ __launch_bounds__(kBinThreads) void k_chunk_hist(Batch B, WsPtrs W) {
   const SessionDev& S = batch_session<ONE>(B, s);
   const int c = (int)blockIdx.x - S.chunk_base;
   const int ts = S.tiles_x * S.tiles_y;
+  const ChunkIn in = load_chunk(S, W, c);
   for (int t = threadIdx.x; t < ts; t += kBinThreads) s_hist[t] = 0u;
-  stage_rects(S, W, c, s_rect);
-  const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
+  stage_rects(in, s_rect);
+  const uint32_t total = chunk_offsets(in, s_off, s_wave);
   // pairs are dealt evenly over the threads, whatever the Gaussians' sizes
   chunk_pairs(S, s_rect, c, s_off, total, [&](int, int tile) { atomicAdd(&s_hist[tile], 1u); });
   __syncthreads();
@@ -482,18 +497,28 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
   uint32_t* s_cur = s_dyn;
   uint16_t* s_loc = reinterpret_cast<uint16_t*>(s_dyn + ts);
   uint32_t* h = W.hist + S.hist_base + (int64_t)c * ts;
+  // every global load of the prologue issued together: the Gaussians' inputs,
+  // their key depths and this thread's run of the chunk's tile counts
+  const ChunkIn in = load_chunk(S, W, c);
+  uint32_t zb[kChunkRounds];
+#pragma unroll
+  for (int j = 0; j < kChunkRounds; ++j) {
+    const int li = c * kChunk + j * kBinThreads + (int)threadIdx.x;
+    zb[j] = li < S.n ? W.zkey[S.gauss_base + li] : 0u;
+  }
+  constexpr int kRunMax = (kMaxTilesPerSession + kBinThreads - 1) / kBinThreads;
+  const int per = (ts + kBinThreads - 1) / kBinThreads;
+  const int beg = min((int)threadIdx.x * per, ts), end = min(beg + per, ts);
+  uint32_t hv[kRunMax];
+#pragma unroll
+  for (int k = 0; k < kRunMax; ++k) hv[k] = beg + k < end ? h[beg + k] : 0u;
   // exclusive scan of the chunk's tile counts: each thread a contiguous run of
   // tiles, the run sums scanned across the waves
   {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int per = (ts + kBinThreads - 1) / kBinThreads;
-    const int beg = min((int)threadIdx.x * per, ts), end = min(beg + per, ts);
     uint32_t sum = 0;
-    for (int t = beg; t < end; ++t) {
-      const uint32_t v = h[t];
-      s_cur[t] = v;
-      sum += v;
-    }
+#pragma unroll
+    for (int k = 0; k < kRunMax; ++k) sum += hv[k];
     uint32_t x = sum;
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(x, off, 64);
@@ -503,20 +528,20 @@ __global__ __launch_bounds__(kBinThreads) void k_emit(Batch B, WsPtrs W) {
     __syncthreads();
     uint32_t run = x - sum;
     for (int q = 0; q < wave; ++q) run += s_wave[q];
-    for (int t = beg; t < end; ++t) {
-      const uint32_t v = s_cur[t];
-      s_cur[t] = run;
-      h[t] = run;
-      run += v;
+#pragma unroll
+    for (int k = 0; k < kRunMax; ++k) {
+      if (beg + k < end) {
+        s_cur[beg + k] = run;
+        h[beg + k] = run;
+      }
+      run += hv[k];
     }
     __syncthreads();                        // s_wave is reused below
   }
-  stage_rects(S, W, c, s_rect);
-  for (int i = threadIdx.x; i < kChunk; i += kBinThreads) {
-    const int li = c * kChunk + i;
-    s_zb[i] = li < S.n ? W.zkey[S.gauss_base + li] : 0u;
-  }
-  const uint32_t total = chunk_offsets(S, W, c, s_off, s_wave);
+  stage_rects(in, s_rect);
+#pragma unroll
+  for (int j = 0; j < kChunkRounds; ++j) s_zb[j * kBinThreads + threadIdx.x] = zb[j];
+  const uint32_t total = chunk_offsets(in, s_off, s_wave);
   const uint32_t base = W.chunk_off[blockIdx.x];
   for (int j = 0; j < kChunk / kBinThreads; ++j) {
     const int i = j * kBinThreads + (int)threadIdx.x;
