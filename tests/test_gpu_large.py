@@ -89,3 +89,43 @@ def test_full_size_sampled_parity(name):
         e = grad_err(gm[name_g].cpu().numpy(), getattr(rg, name_g).numpy())
         say(f"  {name_g} (map only): {e:.2e}")
         assert e < GRAD_TOL, name_g
+
+
+def test_full_size_mapping_step_fused_equals_unfused():
+    """The mapping iteration the benchmark times (1200x680, 300,000
+    Gaussians), fused (the forward writes the loss gradient, the backward
+    applies Adam) against forward, loss pass, backward and adam_step: the
+    loss gradients over the whole frame, then the parameters and moments
+    after two iterations, bit for bit."""
+    from paper_2510_06644_amd import optim
+    say("test_full_size_mapping_step_fused_equals_unfused")
+    spec = synth.CONFIGS["c2"]
+    cam = synth.make_camera(spec.width, spec.height)
+    sc = synth.make_scene(spec, cam)
+    rc = rcam(cam)
+    view = torch.from_numpy(synth.identity_viewmat()).cuda()
+    r = rtgs.Renderer(0, check="every")
+    tgt = r.forward(dev_scene(synth.perturb_scene(sc, spec.seed + 500)), view, rc)
+    tc, td = tgt.color.clone(), tgt.depth.clone()
+    sep = [p.clone() for p in dev_scene(sc)]
+    fus = [p.clone() for p in dev_scene(sc)]
+    opt_s, opt_f = optim.MapAdam(sep, eps=1e-15), optim.MapAdam(fus, eps=1e-15)
+    for it in range(2):
+        st = r.forward(tuple(sep), view, rc)
+        gc = torch.empty_like(st.color)
+        gd = torch.empty_like(st.depth)
+        rtgs.loss_l1_grad(st.color, st.depth, tc, td, gc, gd)
+        gs = r.backward(tuple(sep), view, rc, st, gc, gd, pose=False)
+        opt_s.step(r.handle, [gs[k] for k in ("means", "log_scales", "quats", "opacity_logits",
+                                             "colors")])
+        sf = r.forward(tuple(fus), view, rc, l1=(tc, td, None))
+        torch.cuda.synchronize()
+        assert torch.equal(sf.dL_dcolor, gc) and torch.equal(sf.dL_ddepth, gd), it
+        r.backward(tuple(fus), view, rc, sf, sf.dL_dcolor, sf.dL_ddepth, pose=False,
+                   adam=opt_f)
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip(sep, fus)):
+            assert torch.equal(a, b), f"iteration {it}: parameter {k}"
+            assert torch.equal(opt_s.exp_avg[k], opt_f.exp_avg[k]), f"iteration {it}: m {k}"
+            assert torch.equal(opt_s.exp_avg_sq[k], opt_f.exp_avg_sq[k]), f"iteration {it}: v {k}"
+        say(f"  iteration {it}: bitwise equal")
