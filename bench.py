@@ -51,14 +51,24 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "mapping_1200x680_300k_counters.m
 CSRC = os.path.join(ROOT, "paper_2510_06644_amd", "csrc")
 
 
+def _code_only(src):
+    """Source text without comments and with whitespace runs collapsed: two
+    sources that differ only there compile to the same kernels."""
+    import re
+    src = re.sub(rb"/\*.*?\*/", b" ", src, flags=re.S)
+    src = re.sub(rb"//[^\n]*", b" ", src)
+    return b" ".join(src.split())
+
+
 def kernel_hash():
-    """Digest of every source the library's kernels are compiled from."""
+    """Digest of the code (comments aside) of every source the library's
+    kernels are compiled from."""
     import hashlib
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
         if f.endswith((".hip", ".h")):
             with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+                h.update(f.encode() + b"\0" + _code_only(fh.read()))
     return h.hexdigest()[:16]
 
 

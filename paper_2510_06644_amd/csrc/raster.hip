@@ -12,6 +12,8 @@
 // stop before T would fall below 1e-4; saves final T and the position of the
 // last blended pair (the per-pixel state the backward reuses instead of
 // re-running the forward, the role of the paper's R&B buffer, Sec. 5.2).
+// With a session's loss targets it also writes the gradient of the L1 loss
+// (Eq. 6) of every pixel it writes, so no loss pass reads the image back.
 //
 // Backward: walks the list from the block's largest saved position down,
 // recovering T before each blended fragment as T / (1 - alpha) (Eq. 5 read
