@@ -278,6 +278,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
     if (e + kBlock < end) nid = W.ids[e + kBlock];
     __syncthreads();
     const int cnt = min(kBlock, end - b0);
+    // the lane's last blended entry of this batch, as its LDS byte offset
+    // (16 k, the address the step reads anyway)
+    int last16 = -1;
     for (int q = 0; q < kBlock / 64; ++q) {
       unsigned long long m = wave_entries(s_m, 64 * q, cnt, c.wbit);
       // every lane evaluates each entry; the decisions are selects, not
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         C2 = __builtin_fmaf(w, col.z, C2);
         D = __builtin_fmaf(w, col.w, D);
         T = blend ? tn : (stop_here ? -T : T);
-        last = blend ? b0 + k : last;
+        last16 = blend ? (k << 4) : last16;
         if (STATS) nblend += blend ? 1 : 0;
         if (FRAG) {
           const unsigned long long bm = __ballot(blend);
@@ -320,6 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(Batch B, WsPtrs W) {
         }
       }
     }
+    last = last16 >= 0 ? b0 + (last16 >> 4) : last;
     __syncthreads();
   }
   if (FRAG && flane == 0) W.fcount[(int64_t)tile * 4 + fwave] = fcur;
