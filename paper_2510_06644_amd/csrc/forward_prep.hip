@@ -689,9 +689,12 @@ __device__ void merge_sort_tile(const unsigned long long* keys, uint32_t* ids, i
       int i = lo, j = r - lo;
       unsigned long long x = i < L ? src[sp(a0 + i)] : kKeyPad;
       unsigned long long y = j < L ? src[sp(b0 + j)] : kKeyPad;
+      // an exhausted run reads as all-ones keys, so one compare decides: past
+      // the end of B, x <= y holds; past the end of A, it holds only if y is
+      // padding too, and then either choice writes the same all-ones key
 #pragma unroll
       for (int s = 0; s < K; ++s) {
-        const bool take_a = j >= L || (i < L && x <= y);
+        const bool take_a = x <= y;
         dst[sp(pos + s)] = take_a ? x : y;
         if (take_a) {
           ++i;
