@@ -56,6 +56,17 @@ def test_full_size_sampled_parity(name):
     assert rel_err(col, ref.color.numpy(), keep) < IMG_TOL
     assert rel_err(st.depth.reshape(-1)[pix].cpu().numpy(), ref.depth.numpy(), keep) < IMG_TOL
     assert rel_err(st.final_T.reshape(-1)[pix].cpu().numpy(), ref.final_t.numpy(), keep) < IMG_TOL
+    # last blended Gaussian of each sampled pixel (lists here run over several
+    # staged batches): saved list position -> Gaussian id
+    last = st.last_idx.reshape(-1)[pix].cpu().numpy()
+    gid = np.where(last >= 0, dbg["ids"][np.maximum(last, 0)], -1)
+    assert np.array_equal(gid[keep], ref.last_id.numpy()[keep])
+    tiles_x = (cam.width + 15) // 16
+    tile = (pix // cam.width) // 16 * tiles_x + (pix % cam.width) // 16
+    depth_in_list = np.where(last >= 0, last - dbg["ranges"][tile, 0], -1)
+    longest = int(np.diff(dbg["ranges"], axis=1).max())
+    say(f"  longest tile list {longest}, last blended entry up to {int(depth_in_list.max())} "
+        f"into its tile's list")
     # backward with upstream gradients on the unflagged sampled pixels only
     gcs, gds, gas = synth.upstream_grads(len(pix), 1, spec.seed + 1)
     gcs = gcs.reshape(3, -1) * keep[None]
