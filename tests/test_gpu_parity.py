@@ -313,6 +313,36 @@ def test_long_tile_lists_take_each_sort_path(renderer, n, span, lo, hi):
     assert rel_err(st.color.cpu().numpy(), ref.color.numpy(), keep) < IMG_TOL
 
 
+@pytest.mark.parametrize("n,lo,hi", [(900, 700, 1024), (2500, 1025, 4096), (6000, 4097, 8192),
+                                     (9000, 8193, 10 ** 9)])
+def test_long_tile_lists_with_depth_ties_on_each_sort_path(renderer, n, lo, hi):
+    """As above, with every Gaussian at one of three exactly equal depths: the
+    lists are ordered by depth, then by Gaussian index (Step 2), on every sort
+    path, bit for bit."""
+    say(f"test_long_tile_lists_with_depth_ties n={n}")
+    cam = synth.Camera(32, 32, 25.6, 25.6, 16.0, 16.0)
+    rng = np.random.default_rng(9)
+    z = rng.choice(np.float32([1.5, 2.0, 2.5]), n)
+    u = rng.uniform(4, 12, n)
+    v = rng.uniform(4, 12, n)
+    means = np.stack([(u - 16) * z / 25.6, (v - 16) * z / 25.6, z], 1).astype(np.float32)
+    assert np.array_equal(means[:, 2], z)        # camera depth = z exactly (identity view)
+    sc = synth.Scene(means, np.full((n, 3), -5.5, np.float32),
+                     np.tile(np.float32([1, 0, 0, 0]), (n, 1)),
+                     np.full(n, -4.0, np.float32), rng.random((n, 3)).astype(np.float32))
+    st = renderer.forward(dev_scene(sc), torch.from_numpy(eye_view()).cuda(), rcam(cam))
+    dbg = st.stage()
+    stg = dbg["stage"]
+    assert len(np.unique(stg[:, 6])) == 3
+    ranges, ids = binning.tile_lists(stg[:, 0], stg[:, 1], stg[:, 7], stg[:, 8], stg[:, 6],
+                                     np.ones(n, bool), 32, 32)
+    longest = (ranges[:, 1] - ranges[:, 0]).max()
+    say(f"  longest list {longest}")
+    assert lo <= longest <= hi
+    assert np.array_equal(dbg["ranges"], ranges)
+    assert np.array_equal(dbg["ids"], ids)
+
+
 def test_chunk_with_more_pairs_than_the_emit_stages(renderer):
     """Chunks of 1024 Gaussians that each cover about 30 tiles of an 8 x 8
     tile frame hold about 30k pairs, more than the emit orders by tile in LDS
